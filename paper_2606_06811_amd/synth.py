@@ -1,0 +1,239 @@
+"""Seeded synthetic genome pairs shaped like the paper's cross-species workloads.
+
+The paper measures on real genome pairs (human/mouse, rat/mouse, primates, and
+mouse chr10 x rat chr20 in Sec. 8); none of them is available here, so these
+generators stand in for them.  This module only draws random sequences: it
+holds none of the alignment method's arithmetic and is shared, as the single
+source of inputs, by the tests, the benchmark and the oracle checks.
+
+Recipe (all sizes in bases):
+  * composition P(A) = P(T) = 0.295, P(C) = P(G) = 0.205 (GC 41 %);
+  * ``mutate(d)``: each base is substituted with probability d (a transition
+    with odds 2/3, each of the two transversions 1/6); after each base an indel
+    event happens with probability 0.02 (insertion or deletion with equal odds,
+    length Geometric(1/3) >= 1, mean 3, inserted bases i.i.d.);
+  * structural variants: segments reverse-complemented in place (inversions)
+    and segments cut out and pasted elsewhere (translocations);
+  * repeat families: a consensus of log-uniform length, copies diverged from it
+    and written over the background;
+  * soft-masked low-complexity runs: tandem copies of a 1-6 base motif in
+    lower case.
+
+Sequences are numpy uint8 arrays of ASCII letters (upper case, lower case for
+soft-masked bases).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+COMPOSITION = np.array([0.295, 0.205, 0.205, 0.295])
+LETTERS = np.frombuffer(b"ACGT", dtype=np.uint8)
+LOWER = np.frombuffer(b"acgt", dtype=np.uint8)
+
+# The spaced seed and the scoring used by every workload: the paper's 12-of-19
+# seed (Sec. 7) with one transition tolerated, a HOXD70-style integer matrix
+# (order A C G T N; N scores -100 against everything), gap open 400, extend 30
+# (a gap of length L costs 400 + 30 L), X-drop 910, HSP threshold 3000,
+# Y-drop 9400, gapped threshold 3000.
+SEED_PATTERN = "1110100110010101111"
+HOXD70 = [
+    [91, -114, -31, -123, -100],
+    [-114, 100, -125, -31, -100],
+    [-31, -125, 100, -114, -100],
+    [-123, -31, -114, 91, -100],
+    [-100, -100, -100, -100, -100],
+]
+SCORING = dict(sub=HOXD70, gap_open=400, gap_extend=30, xdrop=910,
+               hsp_thresh=3000, ydrop=9400, gapped_thresh=3000)
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def iid_codes(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n i.i.d. base codes 0..3 (A C G T) with the GC-41 % composition."""
+    return rng.choice(4, size=n, p=COMPOSITION).astype(np.uint8)
+
+
+def to_ascii(codes: np.ndarray, soft: np.ndarray | None = None) -> np.ndarray:
+    out = LETTERS[codes]
+    if soft is not None and soft.any():
+        out = np.where(soft, LOWER[codes], out)
+    return out
+
+
+def mutate(rng, codes, soft, d, indel=0.02):
+    """Substitutions at rate d (transition:transversion 2:1) plus indels."""
+    n = codes.shape[0]
+    codes = codes.copy()
+    sub = rng.random(n) < d
+    nsub = int(sub.sum())
+    # code ^ 2 is the transition partner, code ^ 1 and code ^ 3 the transversions
+    codes[sub] ^= rng.choice(np.array([2, 1, 3], dtype=np.uint8), size=nsub, p=[2 / 3, 1 / 6, 1 / 6])
+    ev = np.nonzero(rng.random(n) < indel)[0]
+    is_ins = rng.random(ev.shape[0]) < 0.5
+    lens = rng.geometric(1 / 3, size=ev.shape[0])
+    # deletions remove the L bases after the event position
+    diff = np.zeros(n + 1, dtype=np.int64)
+    dpos, dlen = ev[~is_ins], lens[~is_ins]
+    np.add.at(diff, np.minimum(dpos + 1, n), 1)
+    np.add.at(diff, np.minimum(dpos + 1 + dlen, n), -1)
+    keep = np.cumsum(diff[:n]) == 0
+    # insertions put L fresh bases after the event position
+    ins_len = np.zeros(n, dtype=np.int64)
+    ins_len[ev[is_ins]] = lens[is_ins]
+    out_len = keep.astype(np.int64) + ins_len
+    start = np.cumsum(out_len) - out_len
+    total = int(out_len.sum())
+    oc = np.empty(total, dtype=np.uint8)
+    os_ = np.zeros(total, dtype=bool)
+    oc[start[keep]] = codes[keep]
+    os_[start[keep]] = soft[keep]
+    has = np.nonzero(ins_len)[0]
+    if has.shape[0]:
+        cnt = ins_len[has]
+        first = start[has] + keep[has]
+        idx = np.repeat(first - np.cumsum(cnt) + cnt, cnt) + np.arange(int(cnt.sum()))
+        oc[idx] = iid_codes(rng, idx.shape[0])
+    return oc, os_
+
+
+def revcomp_codes(codes, soft):
+    return (3 - codes[::-1]).astype(np.uint8), soft[::-1].copy()
+
+
+def _disjoint_segments(rng, n, count, seg_len):
+    """count non-overlapping [s, s + seg_len) segments inside [0, n)."""
+    slots = n // seg_len
+    if count > slots:
+        raise ValueError("too many segments for the sequence length")
+    pick = np.sort(rng.choice(slots, size=count, replace=False))
+    jitter = rng.integers(0, seg_len // 4 + 1, size=count)
+    starts = pick * seg_len + np.minimum(jitter, seg_len - 1)
+    starts = np.minimum(starts, n - seg_len)
+    # keep them disjoint after the jitter
+    for x in range(1, count):
+        starts[x] = max(starts[x], starts[x - 1] + seg_len)
+    return [int(s) for s in starts if s + seg_len <= n]
+
+
+def structural_variants(rng, codes, soft, n_inv, n_trans, seg_len):
+    """Reverse-complement n_inv segments in place, then cut n_trans other
+    segments out and paste each at a random position."""
+    codes, soft = codes.copy(), soft.copy()
+    segs = _disjoint_segments(rng, codes.shape[0], n_inv + n_trans, seg_len)
+    order = rng.permutation(len(segs))
+    inv = [segs[i] for i in order[:n_inv]]
+    trans = sorted(segs[i] for i in order[n_inv:])
+    for s in inv:
+        c, m = revcomp_codes(codes[s:s + seg_len], soft[s:s + seg_len])
+        codes[s:s + seg_len], soft[s:s + seg_len] = c, m
+    pieces_c, pieces_s = [], []
+    keep = np.ones(codes.shape[0], dtype=bool)
+    for s in trans:
+        pieces_c.append(codes[s:s + seg_len].copy())
+        pieces_s.append(soft[s:s + seg_len].copy())
+        keep[s:s + seg_len] = False
+    codes, soft = codes[keep], soft[keep]
+    for c, m in zip(pieces_c, pieces_s):
+        p = int(rng.integers(0, codes.shape[0] + 1))
+        codes = np.concatenate([codes[:p], c, codes[p:]])
+        soft = np.concatenate([soft[:p], m, soft[p:]])
+    return codes, soft
+
+
+def add_repeats(rng, codes, soft, families, copies, len_lo, len_hi, div_lo, div_hi):
+    """Write diverged copies of repeat-family consensus sequences over the background."""
+    n = codes.shape[0]
+    for _ in range(families):
+        L = int(np.exp(rng.uniform(np.log(len_lo), np.log(len_hi))))
+        cons = iid_codes(rng, L)
+        for _ in range(copies):
+            c, m = mutate(rng, cons, np.zeros(L, dtype=bool), rng.uniform(div_lo, div_hi))
+            if rng.random() < 0.5:
+                c, m = revcomp_codes(c, m)
+            if c.shape[0] >= n:
+                continue
+            p = int(rng.integers(0, n - c.shape[0]))
+            codes[p:p + c.shape[0]] = c
+            soft[p:p + c.shape[0]] = m
+    return codes, soft
+
+
+def add_low_complexity(rng, codes, soft, fraction):
+    """Soft-masked tandem runs of a 1-6 base motif, 20-200 bases long, covering `fraction`."""
+    n = codes.shape[0]
+    target = int(fraction * n)
+    covered = 0
+    while covered < target:
+        period = int(rng.integers(1, 7))
+        L = int(rng.integers(20, 201))
+        motif = iid_codes(rng, period)
+        run = np.resize(motif, L)
+        p = int(rng.integers(0, max(1, n - L)))
+        codes[p:p + L] = run
+        soft[p:p + L] = True
+        covered += L
+    return codes, soft
+
+
+def pair_small(n=1_000_000, divergence=0.15, seed=1, n_inv=3, n_trans=3, seg_len=20_000):
+    """Target of n i.i.d. bases; the query is a copy with n_inv inverted and
+    n_trans translocated segments, then mutate(divergence).  With the defaults
+    this is the 1 Mbp, 15 %-divergence small pipeline workload."""
+    rng = rng_for(seed)
+    t = iid_codes(rng, n)
+    ts = np.zeros(n, dtype=bool)
+    seg_len = min(seg_len, max(1, n // max(1, 2 * (n_inv + n_trans))))
+    qc, qs = structural_variants(rng, t, ts, n_inv, n_trans, seg_len)
+    qc, qs = mutate(rng, qc, qs, divergence)
+    return to_ascii(t, ts), [to_ascii(qc, qs)]
+
+
+def pair_mid(n=50_000_000, divergence=0.25, seed=2, families=200, copies=50,
+             sv_per_mbp=3, seg_len=20_000, low_complexity=0.01):
+    """The mid-size pipeline workload: n-base target with repeat families
+    (300-6000 bp consensus, `copies` copies at 10-20 % divergence) and 1 %
+    soft-masked low-complexity runs; the query gets sv_per_mbp inversions and
+    sv_per_mbp translocations of seg_len per Mbp, then mutate(divergence)."""
+    rng = rng_for(seed)
+    t = iid_codes(rng, n)
+    ts = np.zeros(n, dtype=bool)
+    t, ts = add_repeats(rng, t, ts, families, copies, 300, 6000, 0.10, 0.20)
+    t, ts = add_low_complexity(rng, t, ts, low_complexity)
+    nsv = max(1, int(round(sv_per_mbp * n / 1e6)))
+    seg_len = min(seg_len, max(1, n // (4 * nsv)))
+    qc, qs = structural_variants(rng, t, ts, nsv, nsv, seg_len)
+    qc, qs = mutate(rng, qc, qs, divergence)
+    return to_ascii(t, ts), [to_ascii(qc, qs)]
+
+
+def pair_chunks(n=100_000_000, n_chunks=4096, seed=3, families=200, copies=50,
+                low_complexity=0.01, median=50_000, len_lo=10_000, len_hi=2_000_000,
+                sigma=1.0, div_lo=0.10, div_hi=0.35, chunk_ids=None):
+    """The batched workload: a repeat-bearing target and query chunks with
+    lognormal lengths (median `median`, clipped into [len_lo, len_hi] by
+    resampling), each a random target segment on a random strand, mutated at
+    U(div_lo, div_hi).  chunk_ids selects a subset (same draws per chunk)."""
+    rng = rng_for(seed)
+    t = iid_codes(rng, n)
+    ts = np.zeros(n, dtype=bool)
+    t, ts = add_repeats(rng, t, ts, families, copies, 300, 6000, 0.10, 0.20)
+    t, ts = add_low_complexity(rng, t, ts, low_complexity)
+    queries = []
+    for cid in range(n_chunks):
+        crng = rng_for(seed * 1_000_003 + cid)
+        while True:
+            L = int(np.exp(crng.normal(np.log(median), sigma)))
+            if len_lo <= L <= min(len_hi, n):
+                break
+        if chunk_ids is not None and cid not in chunk_ids:
+            continue
+        s = int(crng.integers(0, n - L + 1))
+        c, m = t[s:s + L], ts[s:s + L]
+        if crng.random() < 0.5:
+            c, m = revcomp_codes(c, m)
+        c, m = mutate(crng, c, m, crng.uniform(div_lo, div_hi))
+        queries.append(to_ascii(c, m))
+    return to_ascii(t, ts), queries
