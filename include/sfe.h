@@ -1,0 +1,207 @@
+/*
+ * sfe.h -- C ABI of the MI355X (gfx950) seed -> filter -> extend library.
+ *
+ * The library computes the data-parallel core of the seed-filter-extend
+ * pipeline of Sundram, "Dependencies and Dataflow in Seed-Filter-Extend
+ * Pipelines" (2026): spaced-seed hits of query windows against a target
+ * position table (Sec. 1, Sec. 7), the ungapped X-drop filter on every hit
+ * (Sec. 3, Sec. 8), and gapped Y-drop extension of the surviving candidate
+ * regions, each anchor extended as two halves (Sec. 8), committed with the
+ * semantics of the strict serial algorithm (Alg. 1) while the extensions run
+ * speculatively in batches (Alg. 3, Sec. 5).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Sequences are ASCII: A C G T (upper case), a c g t (soft-masked), N/n and
+ *   the IUPAC ambiguity letters R Y S W K M B D H V (scored as N).  Any other
+ *   byte is SFE_EINVAL.  Residue pointers may be host or device memory.
+ * - Coordinates are 0-based, half-open, uint32.  Strand 0 is the query as
+ *   given; strand 1 is its reverse complement and its coordinates are taken
+ *   in reverse-complement space (position p of the minus strand is base
+ *   length-1-p of the query, complemented).
+ * - Output buffers may be host or device memory; the library copies into
+ *   them with unified addressing.  Calls are ordered on the context's stream
+ *   and return only when their results are in the caller's buffers.
+ * - Capacity protocol: when an output capacity is too small, nothing is
+ *   written, *n_out receives the required count, and SFE_ECAPACITY returns.
+ * - Ownership: contexts and indexes belong to the library until destroyed;
+ *   inputs are borrowed for the duration of the call; outputs belong to the
+ *   caller.
+ * - Scores are int32.  A sequence longer than (2^30 - 1) / max|sub| bases,
+ *   or longer than 2^32 - 64 bases, is SFE_ERANGE.
+ * - No call throws; on failure the status is returned and sfe_last_error()
+ *   describes it.
+ */
+#ifndef SFE_H
+#define SFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sfe_status;
+#define SFE_OK 0
+#define SFE_EINVAL (-1)     /* malformed argument (pattern, letter, scoring, null pointer) */
+#define SFE_ENOMEM (-2)     /* device or host allocation failed */
+#define SFE_ECAPACITY (-3)  /* an output buffer is too small; *n_out holds the need */
+#define SFE_ERANGE (-4)     /* a sequence breaks the int32 score or uint32 coordinate range */
+#define SFE_EDEVICE (-5)    /* a HIP runtime call failed */
+#define SFE_EINTERNAL (-6)  /* an internal consistency check failed */
+
+typedef struct sfe_ctx sfe_ctx;
+typedef struct sfe_index sfe_index;
+
+/* A spaced seed (Sec. 7): pattern of '1' (care) and '0' (don't care), first
+ * and last characters '1', span <= 32, weight (number of '1') <= 14.
+ * transitions = 1 also accepts windows whose care positions differ in exactly
+ * one place by a transition (A<->G, C<->T).  A target position p is indexed
+ * iff p % step == 0. */
+typedef struct {
+    const char *pattern;
+    int32_t transitions;
+    int32_t step;
+} sfe_seed_spec;
+
+/* Integer scoring: sub[a][b] for target base a and query base b in the order
+ * A C G T N; a gap of length L costs gap_open + L * gap_extend.  |sub| < 2^15,
+ * 0 <= gap_open < 2^20, 0 < gap_extend < 2^15, 0 <= xdrop, ydrop < 2^29. */
+typedef struct {
+    int32_t sub[5][5];
+    int32_t gap_open, gap_extend;
+    int32_t xdrop;          /* ungapped extension stops once best - running > xdrop */
+    int32_t hsp_thresh;     /* an HSP passes the filter when its score >= hsp_thresh */
+    int32_t ydrop;          /* a DP cell is pruned when H < (best so far) - ydrop */
+    int32_t gapped_thresh;  /* an extension is committed when its score >= gapped_thresh */
+} sfe_scoring;
+
+typedef struct {
+    const char *residues;   /* host or device pointer to `length` ASCII bytes */
+    int64_t length;
+} sfe_seq;
+
+/* One seed hit: target window start t, query window start q (strand space). */
+typedef struct {
+    uint32_t t, q, query_id;
+    uint8_t strand, pad[3];
+} sfe_hit;                  /* 16 bytes */
+
+/* One ungapped segment: target [t0, t0+len), query [q0, q0+len). */
+typedef struct {
+    uint32_t t0, q0, len;
+    int32_t score;
+    uint32_t query_id;
+    uint8_t strand, pad[3];
+} sfe_hsp;                  /* 24 bytes */
+
+/* One gapped alignment.  ops[ops_offset .. ops_offset+ops_len) are
+ * run-length edit operations (len << 2 | op), op 0 = M (a column consuming
+ * one target and one query base), 1 = I (consumes query only), 2 = D
+ * (consumes target only), read from (t_start, q_start) to (t_end, q_end).
+ * cells = DP cells computed by the two halves; flags bit 0 = score reached
+ * gapped_thresh. */
+typedef struct {
+    uint32_t t_start, t_end, q_start, q_end;
+    int32_t score;
+    uint32_t query_id;
+    uint32_t anchor_t, anchor_q;
+    uint64_t ops_offset;
+    uint64_t cells;
+    uint32_t ops_len;
+    uint8_t strand, flags, pad[2];
+} sfe_aln;                  /* 56 bytes */
+
+#define SFE_ALN_PASSED 1u
+
+/* Schedules of the gapped extension; all give identical results. */
+#define SFE_SCHED_PLAIN 0       /* one wavefront per anchor-half, one launch per batch */
+#define SFE_SCHED_PERSISTENT 1  /* persistent work-stealing launch over a cost-ordered queue */
+
+typedef struct {
+    int32_t round_k;        /* speculative batch size K per (query, strand); <= 0 picks a default */
+    int32_t schedule;       /* SFE_SCHED_* */
+    int32_t strands;        /* bit 0 plus, bit 1 minus; 0 means both */
+    int32_t max_cells_per_lane; /* 0 = automatic; 4 or 16 forces the register band width */
+    int64_t arena_bytes;    /* traceback pointer arena per batch; 0 = default */
+} sfe_align_opts;
+
+typedef struct {
+    int64_t seed_hits;          /* hits evaluated by the X-drop filter */
+    int64_t hsps_raw;           /* hits whose X-drop score passed */
+    int64_t hsps;               /* unique passing HSPs */
+    int64_t rounds;             /* speculative batches (Alg. 3 rounds) */
+    int64_t extensions;         /* gapped extensions computed (both halves = one) */
+    int64_t committed;          /* alignments committed */
+    int64_t shadow;             /* extensions computed but not committed */
+    int64_t cells;              /* DP cells of all computed extensions */
+    int64_t overflow_reruns;    /* halves re-run with a wider band or a larger arena */
+    double ms_seed_xdrop, ms_hsp_set, ms_extend, ms_total;
+} sfe_stats;
+
+/* Context on `device` using `hip_stream` (a hipStream_t, or NULL for a
+ * stream of its own). */
+sfe_status sfe_ctx_create(int device, void *hip_stream, sfe_ctx **out);
+void sfe_ctx_destroy(sfe_ctx *ctx);
+
+/* Position table of the target (Sec. 5 phase 1, Sec. 7): the 2-bit packed
+ * target with N and soft-mask bit planes, and the list of indexed window
+ * starts grouped by seed key (valid windows only: no N or soft-masked base in
+ * the span), resident in device memory. */
+sfe_status sfe_build_index(sfe_ctx *ctx, const sfe_seq *target, const sfe_seed_spec *seed,
+                           sfe_index **out);
+void sfe_index_destroy(sfe_index *idx);
+
+/* All seed hits of the queries (Sec. 1, Sec. 7): (t, q) such that both
+ * windows are valid and the care positions match exactly or, with
+ * transitions, differ by one transition.  strands: bit 0 plus, bit 1 minus.
+ * Output in (query_id, strand, q, t) order; each hit once. */
+sfe_status sfe_seed_hits(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries, int32_t nq,
+                         int32_t strands, sfe_hit *out, int64_t cap, int64_t *n_hits);
+
+/* Ungapped X-drop extension of hits (Sec. 3, Sec. 8).  From the seed window
+ * the scan runs right of it and left of it along the diagonal, stopping once
+ * best - running > xdrop or at a sequence end; on ties the shorter extent is
+ * kept.  With flags = SFE_XDROP_RAW, out[x] is the segment of hits[x] whatever
+ * its score (exactly n records).  With flags = 0, out holds the passing
+ * segments (score >= hsp_thresh) with exact duplicates removed, in the order
+ * the serial algorithm walks them: query_id, score descending, strand, t0,
+ * q0, len ascending. */
+#define SFE_XDROP_RAW 1
+sfe_status sfe_ungapped_xdrop(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries, int32_t nq,
+                              const sfe_hit *hits, int64_t n, const sfe_scoring *sc, int32_t flags,
+                              sfe_hsp *out, int64_t cap, int64_t *n_hsps);
+
+/* Gapped Y-drop extension of each HSP (Sec. 8), without commit.  The anchor
+ * is the HSP's middle column (offset (len-1)/2), part of the alignment; the
+ * forward half extends from the next column on, the backward half from the
+ * previous column backwards.  Each half is an affine-gap DP over
+ * antidiagonals; a cell is live when H >= (best over earlier antidiagonals)
+ * - ydrop; the half stops after two antidiagonals with no live cell; its end
+ * is the first live cell (smallest antidiagonal, then smallest target offset)
+ * reaching its best.  out[x] is the alignment of hsps[x] (exactly n records);
+ * edit operations are written only for records with SFE_ALN_PASSED. */
+sfe_status sfe_gapped_ydrop(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries, int32_t nq,
+                            const sfe_hsp *hsps, int64_t n, const sfe_scoring *sc,
+                            sfe_aln *out, uint32_t *ops, int64_t ops_cap, int64_t *n_ops);
+
+/* The whole pipeline with the commit semantics of Alg. 1 (Sec. 4), run as
+ * Alg. 3 (Sec. 5): per (query, strand), HSPs are walked in the order of
+ * sfe_ungapped_xdrop; an HSP whose anchor column lies on an M column of an
+ * alignment already committed is skipped; batches of up to round_k unskipped
+ * HSPs are extended speculatively and committed in order, re-checking the
+ * anchor against every earlier commit.  The result does not depend on
+ * round_k or on the schedule.  Output order: query_id, strand, t_start,
+ * q_start, t_end, q_end, anchor_t, anchor_q.  stats may be NULL. */
+sfe_status sfe_align(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries, int32_t nq,
+                     const sfe_scoring *sc, const sfe_align_opts *opts,
+                     sfe_aln *out, int64_t cap, int64_t *n_alns,
+                     uint32_t *ops, int64_t ops_cap, int64_t *n_ops, sfe_stats *stats);
+
+const char *sfe_status_str(sfe_status s);
+const char *sfe_last_error(const sfe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFE_H */

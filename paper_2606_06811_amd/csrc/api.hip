@@ -1,0 +1,846 @@
+// api.hip -- the C ABI (include/sfe.h): contexts, the position table, and the
+// host side of the speculative batched pipeline (Alg. 3 of the paper: a
+// serial scan picks a batch, the GPU extends it, a serial commit keeps the
+// result equal to the strict serial Alg. 1).
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <functional>
+#include <tuple>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "sfe_kernels.h"
+
+using namespace sfe;
+
+namespace {
+
+struct SfeError {
+    sfe_status st;
+    std::string msg;
+};
+
+#define HIPCHK(x)                                                                                   \
+    do {                                                                                            \
+        hipError_t e_ = (x);                                                                        \
+        if (e_ != hipSuccess)                                                                       \
+            throw SfeError{SFE_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};          \
+    } while (0)
+
+void fail(sfe_status st, const std::string &m) { throw SfeError{st, m}; }
+
+struct DBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    ~DBuf() { if (p) (void)hipFree(p); }
+    void reset(size_t bytes) {
+        if (p) { HIPCHK(hipFree(p)); p = nullptr; n = 0; }
+        ensure(bytes);
+    }
+    void *ensure(size_t bytes) {
+        if (bytes <= n && p) return p;
+        if (p) { HIPCHK(hipFree(p)); p = nullptr; n = 0; }
+        size_t b = std::max<size_t>(bytes, 256);
+        if (hipMalloc(&p, b) != hipSuccess) { p = nullptr; fail(SFE_ENOMEM, "device allocation failed"); }
+        n = b;
+        return p;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct SeqSet {
+    DBuf bases, nbits, sbits;
+    int64_t total = 0;   // bases including padding
+    SeqSetView view() const { return SeqSetView{(const uint32_t *)bases.p, (const uint32_t *)nbits.p, (const uint32_t *)sbits.p}; }
+};
+
+}  // namespace
+
+struct sfe_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string last_error;
+    DBuf staging, cub_temp, tmp_a, tmp_b, tmp_c, tmp_d, tmp_e, counters;
+    DBuf units_d, chunks_d, qdesc_d;
+    DBuf hsp_raw, hsp_pass, hsp_sorted;
+    DBuf items_d, tasks_d, hres_d, ids_d, aln_d, runoff_d, runs_d, nruns_d, opsoff_d, ops_d, nops_d, ring_d;
+    DBuf arena_d, arena_head;
+    int64_t arena_bytes = 0;
+    SeqSet qplus, qminus;
+    std::vector<QueryDesc> qdesc;
+};
+
+struct sfe_index {
+    sfe_ctx *ctx = nullptr;
+    SeqSet target;
+    int64_t nt = 0;
+    SeedDesc sd{};
+    uint32_t K = 0;
+    DBuf offsets, pos;
+    int64_t n_valid = 0;
+    int32_t max_abs_sub_guard = 0;
+};
+
+namespace {
+
+bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) { (void)hipGetLastError(); return false; }
+    return a.type == hipMemoryTypeDevice;
+}
+
+// Copy n bytes to the caller's buffer (host or device).
+void copy_out(sfe_ctx *c, void *dst, const void *src_dev, size_t n) {
+    if (n == 0) return;
+    HIPCHK(hipMemcpyAsync(dst, src_dev, n, hipMemcpyDefault, c->stream));
+}
+void copy_in(sfe_ctx *c, void *dst_dev, const void *src, size_t n) {
+    if (n == 0) return;
+    HIPCHK(hipMemcpyAsync(dst_dev, src, n, hipMemcpyDefault, c->stream));
+}
+void sync(sfe_ctx *c) { HIPCHK(hipStreamSynchronize(c->stream)); }
+
+unsigned grid(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+int64_t padded(int64_t len) { return ((len + 63) / 64) * 64 + 64; }
+
+// Packs sequences into a set; seq i starts at starts[i].  rc = 1 packs the
+// reverse complements.
+void pack_set(sfe_ctx *c, const sfe_seq *seqs, int32_t n, int rc, SeqSet &set, std::vector<int64_t> &starts) {
+    starts.resize(n);
+    int64_t total = 0;
+    for (int32_t i = 0; i < n; i++) {
+        if (seqs[i].length < 0 || (seqs[i].length > 0 && !seqs[i].residues)) fail(SFE_EINVAL, "bad sequence");
+        if (seqs[i].length > (int64_t)0xffffffffLL - 64) fail(SFE_ERANGE, "sequence longer than 2^32 - 64");
+        starts[i] = total;
+        total += padded(seqs[i].length);
+    }
+    total += 64;
+    set.total = total;
+    set.bases.ensure((size_t)(total / 16 + 4) * 4);
+    set.nbits.ensure((size_t)(total / 32 + 4) * 4);
+    set.sbits.ensure((size_t)(total / 32 + 4) * 4);
+    HIPCHK(hipMemsetAsync(set.bases.p, 0, (size_t)(total / 16 + 4) * 4, c->stream));
+    HIPCHK(hipMemsetAsync(set.nbits.p, 0, (size_t)(total / 32 + 4) * 4, c->stream));
+    HIPCHK(hipMemsetAsync(set.sbits.p, 0, (size_t)(total / 32 + 4) * 4, c->stream));
+    int *bad = c->counters.ensure(64) ? (int *)c->counters.p : nullptr;
+    HIPCHK(hipMemsetAsync(bad, 0, 4, c->stream));
+    for (int32_t i = 0; i < n; i++) {
+        int64_t len = seqs[i].length;
+        if (len == 0) continue;
+        const uint8_t *src = (const uint8_t *)seqs[i].residues;
+        if (!is_device_ptr(src)) {
+            c->staging.ensure((size_t)len);
+            HIPCHK(hipMemcpyAsync(c->staging.p, src, (size_t)len, hipMemcpyHostToDevice, c->stream));
+            src = c->staging.as<uint8_t>();
+        }
+        k_pack<<<grid((len + 31) / 32, 256), 256, 0, c->stream>>>(src, len, starts[i], rc, set.bases.as<uint32_t>(),
+                                                                   set.nbits.as<uint32_t>(), set.sbits.as<uint32_t>(), bad);
+        HIPCHK(hipGetLastError());
+        if (src == c->staging.p) sync(c);   // staging is reused by the next sequence
+    }
+    int hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    if (hbad) fail(SFE_EINVAL, "sequence holds a byte outside ACGTN / IUPAC letters");
+}
+
+SeedDesc parse_seed(const sfe_seed_spec *s) {
+    if (!s || !s->pattern) fail(SFE_EINVAL, "null seed spec");
+    SeedDesc d{};
+    int span = (int)strlen(s->pattern);
+    if (span < 1 || span > 32) fail(SFE_EINVAL, "seed span must be 1..32");
+    if (s->pattern[0] != '1' || s->pattern[span - 1] != '1') fail(SFE_EINVAL, "seed must start and end with '1'");
+    int w = 0;
+    for (int i = 0; i < span; i++) {
+        char ch = s->pattern[i];
+        if (ch == '1') {
+            if (w >= 14) fail(SFE_EINVAL, "seed weight above 14");
+            d.care[w++] = i;
+        } else if (ch != '0') {
+            fail(SFE_EINVAL, "seed pattern holds a character other than 0/1");
+        }
+    }
+    if (s->step < 1) fail(SFE_EINVAL, "step must be >= 1");
+    if (s->transitions != 0 && s->transitions != 1) fail(SFE_EINVAL, "transitions must be 0 or 1");
+    d.span = span;
+    d.weight = w;
+    d.transitions = s->transitions;
+    d.step = s->step;
+    return d;
+}
+
+ScoreDesc check_scoring(const sfe_scoring *s) {
+    if (!s) fail(SFE_EINVAL, "null scoring");
+    ScoreDesc d;
+    for (int a = 0; a < 5; a++)
+        for (int b = 0; b < 5; b++) {
+            if (s->sub[a][b] <= -(1 << 15) || s->sub[a][b] >= (1 << 15)) fail(SFE_EINVAL, "|sub| must be < 2^15");
+            d.sub[a][b] = s->sub[a][b];
+        }
+    if (s->gap_open < 0 || s->gap_open >= (1 << 20)) fail(SFE_EINVAL, "gap_open out of range");
+    if (s->gap_extend <= 0 || s->gap_extend >= (1 << 15)) fail(SFE_EINVAL, "gap_extend out of range");
+    if (s->xdrop < 0 || s->xdrop >= (1 << 29)) fail(SFE_EINVAL, "xdrop out of range");
+    if (s->ydrop < 0 || s->ydrop >= (1 << 29)) fail(SFE_EINVAL, "ydrop out of range");
+    d.gap_open = s->gap_open;
+    d.gap_extend = s->gap_extend;
+    d.xdrop = s->xdrop;
+    d.hsp_thresh = s->hsp_thresh;
+    d.ydrop = s->ydrop;
+    d.gapped_thresh = s->gapped_thresh;
+    return d;
+}
+
+int max_abs_sub(const ScoreDesc &d) {
+    int m = 1;
+    for (int a = 0; a < 5; a++)
+        for (int b = 0; b < 5; b++) m = std::max(m, std::abs(d.sub[a][b]));
+    return m;
+}
+
+void check_range(const sfe_index *idx, const sfe_seq *q, int32_t nq, const ScoreDesc &d) {
+    int64_t m = max_abs_sub(d);
+    for (int32_t i = 0; i < nq; i++) {
+        int64_t L = std::min<int64_t>(q[i].length, idx->nt);
+        if (L * m >= (1LL << 30) - 1) fail(SFE_ERANGE, "alignment scores could leave the int32 range");
+    }
+}
+
+template <class T>
+void cub_exclusive_sum(sfe_ctx *c, const T *in, T *out, int64_t n) {
+    size_t bytes = 0;
+    HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, c->stream));
+    c->cub_temp.ensure(bytes);
+    HIPCHK(hipcub::DeviceScan::ExclusiveSum(c->cub_temp.p, bytes, in, out, (int)n, c->stream));
+}
+
+void cub_sort_pairs(sfe_ctx *c, const uint32_t *kin, uint32_t *kout, const uint32_t *vin, uint32_t *vout, int64_t n,
+                    int end_bit) {
+    size_t bytes = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, (int)n, 0, end_bit, c->stream));
+    c->cub_temp.ensure(bytes);
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(c->cub_temp.p, bytes, kin, kout, vin, vout, (int)n, 0, end_bit, c->stream));
+}
+
+// Uploads the queries (both strands) and describes the (query, strand) units
+// and 64-window chunks.
+struct QueryLayout {
+    std::vector<UnitDesc> units;
+    std::vector<Chunk> chunks;
+    std::vector<int64_t> starts;
+};
+
+void upload_queries(sfe_ctx *c, const sfe_seq *q, int32_t nq, int strands, int span, QueryLayout &L) {
+    if (nq < 0 || (nq > 0 && !q)) fail(SFE_EINVAL, "bad query list");
+    std::vector<int64_t> s2;
+    pack_set(c, q, nq, 0, c->qplus, L.starts);
+    pack_set(c, q, nq, 1, c->qminus, s2);
+    c->qdesc.resize(nq);
+    for (int32_t i = 0; i < nq; i++) c->qdesc[i] = QueryDesc{L.starts[i], q[i].length};
+    L.units.clear();
+    L.chunks.clear();
+    for (int32_t i = 0; i < nq; i++)
+        for (int s = 0; s < 2; s++) {
+            if (!((strands >> s) & 1)) continue;
+            UnitDesc u{L.starts[i], q[i].length, i, s};
+            int32_t ui = (int32_t)L.units.size();
+            L.units.push_back(u);
+            int64_t nwin = q[i].length >= span ? q[i].length - span + 1 : 0;
+            for (int64_t w = 0; w < nwin; w += 64) L.chunks.push_back(Chunk{ui, (int32_t)w});
+        }
+    c->units_d.ensure(std::max<size_t>(1, L.units.size()) * sizeof(UnitDesc));
+    c->chunks_d.ensure(std::max<size_t>(1, L.chunks.size()) * sizeof(Chunk));
+    c->qdesc_d.ensure(std::max<size_t>(1, c->qdesc.size()) * sizeof(QueryDesc));
+    copy_in(c, c->units_d.p, L.units.data(), L.units.size() * sizeof(UnitDesc));
+    copy_in(c, c->chunks_d.p, L.chunks.data(), L.chunks.size() * sizeof(Chunk));
+    copy_in(c, c->qdesc_d.p, c->qdesc.data(), c->qdesc.size() * sizeof(QueryDesc));
+}
+
+// Sorts n HSPs (device) into the walking order and removes exact duplicates.
+// Returns the unique count; result in c->hsp_sorted.  h must not live in the
+// tmp_a..tmp_d scratch buffers, which the sort uses.
+int64_t hsp_set(sfe_ctx *c, const sfe_hsp *h, int64_t n) {
+    c->hsp_sorted.ensure((size_t)std::max<int64_t>(n, 1) * sizeof(sfe_hsp));
+    if (n == 0) return 0;
+    uint32_t *perm = (uint32_t *)c->tmp_a.ensure((size_t)n * 4);
+    uint32_t *perm2 = (uint32_t *)c->tmp_b.ensure((size_t)n * 4);
+    uint32_t *key = (uint32_t *)c->tmp_c.ensure((size_t)n * 4);
+    uint32_t *key2 = (uint32_t *)c->tmp_d.ensure((size_t)n * 4);
+    k_iota<<<grid(n, 256), 256, 0, c->stream>>>(perm, n);
+    // least significant field first; radix sort is stable
+    for (int field = 0; field < 6; field++) {
+        k_hsp_key<<<grid(n, 256), 256, 0, c->stream>>>(h, perm, n, field, key);
+        cub_sort_pairs(c, key, key2, perm, perm2, n, field == 3 ? 1 : 32);
+        std::swap(perm, perm2);
+    }
+    uint32_t *flag = key, *dst = key2;
+    k_hsp_unique_flags<<<grid(n, 256), 256, 0, c->stream>>>(h, perm, n, flag);
+    cub_exclusive_sum(c, flag, dst, n);
+    k_hsp_compact<<<grid(n, 256), 256, 0, c->stream>>>(h, perm, flag, dst, n, c->hsp_sorted.as<sfe_hsp>());
+    uint32_t lastf = 0, lastd = 0;
+    HIPCHK(hipMemcpyAsync(&lastf, flag + n - 1, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&lastd, dst + n - 1, 4, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    return (int64_t)lastd + lastf;
+}
+
+__global__ void k_hsp_filter(const sfe_hsp *__restrict__ in, int64_t n, int32_t thresh, sfe_hsp *__restrict__ out,
+                             unsigned long long *__restrict__ cnt) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    sfe_hsp h = in[x];
+    if (h.score >= thresh) out[atomicAdd(cnt, 1ull)] = h;
+}
+
+// ---------------------------------------------------------------------------
+// One batch of gapped extensions (no commit): items -> alignments + ops.
+// ---------------------------------------------------------------------------
+struct BatchResult {
+    std::vector<sfe_aln> alns;        // per item; ops_offset indexes `ops`, ops_len set for passing items
+    std::vector<uint32_t> ops;
+    int64_t reruns = 0;
+};
+
+void ensure_arena(sfe_ctx *c, int64_t bytes) {
+    if (c->arena_bytes >= bytes && c->arena_d.p) return;
+    c->arena_d.ensure((size_t)bytes);
+    c->arena_bytes = bytes;
+    c->arena_head.ensure(8);
+}
+
+void set_arena(sfe_ctx *c, int64_t bytes) {
+    if (c->arena_bytes == bytes && c->arena_d.p) return;
+    c->arena_d.reset((size_t)bytes);
+    c->arena_bytes = bytes;
+    c->arena_head.ensure(8);
+}
+
+void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &items, const ScoreDesc &sc,
+               int cells_per_lane, BatchResult &out) {
+    const int64_t n = (int64_t)items.size();
+    out.alns.assign(n, sfe_aln{});
+    out.ops.clear();
+    if (n == 0) return;
+    ExtItem *items_d = (ExtItem *)c->items_d.ensure((size_t)n * sizeof(ExtItem));
+    HalfTask *tasks = (HalfTask *)c->tasks_d.ensure((size_t)2 * n * sizeof(HalfTask));
+    HalfResult *hres = (HalfResult *)c->hres_d.ensure((size_t)2 * n * sizeof(HalfResult));
+    copy_in(c, items_d, items.data(), (size_t)n * sizeof(ExtItem));
+    launch_make_tasks(items_d, n, c->units_d.as<UnitDesc>(), idx->nt, tasks, c->stream);
+    SeqSetView T = idx->target.view(), Qp = c->qplus.view(), Qm = c->qminus.view();
+    std::vector<HalfResult> hr(2 * n);
+    for (int attempt = 0;; attempt++) {
+        Arena ar{c->arena_d.as<uint8_t>(), (uint64_t)c->arena_bytes, c->arena_head.as<unsigned long long>()};
+        HIPCHK(hipMemsetAsync(c->arena_head.p, 0, 8, c->stream));
+        launch_ydrop(cells_per_lane, tasks, nullptr, 2 * n, T, Qp, Qm, sc, ar, hres, c->stream);
+        HIPCHK(hipGetLastError());
+        copy_out(c, hr.data(), hres, hr.size() * sizeof(HalfResult));
+        sync(c);
+        // halves whose band outgrew the window: wider window, then the workgroup kernel
+        std::vector<int32_t> wide;
+        bool arena_full = false;
+        for (int64_t h = 0; h < 2 * n; h++) {
+            if (hr[h].status == HALF_WIDTH_OVERFLOW) wide.push_back((int32_t)h);
+            if (hr[h].status == HALF_ARENA_OVERFLOW) arena_full = true;
+        }
+        int32_t cap = 4096;
+        int stage = cells_per_lane <= 4 ? 0 : 1;
+        while (!wide.empty() && !arena_full) {
+            out.reruns += (int64_t)wide.size();
+            int32_t *ids = (int32_t *)c->ids_d.ensure(wide.size() * 4);
+            copy_in(c, ids, wide.data(), wide.size() * 4);
+            if (stage == 0) {
+                launch_ydrop(16, tasks, ids, (int64_t)wide.size(), T, Qp, Qm, sc, ar, hres, c->stream);
+                stage = 1;
+            } else {
+                int32_t *ring = (int32_t *)c->ring_d.ensure((size_t)wide.size() * 7 * cap * 4);
+                launch_ydrop_ring(tasks, ids, (int64_t)wide.size(), T, Qp, Qm, sc, ar, ring, cap, hres, c->stream);
+                cap *= 4;
+            }
+            HIPCHK(hipGetLastError());
+            copy_out(c, hr.data(), hres, hr.size() * sizeof(HalfResult));
+            sync(c);
+            std::vector<int32_t> still;
+            for (int32_t h : wide) {
+                if (hr[h].status == HALF_WIDTH_OVERFLOW) still.push_back(h);
+                if (hr[h].status == HALF_ARENA_OVERFLOW) arena_full = true;
+            }
+            wide.swap(still);
+            if (cap > (1 << 26)) fail(SFE_EINTERNAL, "band width beyond 2^26 rows");
+        }
+        if (!arena_full) break;
+        if (attempt > 8) fail(SFE_ENOMEM, "traceback arena cannot hold one batch");
+        out.reruns += 2 * n;
+        ensure_arena(c, c->arena_bytes * 2);
+    }
+    Arena ar{c->arena_d.as<uint8_t>(), (uint64_t)c->arena_bytes, c->arena_head.as<unsigned long long>()};
+    sfe_aln *aln_d = (sfe_aln *)c->aln_d.ensure((size_t)n * sizeof(sfe_aln));
+    launch_assemble(items_d, n, c->units_d.as<UnitDesc>(), hres, T, Qp, Qm, sc, aln_d, c->stream);
+    copy_out(c, out.alns.data(), aln_d, (size_t)n * sizeof(sfe_aln));
+    sync(c);
+    // traceback of the passing items
+    std::vector<int32_t> pass, half_ids;
+    std::vector<uint64_t> run_off;
+    uint64_t roff = 0;
+    for (int64_t x = 0; x < n; x++) {
+        if (!(out.alns[x].flags & SFE_ALN_PASSED)) continue;
+        pass.push_back((int32_t)x);
+        for (int s = 0; s < 2; s++) {
+            const HalfResult &r = hr[2 * x + s];
+            half_ids.push_back((int32_t)(2 * x + s));
+            run_off.push_back(roff);
+            roff += (uint64_t)r.i_end + (uint64_t)r.j_end + 1;
+        }
+    }
+    if (pass.empty()) return;
+    const int64_t np = (int64_t)pass.size();
+    int32_t *hid_d = (int32_t *)c->ids_d.ensure(half_ids.size() * 4);
+    uint64_t *roff_d = (uint64_t *)c->runoff_d.ensure(run_off.size() * 8);
+    uint32_t *runs_d = (uint32_t *)c->runs_d.ensure((size_t)roff * 4);
+    uint32_t *nruns_d = (uint32_t *)c->nruns_d.ensure(half_ids.size() * 4);
+    copy_in(c, hid_d, half_ids.data(), half_ids.size() * 4);
+    copy_in(c, roff_d, run_off.data(), run_off.size() * 8);
+    launch_traceback(hres, hid_d, (int64_t)half_ids.size(), ar, roff_d, runs_d, nruns_d, c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<uint32_t> nruns(half_ids.size());
+    copy_out(c, nruns.data(), nruns_d, nruns.size() * 4);
+    sync(c);
+    for (uint32_t v : nruns)
+        if (v == 0xffffffffu) fail(SFE_EINTERNAL, "traceback records are inconsistent");
+    std::vector<uint64_t> ops_off(np);
+    uint64_t ooff = 0;
+    for (int64_t p = 0; p < np; p++) {
+        ops_off[p] = ooff;
+        ooff += (uint64_t)nruns[2 * p] + nruns[2 * p + 1] + 1;
+    }
+    uint64_t *ooff_d = (uint64_t *)c->opsoff_d.ensure((size_t)np * 8);
+    uint32_t *ops_d = (uint32_t *)c->ops_d.ensure((size_t)ooff * 4);
+    uint32_t *nops_d = (uint32_t *)c->nops_d.ensure((size_t)np * 4);
+    copy_in(c, ooff_d, ops_off.data(), (size_t)np * 8);
+    launch_ops_assemble(nullptr, np, roff_d, runs_d, nruns_d, ooff_d, ops_d, nops_d, c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<uint32_t> nops(np), ops_all(ooff);
+    copy_out(c, nops.data(), nops_d, (size_t)np * 4);
+    copy_out(c, ops_all.data(), ops_d, (size_t)ooff * 4);
+    sync(c);
+    for (int64_t p = 0; p < np; p++) {
+        sfe_aln &a = out.alns[pass[p]];
+        a.ops_offset = out.ops.size();
+        a.ops_len = nops[p];
+        out.ops.insert(out.ops.end(), ops_all.begin() + ops_off[p], ops_all.begin() + ops_off[p] + nops[p]);
+    }
+}
+
+// Committed M columns of one (query, strand) unit, by diagonal t - q.
+struct SegList {
+    std::unordered_map<int64_t, std::vector<std::pair<uint32_t, uint32_t>>> diag;
+    bool contains(uint32_t t, uint32_t q) const {
+        auto it = diag.find((int64_t)t - (int64_t)q);
+        if (it == diag.end()) return false;
+        for (auto &iv : it->second)
+            if (iv.first <= t && t < iv.second) return true;
+        return false;
+    }
+    void add(const sfe_aln &a, const uint32_t *ops) {
+        uint32_t t = a.t_start, q = a.q_start;
+        for (uint32_t x = 0; x < a.ops_len; x++) {
+            uint32_t len = ops[x] >> 2, op = ops[x] & 3u;
+            if (op == 0) {
+                diag[(int64_t)t - (int64_t)q].push_back({t, t + len});
+                t += len;
+                q += len;
+            } else if (op == 1) {
+                q += len;
+            } else {
+                t += len;
+            }
+        }
+    }
+};
+
+sfe_status guard(sfe_ctx *c, const std::function<void()> &f) {
+    try {
+        if (c) HIPCHK(hipSetDevice(c->device));
+        f();
+        return SFE_OK;
+    } catch (const SfeError &e) {
+        if (c) c->last_error = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        if (c) c->last_error = "host allocation failed";
+        return SFE_ENOMEM;
+    } catch (...) {
+        if (c) c->last_error = "internal error";
+        return SFE_EINTERNAL;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+sfe_status sfe_ctx_create(int device, void *hip_stream, sfe_ctx **out) {
+    if (!out) return SFE_EINVAL;
+    *out = nullptr;
+    sfe_ctx *c = new (std::nothrow) sfe_ctx;
+    if (!c) return SFE_ENOMEM;
+    c->device = device;
+    sfe_status st = guard(c, [&] {
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        HIPCHK(upload_encoding_table(c->stream));
+        c->counters.ensure(64);
+        ensure_arena(c, (int64_t)1 << 30);
+        sync(c);
+    });
+    if (st != SFE_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return SFE_OK;
+}
+
+void sfe_ctx_destroy(sfe_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+sfe_status sfe_build_index(sfe_ctx *c, const sfe_seq *target, const sfe_seed_spec *seed, sfe_index **out) {
+    if (!c || !target || !out) return SFE_EINVAL;
+    *out = nullptr;
+    sfe_index *ix = new (std::nothrow) sfe_index;
+    if (!ix) return SFE_ENOMEM;
+    sfe_status st = guard(c, [&] {
+        ix->ctx = c;
+        ix->sd = parse_seed(seed);
+        std::vector<int64_t> starts;
+        pack_set(c, target, 1, 0, ix->target, starts);
+        ix->nt = target->length;
+        const SeedDesc &sd = ix->sd;
+        ix->K = 1u << (2 * sd.weight);
+        int64_t nslots = ix->nt >= sd.span ? (ix->nt - sd.span) / sd.step + 1 : 0;
+        uint32_t *keys = (uint32_t *)c->tmp_a.ensure((size_t)std::max<int64_t>(nslots, 1) * 4);
+        uint32_t *pos0 = (uint32_t *)c->tmp_b.ensure((size_t)std::max<int64_t>(nslots, 1) * 4);
+        uint32_t *keys2 = (uint32_t *)c->tmp_c.ensure((size_t)std::max<int64_t>(nslots, 1) * 4);
+        ix->pos.ensure((size_t)std::max<int64_t>(nslots, 1) * 4);
+        ix->offsets.ensure(((size_t)ix->K + 1) * 4);
+        if (nslots > 0) {
+            k_index_keys<<<grid(nslots, 256), 256, 0, c->stream>>>(ix->target.view(), nslots, sd.step, sd, ix->K, keys, pos0);
+            cub_sort_pairs(c, keys, keys2, pos0, ix->pos.as<uint32_t>(), nslots, 2 * sd.weight + 1);
+        }
+        k_offsets<<<grid(nslots + 1, 256), 256, 0, c->stream>>>(keys2, nslots, ix->K, ix->offsets.as<uint32_t>());
+        HIPCHK(hipGetLastError());
+        uint32_t nv = 0;
+        HIPCHK(hipMemcpyAsync(&nv, ix->offsets.as<uint32_t>() + ix->K, 4, hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        ix->n_valid = nv;
+    });
+    if (st != SFE_OK) {
+        delete ix;
+        return st;
+    }
+    *out = ix;
+    return SFE_OK;
+}
+
+void sfe_index_destroy(sfe_index *ix) {
+    if (!ix) return;
+    if (ix->ctx) (void)hipSetDevice(ix->ctx->device);
+    delete ix;
+}
+
+sfe_status sfe_seed_hits(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, int32_t strands,
+                         sfe_hit *out, int64_t cap, int64_t *n_hits) {
+    if (!c || !ix || !n_hits) return SFE_EINVAL;
+    return guard(c, [&] {
+        if (strands == 0) strands = 3;
+        if (strands < 0 || strands > 3) fail(SFE_EINVAL, "strands must be 1, 2 or 3");
+        QueryLayout L;
+        upload_queries(c, queries, nq, strands, ix->sd.span, L);
+        int64_t nch = (int64_t)L.chunks.size();
+        *n_hits = 0;
+        if (nch == 0) return;
+        uint64_t *cnt = (uint64_t *)c->tmp_d.ensure((size_t)nch * 64 * 8);
+        uint64_t *off = (uint64_t *)c->tmp_e.ensure((size_t)nch * 64 * 8);
+        SeqSetView Qp = c->qplus.view(), Qm = c->qminus.view();
+        k_seed_count<<<(unsigned)nch, 64, 0, c->stream>>>(c->units_d.as<UnitDesc>(), c->chunks_d.as<Chunk>(), Qp, Qm,
+                                                         ix->offsets.as<uint32_t>(), ix->sd, cnt);
+        cub_exclusive_sum(c, cnt, off, nch * 64);
+        uint64_t lastc = 0, lasto = 0;
+        HIPCHK(hipMemcpyAsync(&lastc, cnt + nch * 64 - 1, 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(&lasto, off + nch * 64 - 1, 8, hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        int64_t total = (int64_t)(lastc + lasto);
+        *n_hits = total;
+        if (total > cap) fail(SFE_ECAPACITY, "hit buffer too small");
+        if (total == 0) return;
+        if (!out) fail(SFE_EINVAL, "null output");
+        sfe_hit *dst = out;
+        bool dev = is_device_ptr(out);
+        if (!dev) dst = (sfe_hit *)c->tmp_c.ensure((size_t)total * sizeof(sfe_hit));
+        k_seed_emit<<<(unsigned)nch, 64, 0, c->stream>>>(c->units_d.as<UnitDesc>(), c->chunks_d.as<Chunk>(), Qp, Qm,
+                                                        ix->offsets.as<uint32_t>(), ix->pos.as<uint32_t>(), ix->sd, off, dst);
+        HIPCHK(hipGetLastError());
+        if (!dev) copy_out(c, out, dst, (size_t)total * sizeof(sfe_hit));
+        sync(c);
+    });
+}
+
+sfe_status sfe_ungapped_xdrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, const sfe_hit *hits,
+                              int64_t n, const sfe_scoring *scp, int32_t flags, sfe_hsp *out, int64_t cap,
+                              int64_t *n_hsps) {
+    if (!c || !ix || !n_hsps || n < 0) return SFE_EINVAL;
+    return guard(c, [&] {
+        ScoreDesc sc = check_scoring(scp);
+        QueryLayout L;
+        upload_queries(c, queries, nq, 3, ix->sd.span, L);
+        check_range(ix, queries, nq, sc);
+        *n_hsps = 0;
+        if (n == 0) return;
+        if (!hits) fail(SFE_EINVAL, "null hits");
+        // validate the hits on the host copy
+        std::vector<sfe_hit> hh((size_t)n);
+        HIPCHK(hipMemcpyAsync(hh.data(), hits, (size_t)n * sizeof(sfe_hit), hipMemcpyDefault, c->stream));
+        sync(c);
+        for (const sfe_hit &h : hh) {
+            if (h.query_id >= (uint32_t)nq || h.strand > 1) fail(SFE_EINVAL, "hit names an unknown query or strand");
+            if ((int64_t)h.t + ix->sd.span > ix->nt || (int64_t)h.q + ix->sd.span > queries[h.query_id].length)
+                fail(SFE_EINVAL, "hit window outside its sequence");
+        }
+        sfe_hit *hd = (sfe_hit *)c->tmp_e.ensure((size_t)n * sizeof(sfe_hit));
+        copy_in(c, hd, hh.data(), (size_t)n * sizeof(sfe_hit));
+        sfe_hsp *raw = (sfe_hsp *)c->hsp_raw.ensure((size_t)n * sizeof(sfe_hsp));
+        k_xdrop_raw<<<grid(n, 256), 256, 0, c->stream>>>(hd, n, c->qdesc_d.as<QueryDesc>(), nq, ix->target.view(), 0,
+                                                        ix->nt, c->qplus.view(), c->qminus.view(), sc, ix->sd.span, raw);
+        HIPCHK(hipGetLastError());
+        if (flags & SFE_XDROP_RAW) {
+            *n_hsps = n;
+            if (n > cap) fail(SFE_ECAPACITY, "hsp buffer too small");
+            if (!out) fail(SFE_EINVAL, "null output");
+            copy_out(c, out, raw, (size_t)n * sizeof(sfe_hsp));
+            sync(c);
+            return;
+        }
+        sfe_hsp *pass = (sfe_hsp *)c->hsp_pass.ensure((size_t)n * sizeof(sfe_hsp));
+        unsigned long long *cnt = c->counters.as<unsigned long long>();
+        HIPCHK(hipMemsetAsync(cnt, 0, 8, c->stream));
+        k_hsp_filter<<<grid(n, 256), 256, 0, c->stream>>>(raw, n, sc.hsp_thresh, pass, cnt);
+        unsigned long long np = 0;
+        HIPCHK(hipMemcpyAsync(&np, cnt, 8, hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        int64_t nu = hsp_set(c, pass, (int64_t)np);
+        *n_hsps = nu;
+        if (nu > cap) fail(SFE_ECAPACITY, "hsp buffer too small");
+        if (nu && !out) fail(SFE_EINVAL, "null output");
+        copy_out(c, out, c->hsp_sorted.p, (size_t)nu * sizeof(sfe_hsp));
+        sync(c);
+    });
+}
+
+sfe_status sfe_gapped_ydrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, const sfe_hsp *hsps,
+                            int64_t n, const sfe_scoring *scp, sfe_aln *out, uint32_t *ops, int64_t ops_cap,
+                            int64_t *n_ops) {
+    if (!c || !ix || !n_ops || n < 0) return SFE_EINVAL;
+    return guard(c, [&] {
+        ScoreDesc sc = check_scoring(scp);
+        QueryLayout L;
+        upload_queries(c, queries, nq, 3, ix->sd.span, L);
+        check_range(ix, queries, nq, sc);
+        *n_ops = 0;
+        if (n == 0) return;
+        if (!hsps || !out) fail(SFE_EINVAL, "null hsps or output");
+        std::vector<sfe_hsp> hh((size_t)n);
+        HIPCHK(hipMemcpyAsync(hh.data(), hsps, (size_t)n * sizeof(sfe_hsp), hipMemcpyDefault, c->stream));
+        sync(c);
+        std::vector<ExtItem> items((size_t)n);
+        for (int64_t x = 0; x < n; x++) {
+            const sfe_hsp &h = hh[x];
+            if (h.query_id >= (uint32_t)nq || h.strand > 1 || h.len == 0) fail(SFE_EINVAL, "bad hsp");
+            if ((int64_t)h.t0 + h.len > ix->nt || (int64_t)h.q0 + h.len > queries[h.query_id].length)
+                fail(SFE_EINVAL, "hsp outside its sequences");
+            uint32_t off = (h.len - 1) / 2;
+            items[x] = ExtItem{h.t0 + off, h.q0 + off, (int32_t)(2 * h.query_id + h.strand), 0};
+        }
+        BatchResult br;
+        run_batch(c, ix, items, sc, 4, br);
+        int64_t need = (int64_t)br.ops.size();
+        *n_ops = need;
+        if (need > ops_cap) fail(SFE_ECAPACITY, "ops buffer too small");
+        if (need && !ops) fail(SFE_EINVAL, "null ops");
+        copy_out(c, out, br.alns.data(), (size_t)n * sizeof(sfe_aln));
+        copy_out(c, ops, br.ops.data(), (size_t)need * 4);
+        sync(c);
+    });
+}
+
+sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, const sfe_scoring *scp,
+                     const sfe_align_opts *opts, sfe_aln *out, int64_t cap, int64_t *n_alns, uint32_t *ops,
+                     int64_t ops_cap, int64_t *n_ops, sfe_stats *stats) {
+    if (!c || !ix || !n_alns || !n_ops) return SFE_EINVAL;
+    return guard(c, [&] {
+        const double t0 = now_ms();
+        ScoreDesc sc = check_scoring(scp);
+        sfe_align_opts o{};
+        if (opts) o = *opts;
+        int strands = o.strands ? o.strands : 3;
+        if (strands < 1 || strands > 3) fail(SFE_EINVAL, "strands must be 1, 2 or 3");
+        const int64_t K = o.round_k > 0 ? o.round_k : 256;
+        const int cpl = o.max_cells_per_lane == 16 ? 16 : 4;
+        if (o.arena_bytes > 0) set_arena(c, std::max<int64_t>(o.arena_bytes, 2 * ARENA_PAGE));
+        sfe_stats st{};
+        QueryLayout L;
+        upload_queries(c, queries, nq, strands, ix->sd.span, L);
+        check_range(ix, queries, nq, sc);
+        // --- seeds + X-drop (fused) --------------------------------------------------
+        const double t1 = now_ms();
+        int64_t nch = (int64_t)L.chunks.size();
+        int64_t nraw = 0;
+        if (nch > 0) {
+            uint64_t capraw = std::max<uint64_t>(c->hsp_raw.n / sizeof(sfe_hsp), 1u << 20);
+            for (;;) {
+                sfe_hsp *raw = (sfe_hsp *)c->hsp_raw.ensure(capraw * sizeof(sfe_hsp));
+                unsigned long long *cnt = c->counters.as<unsigned long long>();
+                HIPCHK(hipMemsetAsync(cnt, 0, 16, c->stream));
+                k_seed_xdrop<<<(unsigned)nch, 256, 0, c->stream>>>(c->units_d.as<UnitDesc>(), c->chunks_d.as<Chunk>(),
+                                                                  ix->target.view(), 0, ix->nt, c->qplus.view(),
+                                                                  c->qminus.view(), ix->offsets.as<uint32_t>(),
+                                                                  ix->pos.as<uint32_t>(), ix->sd, sc, raw, capraw, cnt);
+                HIPCHK(hipGetLastError());
+                unsigned long long hc[2];
+                HIPCHK(hipMemcpyAsync(hc, cnt, 16, hipMemcpyDeviceToHost, c->stream));
+                sync(c);
+                st.seed_hits = (int64_t)hc[0];
+                nraw = (int64_t)hc[1];
+                if ((uint64_t)nraw <= capraw) break;
+                capraw = (uint64_t)nraw + nraw / 8 + 1024;
+            }
+        }
+        st.hsps_raw = nraw;
+        const double t2 = now_ms();
+        int64_t nh = hsp_set(c, c->hsp_raw.as<sfe_hsp>(), nraw);
+        st.hsps = nh;
+        std::vector<sfe_hsp> hs((size_t)nh);
+        copy_out(c, hs.data(), c->hsp_sorted.p, (size_t)nh * sizeof(sfe_hsp));
+        sync(c);
+        const double t3 = now_ms();
+        // --- Alg. 3 rounds ------------------------------------------------------------
+        std::vector<int32_t> unit_of(2 * (size_t)std::max(nq, 1), -1);
+        for (size_t u = 0; u < L.units.size(); u++) unit_of[2 * L.units[u].query_id + L.units[u].strand] = (int32_t)u;
+        std::vector<std::vector<int64_t>> per_unit(L.units.size());
+        for (int64_t x = 0; x < nh; x++) per_unit[unit_of[2 * hs[x].query_id + hs[x].strand]].push_back(x);
+        std::vector<size_t> cursor(L.units.size(), 0);
+        std::vector<SegList> seg(L.units.size());
+        std::vector<sfe_aln> committed;
+        std::vector<uint32_t> cops;
+        std::vector<ExtItem> items;
+        std::vector<int32_t> item_unit;
+        BatchResult br;
+        for (;;) {
+            items.clear();
+            item_unit.clear();
+            for (size_t u = 0; u < L.units.size(); u++) {         // phase 1: serial scan per unit
+                int64_t taken = 0;
+                auto &lst = per_unit[u];
+                while (taken < K && cursor[u] < lst.size()) {
+                    const sfe_hsp &h = hs[lst[cursor[u]++]];
+                    uint32_t off = (h.len - 1) / 2;
+                    uint32_t ta = h.t0 + off, qa = h.q0 + off;
+                    if (seg[u].contains(ta, qa)) continue;
+                    items.push_back(ExtItem{ta, qa, (int32_t)u, 0});
+                    item_unit.push_back((int32_t)u);
+                    taken++;
+                }
+            }
+            if (items.empty()) break;
+            st.rounds++;
+            run_batch(c, ix, items, sc, cpl, br);                 // phase 2: speculative extensions
+            st.overflow_reruns += br.reruns;
+            st.extensions += (int64_t)items.size();
+            for (size_t x = 0; x < items.size(); x++) {          // phase 3: serial commit
+                const sfe_aln &a = br.alns[x];
+                st.cells += (int64_t)a.cells;
+                SegList &sl = seg[item_unit[x]];
+                if (sl.contains(a.anchor_t, a.anchor_q) || !(a.flags & SFE_ALN_PASSED)) continue;
+                sfe_aln k = a;
+                k.ops_offset = cops.size();
+                cops.insert(cops.end(), br.ops.begin() + a.ops_offset, br.ops.begin() + a.ops_offset + a.ops_len);
+                sl.add(k, cops.data() + k.ops_offset);
+                committed.push_back(k);
+            }
+        }
+        st.committed = (int64_t)committed.size();
+        st.shadow = st.extensions - st.committed;
+        const double t4 = now_ms();
+        // --- output in (query, strand, t_start, q_start, t_end, q_end, anchor) order ---
+        std::vector<int64_t> order(committed.size());
+        for (size_t x = 0; x < order.size(); x++) order[x] = (int64_t)x;
+        std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+            const sfe_aln &x = committed[a], &y = committed[b];
+            auto kx = std::make_tuple(x.query_id, x.strand, x.t_start, x.q_start, x.t_end, x.q_end, x.anchor_t, x.anchor_q);
+            auto ky = std::make_tuple(y.query_id, y.strand, y.t_start, y.q_start, y.t_end, y.q_end, y.anchor_t, y.anchor_q);
+            return kx < ky;
+        });
+        *n_alns = (int64_t)committed.size();
+        *n_ops = (int64_t)cops.size();
+        if (stats) {
+            st.ms_seed_xdrop = t2 - t1;
+            st.ms_hsp_set = t3 - t2;
+            st.ms_extend = t4 - t3;
+            st.ms_total = now_ms() - t0;
+            *stats = st;
+        }
+        if (*n_alns > cap || *n_ops > ops_cap) fail(SFE_ECAPACITY, "alignment or ops buffer too small");
+        if ((*n_alns && !out) || (*n_ops && !ops)) fail(SFE_EINVAL, "null output");
+        std::vector<sfe_aln> oa(committed.size());
+        std::vector<uint32_t> oo;
+        oo.reserve(cops.size());
+        for (size_t x = 0; x < order.size(); x++) {
+            sfe_aln a = committed[order[x]];
+            uint64_t src = a.ops_offset;
+            a.ops_offset = oo.size();
+            oo.insert(oo.end(), cops.begin() + src, cops.begin() + src + a.ops_len);
+            oa[x] = a;
+        }
+        copy_out(c, out, oa.data(), oa.size() * sizeof(sfe_aln));
+        copy_out(c, ops, oo.data(), oo.size() * 4);
+        sync(c);
+        if (stats) stats->ms_total = now_ms() - t0;
+    });
+}
+
+const char *sfe_status_str(sfe_status s) {
+    switch (s) {
+    case SFE_OK: return "ok";
+    case SFE_EINVAL: return "invalid argument";
+    case SFE_ENOMEM: return "out of memory";
+    case SFE_ECAPACITY: return "output capacity too small";
+    case SFE_ERANGE: return "value range exceeded";
+    case SFE_EDEVICE: return "device error";
+    case SFE_EINTERNAL: return "internal error";
+    default: return "unknown status";
+    }
+}
+
+const char *sfe_last_error(const sfe_ctx *c) { return c ? c->last_error.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,327 @@
+// k_seed.hip -- packing, position table, seed hits and the ungapped X-drop
+// filter on gfx950 (Sec. 1, Sec. 3, Sec. 7, Sec. 8 of the paper).
+#include "sfe_kernels.h"
+
+namespace sfe {
+
+__constant__ uint8_t c_enc[256];   // bits 0-1 code, bit 2 N, bit 3 soft, bit 7 invalid letter
+
+hipError_t upload_encoding_table(hipStream_t st) {
+    uint8_t t[256];
+    for (int c = 0; c < 256; c++) t[c] = 0x80;
+    const char *N = "NRYSWKMBDHV";
+    for (int s = 0; s < 2; s++) {
+        int off = s ? 'a' - 'A' : 0;
+        uint8_t soft = s ? 8 : 0;
+        t['A' + off] = 0 | soft;
+        t['C' + off] = 1 | soft;
+        t['G' + off] = 2 | soft;
+        t['T' + off] = 3 | soft;
+        for (const char *p = N; *p; p++) t[*p + off] = 4 | soft;
+    }
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_enc), t, 256, 0, hipMemcpyHostToDevice, st);
+}
+
+// One thread per 32 output bases.  rc = 1 writes the reverse complement.
+__global__ void k_pack(const uint8_t *__restrict__ txt, int64_t len, int64_t out_start, int rc,
+                       uint32_t *__restrict__ bases, uint32_t *__restrict__ nbits,
+                       uint32_t *__restrict__ sbits, int *__restrict__ bad) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p0 = g * 32;
+    if (p0 >= len) return;
+    uint32_t w0 = 0, w1 = 0, nb = 0, sb = 0;
+    int badl = 0;
+    for (int u = 0; u < 32; u++) {
+        int64_t p = p0 + u;
+        if (p >= len) break;
+        int64_t src = rc ? len - 1 - p : p;
+        uint8_t e = c_enc[txt[src]];
+        badl |= e >> 7;
+        uint32_t isn = (e >> 2) & 1u;
+        uint32_t code = isn ? 0u : (uint32_t)(e & 3u);
+        if (rc && !isn) code = 3u - code;
+        if (u < 16) w0 |= code << (2 * u); else w1 |= code << (2 * (u - 16));
+        nb |= isn << u;
+        sb |= (uint32_t)((e >> 3) & 1u) << u;
+    }
+    int64_t wp = (out_start + p0) >> 4;
+    bases[wp] = w0;
+    bases[wp + 1] = w1;
+    nbits[(out_start + p0) >> 5] = nb;
+    sbits[(out_start + p0) >> 5] = sb;
+    if (badl) atomicOr(bad, 1);
+}
+
+// keys[x] = seed key of target window x*step, or `sentinel` when invalid.
+__global__ void k_index_keys(SeqSetView T, int64_t nslots, int32_t step, SeedDesc sd, uint32_t sentinel,
+                             uint32_t *__restrict__ keys, uint32_t *__restrict__ pos) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nslots) return;
+    int64_t p = x * step;
+    uint32_t key;
+    bool ok = window_key(T, p, sd, &key);
+    keys[x] = ok ? key : sentinel;
+    pos[x] = (uint32_t)p;
+}
+
+// offsets[kk] = first index x with keys[x] >= kk, for kk in [0, K]; keys sorted.
+__global__ void k_offsets(const uint32_t *__restrict__ keys, int64_t n, uint32_t K, uint32_t *__restrict__ offsets) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > n) return;
+    int64_t prev = x > 0 ? (int64_t)keys[x - 1] : -1;
+    int64_t cur = x < n ? (int64_t)keys[x] : (int64_t)K + 1;
+    if (cur > (int64_t)K) cur = K;
+    for (int64_t kk = prev + 1; kk <= cur; kk++) offsets[kk] = (uint32_t)x;
+}
+
+// ---------------------------------------------------------------------------
+// Query windows: chunks of 64 consecutive windows of one (query, strand) unit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int seed_buckets(const SeqSetView &Q, int64_t p, const SeedDesc &sd,
+                                            const uint32_t *__restrict__ offsets, uint32_t *bstart,
+                                            uint32_t *bcount) {
+    uint32_t key;
+    if (!window_key(Q, p, sd, &key)) return 0;
+    int nb = 0;
+    int nvar = sd.transitions ? sd.weight : 0;
+    for (int v = -1; v < nvar; v++) {
+        uint32_t kk = key;
+        if (v >= 0) kk ^= 2u << (2 * (sd.weight - 1 - v));
+        uint32_t s = offsets[kk], e = offsets[kk + 1];
+        bstart[nb] = s;
+        bcount[nb] = e - s;
+        nb++;
+    }
+    return nb;
+}
+
+__global__ void __launch_bounds__(64) k_seed_count(const UnitDesc *__restrict__ units, const Chunk *__restrict__ chunks,
+                                                   SeqSetView Qp, SeqSetView Qm, const uint32_t *__restrict__ offsets,
+                                                   SeedDesc sd, uint64_t *__restrict__ counts) {
+    Chunk c = chunks[blockIdx.x];
+    UnitDesc u = units[c.unit];
+    int64_t q = (int64_t)c.w0 + threadIdx.x;
+    uint64_t n = 0;
+    if (q + sd.span <= u.len) {
+        uint32_t bs[17], bc[17];
+        int nb = seed_buckets(u.strand ? Qm : Qp, u.seq_start + q, sd, offsets, bs, bc);
+        for (int b = 0; b < nb; b++) n += bc[b];
+    }
+    counts[(int64_t)blockIdx.x * 64 + threadIdx.x] = n;
+}
+
+// Writes the hits of each window at its offset, merged into t order.
+__global__ void __launch_bounds__(64) k_seed_emit(const UnitDesc *__restrict__ units, const Chunk *__restrict__ chunks,
+                                                  SeqSetView Qp, SeqSetView Qm, const uint32_t *__restrict__ offsets,
+                                                  const uint32_t *__restrict__ tpos, SeedDesc sd,
+                                                  const uint64_t *__restrict__ hit_off, sfe_hit *__restrict__ out) {
+    Chunk c = chunks[blockIdx.x];
+    UnitDesc u = units[c.unit];
+    int64_t q = (int64_t)c.w0 + threadIdx.x;
+    if (q + sd.span > u.len) return;
+    uint32_t bs[17], bc[17];
+    int nb = seed_buckets(u.strand ? Qm : Qp, u.seq_start + q, sd, offsets, bs, bc);
+    uint64_t o = hit_off[(int64_t)blockIdx.x * 64 + threadIdx.x];
+    // k-way merge of the (t-sorted) buckets; buckets hold disjoint t sets
+    for (;;) {
+        int bmin = -1;
+        uint32_t tmin = 0xffffffffu;
+        for (int b = 0; b < nb; b++) {
+            if (bc[b]) {
+                uint32_t t = tpos[bs[b]];
+                if (bmin < 0 || t < tmin) { tmin = t; bmin = b; }
+            }
+        }
+        if (bmin < 0) break;
+        bs[bmin]++;
+        bc[bmin]--;
+        sfe_hit h;
+        h.t = tmin;
+        h.q = (uint32_t)q;
+        h.query_id = (uint32_t)u.query_id;
+        h.strand = (uint8_t)u.strand;
+        h.pad[0] = h.pad[1] = h.pad[2] = 0;
+        out[o++] = h;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ungapped X-drop (one hit per lane)
+// ---------------------------------------------------------------------------
+struct XResult { int64_t t0, q0, len; int32_t score; };
+
+// t, q relative to their sequences (which start at tb / qb in their sets and
+// have lengths nt / nq).  sub: 5x8 table in LDS.
+__device__ __forceinline__ XResult xdrop_one(const SeqSetView &T, int64_t tb, int64_t nt, const SeqSetView &Q,
+                                             int64_t qb, int64_t nq, int64_t t, int64_t q, int span,
+                                             const int *sub, int32_t X) {
+    int32_t s0 = 0;
+    for (int u = 0; u < span; u++) s0 += sub[base_code(T, tb + t + u) * 8 + base_code(Q, qb + q + u)];
+    int32_t s = 0, bR = 0;
+    int64_t R = 0;
+    int64_t lim = nt - t - span;
+    if (nq - q - span < lim) lim = nq - q - span;
+    for (int64_t r = 1; r <= lim; r++) {
+        s += sub[base_code(T, tb + t + span - 1 + r) * 8 + base_code(Q, qb + q + span - 1 + r)];
+        if (s > bR) { bR = s; R = r; }
+        else if (bR - s > X) break;
+    }
+    int32_t bL = 0;
+    int64_t L = 0;
+    s = 0;
+    lim = t < q ? t : q;
+    for (int64_t r = 1; r <= lim; r++) {
+        s += sub[base_code(T, tb + t - r) * 8 + base_code(Q, qb + q - r)];
+        if (s > bL) { bL = s; L = r; }
+        else if (bL - s > X) break;
+    }
+    XResult res;
+    res.t0 = t - L;
+    res.q0 = q - L;
+    res.len = L + span + R;
+    res.score = s0 + bL + bR;
+    return res;
+}
+
+__global__ void k_xdrop_raw(const sfe_hit *__restrict__ hits, int64_t n, const QueryDesc *__restrict__ qd,
+                            int32_t nq, SeqSetView T, int64_t tb, int64_t nt, SeqSetView Qp, SeqSetView Qm,
+                            ScoreDesc sc, int span, sfe_hsp *__restrict__ out) {
+    __shared__ int sub[40];
+    if (threadIdx.x < 40) sub[threadIdx.x] = (threadIdx.x & 7) < 5 ? sc.sub[threadIdx.x >> 3][threadIdx.x & 7] : 0;
+    __syncthreads();
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    sfe_hit h = hits[x];
+    QueryDesc d = qd[h.query_id];
+    XResult r = xdrop_one(T, tb, nt, h.strand ? Qm : Qp, d.start, d.len, h.t, h.q, span, sub, sc.xdrop);
+    sfe_hsp o;
+    o.t0 = (uint32_t)r.t0;
+    o.q0 = (uint32_t)r.q0;
+    o.len = (uint32_t)r.len;
+    o.score = r.score;
+    o.query_id = h.query_id;
+    o.strand = h.strand;
+    o.pad[0] = o.pad[1] = o.pad[2] = 0;
+    out[x] = o;
+}
+
+// Fused seed + X-drop: a block takes one chunk of 64 windows; its threads
+// walk the chunk's hits (flattened over windows and buckets) and append the
+// passing segments.  Hits never leave the chip.
+__global__ void __launch_bounds__(256) k_seed_xdrop(const UnitDesc *__restrict__ units, const Chunk *__restrict__ chunks,
+                                                    SeqSetView T, int64_t tb, int64_t nt, SeqSetView Qp, SeqSetView Qm,
+                                                    const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ tpos,
+                                                    SeedDesc sd, ScoreDesc sc, sfe_hsp *__restrict__ out, uint64_t cap,
+                                                    unsigned long long *__restrict__ counters) {
+    __shared__ int sub[40];
+    __shared__ uint32_t s_bstart[64][16];
+    __shared__ uint32_t s_bcum[64][17];     // cumulative bucket counts per window
+    __shared__ uint32_t s_wcum[65];         // cumulative hit counts over windows
+    Chunk c = chunks[blockIdx.x];
+    UnitDesc u = units[c.unit];
+    const SeqSetView Q = u.strand ? Qm : Qp;
+    if (threadIdx.x < 40) sub[threadIdx.x] = (threadIdx.x & 7) < 5 ? sc.sub[threadIdx.x >> 3][threadIdx.x & 7] : 0;
+    if (threadIdx.x < 64) {
+        int64_t q = (int64_t)c.w0 + threadIdx.x;
+        uint32_t bs[17], bc[17];
+        int nb = 0;
+        if (q + sd.span <= u.len) nb = seed_buckets(Q, u.seq_start + q, sd, offsets, bs, bc);
+        uint32_t cum = 0;
+        s_bcum[threadIdx.x][0] = 0;
+        for (int b = 0; b < 16; b++) {
+            uint32_t cnt = b < nb ? bc[b] : 0;
+            s_bstart[threadIdx.x][b] = b < nb ? bs[b] : 0;
+            cum += cnt;
+            s_bcum[threadIdx.x][b + 1] = cum;
+        }
+        s_wcum[threadIdx.x + 1] = cum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_wcum[0] = 0;
+        for (int w = 1; w <= 64; w++) s_wcum[w] += s_wcum[w - 1];
+    }
+    __syncthreads();
+    uint32_t total = s_wcum[64];
+    if (threadIdx.x == 0 && total) atomicAdd(&counters[0], (unsigned long long)total);
+    uint32_t passed = 0;
+    for (uint32_t h = threadIdx.x; h < total; h += blockDim.x) {
+        // window: last w with s_wcum[w] <= h
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (s_wcum[mid] <= h) lo = mid; else hi = mid - 1;
+        }
+        int w = lo;
+        uint32_t r = h - s_wcum[w];
+        int b = 0;
+        while (s_bcum[w][b + 1] <= r) b++;
+        uint32_t t = tpos[s_bstart[w][b] + (r - s_bcum[w][b])];
+        int64_t q = (int64_t)c.w0 + w;
+        XResult x = xdrop_one(T, tb, nt, Q, u.seq_start, u.len, t, q, sd.span, sub, sc.xdrop);
+        if (x.score >= sc.hsp_thresh) {
+            unsigned long long slot = atomicAdd(&counters[1], 1ull);
+            passed++;
+            if (slot < cap) {
+                sfe_hsp o;
+                o.t0 = (uint32_t)x.t0;
+                o.q0 = (uint32_t)x.q0;
+                o.len = (uint32_t)x.len;
+                o.score = x.score;
+                o.query_id = (uint32_t)u.query_id;
+                o.strand = (uint8_t)u.strand;
+                o.pad[0] = o.pad[1] = o.pad[2] = 0;
+                out[slot] = o;
+            }
+        }
+    }
+    (void)passed;
+}
+
+// ---------------------------------------------------------------------------
+// HSP set helpers: field extraction for the LSD multi-key sort, gather,
+// duplicate flags.
+// ---------------------------------------------------------------------------
+__global__ void k_hsp_key(const sfe_hsp *__restrict__ h, const uint32_t *__restrict__ perm, int64_t n, int field,
+                          uint32_t *__restrict__ key) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    sfe_hsp r = h[perm[x]];
+    uint32_t k;
+    switch (field) {
+    case 0: k = r.len; break;
+    case 1: k = r.q0; break;
+    case 2: k = r.t0; break;
+    case 3: k = r.strand; break;
+    case 4: k = ~((uint32_t)r.score ^ 0x80000000u); break;   // score descending
+    default: k = r.query_id; break;
+    }
+    key[x] = k;
+}
+
+__global__ void k_iota(uint32_t *__restrict__ a, int64_t n) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) a[x] = (uint32_t)x;
+}
+
+__global__ void k_hsp_unique_flags(const sfe_hsp *__restrict__ h, const uint32_t *__restrict__ perm, int64_t n,
+                                   uint32_t *__restrict__ flag) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    uint32_t f = 1;
+    if (x > 0) {
+        sfe_hsp a = h[perm[x - 1]], b = h[perm[x]];
+        f = !(a.t0 == b.t0 && a.q0 == b.q0 && a.len == b.len && a.strand == b.strand && a.query_id == b.query_id);
+    }
+    flag[x] = f;
+}
+
+__global__ void k_hsp_compact(const sfe_hsp *__restrict__ h, const uint32_t *__restrict__ perm,
+                              const uint32_t *__restrict__ flag, const uint32_t *__restrict__ dst, int64_t n,
+                              sfe_hsp *__restrict__ out) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    if (flag[x]) out[dst[x]] = h[perm[x]];
+}
+
+}  // namespace sfe

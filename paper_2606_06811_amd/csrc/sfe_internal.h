@@ -1,0 +1,118 @@
+// sfe_internal.h -- shared definitions of the gfx950 library (not installed).
+//
+// Device layout of a sequence set (target, query plus strands, query minus
+// strands): every sequence starts at a multiple of 64 bases and is followed by
+// at least 64 bases of padding, so word-granular reads never leave the
+// buffers.  Per base p of the set:
+//   bases[p >> 4] bits 2*(p & 15) .. +1   code A0 C1 G2 T3 (N stored as 0)
+//   nbits[p >> 5] bit  p & 31             1 = N (or an IUPAC ambiguity letter)
+//   sbits[p >> 5] bit  p & 31             1 = soft-masked (lower case)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sfe.h"
+
+#define SFE_NEG (-(1 << 30))
+
+namespace sfe {
+
+struct SeqSetView {
+    const uint32_t *bases;
+    const uint32_t *nbits;
+    const uint32_t *sbits;
+};
+
+// code 0..3, or 4 for N
+__device__ __forceinline__ int base_code(const SeqSetView &s, int64_t p) {
+    uint32_t w = s.bases[p >> 4];
+    uint32_t n = s.nbits[p >> 5];
+    int c = (int)((w >> ((p & 15) * 2)) & 3u);
+    return ((n >> (p & 31)) & 1u) ? 4 : c;
+}
+
+// Seed description resolved on the host.
+struct SeedDesc {
+    int32_t span, weight, transitions, step;
+    int32_t care[16];
+};
+
+// 64 consecutive bases starting at p (bit 2*u = base p+u) as two words, and
+// the OR of the N and soft planes over 32 bases starting at p.
+__device__ __forceinline__ uint64_t bases64(const SeqSetView &s, int64_t p) {
+    int64_t w = p >> 4;
+    int sh = (int)(p & 15) * 2;
+    uint64_t lo = (uint64_t)s.bases[w] | ((uint64_t)s.bases[w + 1] << 32);
+    uint64_t hi = (uint64_t)s.bases[w + 2];
+    if (sh == 0) return lo;
+    return (lo >> sh) | (hi << (64 - sh));
+}
+__device__ __forceinline__ uint32_t masked32(const SeqSetView &s, int64_t p) {
+    int64_t w = p >> 5;
+    int sh = (int)(p & 31);
+    uint64_t a = (uint64_t)(s.nbits[w] | s.sbits[w]) | ((uint64_t)(s.nbits[w + 1] | s.sbits[w + 1]) << 32);
+    return (uint32_t)(a >> sh);
+}
+
+// Window at p (absolute position in the set) of a sequence whose last valid
+// window start is `last`: valid iff p <= last and no N / soft-masked base in
+// the span.  On success *key holds the care codes, first care position most
+// significant.
+__device__ __forceinline__ bool window_key(const SeqSetView &s, int64_t p, const SeedDesc &sd, uint32_t *key) {
+    uint32_t m = masked32(s, p);
+    uint32_t spanmask = sd.span >= 32 ? 0xffffffffu : ((1u << sd.span) - 1u);
+    if (m & spanmask) return false;
+    uint64_t b = bases64(s, p);
+    uint32_t k = 0;
+    for (int c = 0; c < sd.weight; c++) k = (k << 2) | (uint32_t)((b >> (2 * sd.care[c])) & 3u);
+    *key = k;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Gapped extension: tasks, results, traceback arena
+// ---------------------------------------------------------------------------
+// A half reads A(i) = target[a0 + adir * i] for i < nA and
+// B(j) = qset[b0 + bdir * j] for j < nB (positions absolute in their sets).
+struct HalfTask {
+    int64_t a0, b0;
+    int32_t nA, nB;
+    int32_t adir, bdir;
+    int32_t qset;           // 0 plus-strand query set, 1 minus-strand set
+    int32_t pad;
+};
+
+#define HALF_OK 0
+#define HALF_WIDTH_OVERFLOW 1
+#define HALF_ARENA_OVERFLOW 2
+
+struct HalfResult {
+    int32_t best, i_end, j_end, status;
+    uint64_t cells;
+    uint64_t tb_page;       // arena byte offset of the page holding the end cell's record
+    uint32_t tb_end;        // end offset (within that page) of the end cell's record
+    int32_t k_last;         // last antidiagonal computed
+};
+
+// Traceback pointer arena.  Pages of ARENA_PAGE bytes (a record larger than a
+// page gets several consecutive pages).  Page header (16 bytes):
+//   u64 previous page offset (~0 for the first page of a half), u32 end offset
+//   of the last record in the previous page, u32 pages in this allocation.
+// Records follow, one per antidiagonal k = 1, 2, ... of the half, each
+//   payload: 4-bit codes for rows r0 .. r0+n-1, two per byte, low nibble
+//            first, padded to a multiple of 4 bytes
+//   footer : u32 r0, u32 n
+// Code bits: 0-1 H source (0 diagonal, 1 E, 2 F), 2 E opened from H,
+//            3 F opened from H.
+#define ARENA_PAGE 32768u
+#define ARENA_HDR 16u
+
+struct Arena {
+    uint8_t *base;
+    uint64_t bytes;
+    unsigned long long *head;   // device counter: bytes handed out
+};
+
+__host__ __device__ __forceinline__ uint32_t rec_payload_bytes(uint32_t n) { return ((n + 1) / 2 + 3) & ~3u; }
+
+}  // namespace sfe

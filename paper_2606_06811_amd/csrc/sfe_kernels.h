@@ -1,0 +1,79 @@
+// sfe_kernels.h -- kernel declarations and small device-side descriptors.
+#pragma once
+#include "sfe_internal.h"
+
+namespace sfe {
+
+struct ScoreDesc {
+    int32_t sub[5][5];
+    int32_t gap_open, gap_extend, xdrop, hsp_thresh, ydrop, gapped_thresh;
+};
+
+// One (query, strand) unit: its bases are [seq_start, seq_start + len) of the
+// plus or minus query set.
+struct UnitDesc {
+    int64_t seq_start;
+    int64_t len;
+    int32_t query_id;
+    int32_t strand;
+};
+
+// 64 consecutive query windows of one unit, starting at window w0.
+struct Chunk {
+    int32_t unit;
+    int32_t w0;
+};
+
+struct QueryDesc {
+    int64_t start;      // same start in the plus and the minus set
+    int64_t len;
+};
+
+// A batch item of the gapped stage: anchor column (ta, qa) of a unit.
+struct ExtItem {
+    uint32_t ta, qa;
+    int32_t unit;
+    int32_t pad;
+};
+
+hipError_t upload_encoding_table(hipStream_t st);
+
+__global__ void k_pack(const uint8_t *txt, int64_t len, int64_t out_start, int rc, uint32_t *bases,
+                       uint32_t *nbits, uint32_t *sbits, int *bad);
+__global__ void k_index_keys(SeqSetView T, int64_t nslots, int32_t step, SeedDesc sd, uint32_t sentinel,
+                             uint32_t *keys, uint32_t *pos);
+__global__ void k_offsets(const uint32_t *keys, int64_t n, uint32_t K, uint32_t *offsets);
+__global__ void k_seed_count(const UnitDesc *units, const Chunk *chunks, SeqSetView Qp, SeqSetView Qm,
+                             const uint32_t *offsets, SeedDesc sd, uint64_t *counts);
+__global__ void k_seed_emit(const UnitDesc *units, const Chunk *chunks, SeqSetView Qp, SeqSetView Qm,
+                            const uint32_t *offsets, const uint32_t *tpos, SeedDesc sd, const uint64_t *hit_off,
+                            sfe_hit *out);
+__global__ void k_xdrop_raw(const sfe_hit *hits, int64_t n, const QueryDesc *qd, int32_t nq, SeqSetView T, int64_t tb,
+                            int64_t nt, SeqSetView Qp, SeqSetView Qm, ScoreDesc sc, int span, sfe_hsp *out);
+__global__ void k_seed_xdrop(const UnitDesc *units, const Chunk *chunks, SeqSetView T, int64_t tb, int64_t nt,
+                             SeqSetView Qp, SeqSetView Qm, const uint32_t *offsets, const uint32_t *tpos, SeedDesc sd,
+                             ScoreDesc sc, sfe_hsp *out, uint64_t cap, unsigned long long *counters);
+__global__ void k_hsp_key(const sfe_hsp *h, const uint32_t *perm, int64_t n, int field, uint32_t *key);
+__global__ void k_iota(uint32_t *a, int64_t n);
+__global__ void k_hsp_unique_flags(const sfe_hsp *h, const uint32_t *perm, int64_t n, uint32_t *flag);
+__global__ void k_hsp_compact(const sfe_hsp *h, const uint32_t *perm, const uint32_t *flag, const uint32_t *dst,
+                              int64_t n, sfe_hsp *out);
+
+// gapped stage (k_extend.hip)
+void launch_make_tasks(const ExtItem *items, int64_t n, const UnitDesc *units, int64_t nt, HalfTask *tasks,
+                       hipStream_t st);
+void launch_ydrop(int cells_per_lane, const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T,
+                  SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, Arena arena, HalfResult *res, hipStream_t st);
+void launch_ydrop_ring(const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T, SeqSetView Qp,
+                       SeqSetView Qm, const ScoreDesc &sc, Arena arena, int32_t *ring, int32_t cap_rows,
+                       HalfResult *res, hipStream_t st);
+void launch_assemble(const ExtItem *items, int64_t n, const UnitDesc *units, const HalfResult *res,
+                     SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, sfe_aln *out,
+                     hipStream_t st);
+void launch_traceback(const HalfResult *res, const int32_t *half_ids, int64_t n, Arena arena,
+                      const uint64_t *run_off, uint32_t *runs, uint32_t *nruns, hipStream_t st);
+void launch_ops_assemble(const int32_t *item_ids, int64_t n, const uint64_t *run_off, const uint32_t *runs,
+                         const uint32_t *nruns, const uint64_t *ops_off, uint32_t *ops, uint32_t *nops,
+                         hipStream_t st);
+
+}  // namespace sfe

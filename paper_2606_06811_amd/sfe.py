@@ -1,0 +1,264 @@
+"""Python binding of libsfe.so (include/sfe.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module converts
+numpy arrays / torch tensors to the C structs and pointers and back.  If the
+library is not built the import of the product path fails loudly: there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfe.so")
+_lib = None
+
+SFE_OK, SFE_EINVAL, SFE_ENOMEM, SFE_ECAPACITY, SFE_ERANGE, SFE_EDEVICE, SFE_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+SFE_XDROP_RAW = 1
+SFE_ALN_PASSED = 1
+SFE_SCHED_PLAIN, SFE_SCHED_PERSISTENT = 0, 1
+
+HIT_DTYPE = np.dtype([("t", "<u4"), ("q", "<u4"), ("query_id", "<u4"), ("strand", "u1"), ("pad", "u1", (3,))])
+HSP_DTYPE = np.dtype([("t0", "<u4"), ("q0", "<u4"), ("len", "<u4"), ("score", "<i4"), ("query_id", "<u4"),
+                      ("strand", "u1"), ("pad", "u1", (3,))])
+ALN_DTYPE = np.dtype([("t_start", "<u4"), ("t_end", "<u4"), ("q_start", "<u4"), ("q_end", "<u4"),
+                      ("score", "<i4"), ("query_id", "<u4"), ("anchor_t", "<u4"), ("anchor_q", "<u4"),
+                      ("ops_offset", "<u8"), ("cells", "<u8"), ("ops_len", "<u4"), ("strand", "u1"),
+                      ("flags", "u1"), ("pad", "u1", (2,))])
+assert HIT_DTYPE.itemsize == 16 and HSP_DTYPE.itemsize == 24 and ALN_DTYPE.itemsize == 56
+
+
+class SfeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"sfe status {status}: {msg}")
+        self.status = status
+
+
+class _Seq(ctypes.Structure):
+    _fields_ = [("residues", ctypes.c_void_p), ("length", ctypes.c_int64)]
+
+
+class _SeedSpec(ctypes.Structure):
+    _fields_ = [("pattern", ctypes.c_char_p), ("transitions", ctypes.c_int32), ("step", ctypes.c_int32)]
+
+
+class _Scoring(ctypes.Structure):
+    _fields_ = [("sub", ctypes.c_int32 * 25), ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32),
+                ("xdrop", ctypes.c_int32), ("hsp_thresh", ctypes.c_int32), ("ydrop", ctypes.c_int32),
+                ("gapped_thresh", ctypes.c_int32)]
+
+
+class _AlignOpts(ctypes.Structure):
+    _fields_ = [("round_k", ctypes.c_int32), ("schedule", ctypes.c_int32), ("strands", ctypes.c_int32),
+                ("max_cells_per_lane", ctypes.c_int32), ("arena_bytes", ctypes.c_int64)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("seed_hits", "hsps_raw", "hsps", "rounds", "extensions", "committed",
+                                               "shadow", "cells", "overflow_reruns")] + \
+               [(n, ctypes.c_double) for n in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total")]
+
+
+def lib():
+    """The loaded libsfe.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.sfe_ctx_create.argtypes = [ctypes.c_int, P, ctypes.POINTER(P)]
+        L.sfe_ctx_destroy.argtypes = [P]
+        L.sfe_build_index.argtypes = [P, ctypes.POINTER(_Seq), ctypes.POINTER(_SeedSpec), ctypes.POINTER(P)]
+        L.sfe_index_destroy.argtypes = [P]
+        L.sfe_seed_hits.argtypes = [P, P, ctypes.POINTER(_Seq), I32, I32, P, I64, ctypes.POINTER(I64)]
+        L.sfe_ungapped_xdrop.argtypes = [P, P, ctypes.POINTER(_Seq), I32, P, I64, ctypes.POINTER(_Scoring), I32, P,
+                                         I64, ctypes.POINTER(I64)]
+        L.sfe_gapped_ydrop.argtypes = [P, P, ctypes.POINTER(_Seq), I32, P, I64, ctypes.POINTER(_Scoring), P, P, I64,
+                                       ctypes.POINTER(I64)]
+        L.sfe_align.argtypes = [P, P, ctypes.POINTER(_Seq), I32, ctypes.POINTER(_Scoring), ctypes.POINTER(_AlignOpts),
+                                P, I64, ctypes.POINTER(I64), P, I64, ctypes.POINTER(I64), ctypes.POINTER(_Stats)]
+        L.sfe_status_str.argtypes = [I32]
+        L.sfe_status_str.restype = ctypes.c_char_p
+        L.sfe_last_error.argtypes = [P]
+        L.sfe_last_error.restype = ctypes.c_char_p
+        for f in ("sfe_ctx_create", "sfe_build_index", "sfe_seed_hits", "sfe_ungapped_xdrop", "sfe_gapped_ydrop",
+                  "sfe_align"):
+            getattr(L, f).restype = I32
+        _lib = L
+    return _lib
+
+
+def _check(st, ctx=None):
+    if st != SFE_OK:
+        msg = lib().sfe_last_error(ctx.ptr if ctx is not None else None)
+        raise SfeError(st, msg.decode() if msg else "")
+
+
+def _ptr(a):
+    """Raw address of a numpy array or a torch tensor (host or device)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _seq_arrays(seqs):
+    """Keeps the residue buffers alive and builds the sfe_seq array."""
+    keep = []
+    arr = (_Seq * max(1, len(seqs)))()
+    for i, s in enumerate(seqs):
+        if isinstance(s, (bytes, bytearray)):
+            s = np.frombuffer(bytes(s), dtype=np.uint8)
+        if hasattr(s, "data_ptr"):
+            n = s.numel()
+        else:
+            s = np.ascontiguousarray(s, dtype=np.uint8)
+            n = s.shape[0]
+        keep.append(s)
+        arr[i].residues = _ptr(s) if n else None
+        arr[i].length = n
+    return arr, keep
+
+
+def scoring_struct(d: dict) -> _Scoring:
+    s = _Scoring()
+    flat = [int(v) for row in d["sub"] for v in row]
+    for i, v in enumerate(flat):
+        s.sub[i] = v
+    for f in ("gap_open", "gap_extend", "xdrop", "hsp_thresh", "ydrop", "gapped_thresh"):
+        setattr(s, f, int(d[f]))
+    return s
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        p = ctypes.c_void_p()
+        _check(lib().sfe_ctx_create(int(device), stream, ctypes.byref(p)))
+        self.ptr = p
+
+    def close(self):
+        if self.ptr:
+            lib().sfe_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Index:
+    def __init__(self, ctx: Context, ptr, nt: int):
+        self.ctx, self.ptr, self.nt = ctx, ptr, nt
+
+    def close(self):
+        if self.ptr:
+            lib().sfe_index_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sfe_ctx_create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+def sfe_build_index(ctx: Context, target, pattern: str = "1110100110010101111", transitions: int = 1,
+                    step: int = 1) -> Index:
+    seqs, keep = _seq_arrays([target])
+    spec = _SeedSpec(pattern.encode(), int(transitions), int(step))
+    p = ctypes.c_void_p()
+    _check(lib().sfe_build_index(ctx.ptr, seqs, ctypes.byref(spec), ctypes.byref(p)), ctx)
+    return Index(ctx, p, seqs[0].length)
+
+
+def _two_call(fn, dtype, guess):
+    """Runs fn(buffer, cap) -> (status, needed) with the capacity protocol."""
+    cap = max(int(guess), 1)
+    while True:
+        buf = np.zeros(cap, dtype)
+        st, need = fn(buf, cap)
+        if st == SFE_ECAPACITY and need > cap:
+            cap = need
+            continue
+        return st, buf[:need] if st == SFE_OK else buf[:0], need
+
+
+def sfe_seed_hits(ctx: Context, idx: Index, queries, strands: int = 3) -> np.ndarray:
+    seqs, keep = _seq_arrays(queries)
+    n = ctypes.c_int64()
+
+    def fn(buf, cap):
+        st = lib().sfe_seed_hits(ctx.ptr, idx.ptr, seqs, len(queries), int(strands), _ptr(buf), cap, ctypes.byref(n))
+        return st, n.value
+
+    st, out, _ = _two_call(fn, HIT_DTYPE, 1 << 16)
+    _check(st, ctx)
+    return out
+
+
+def sfe_ungapped_xdrop(ctx: Context, idx: Index, queries, hits: np.ndarray, scoring: dict, raw: bool = False):
+    seqs, keep = _seq_arrays(queries)
+    hits = np.ascontiguousarray(hits, HIT_DTYPE)
+    sc = scoring_struct(scoring)
+    n = ctypes.c_int64()
+
+    def fn(buf, cap):
+        st = lib().sfe_ungapped_xdrop(ctx.ptr, idx.ptr, seqs, len(queries), _ptr(hits), hits.shape[0],
+                                      ctypes.byref(sc), SFE_XDROP_RAW if raw else 0, _ptr(buf), cap, ctypes.byref(n))
+        return st, n.value
+
+    st, out, _ = _two_call(fn, HSP_DTYPE, max(hits.shape[0], 1) if raw else 1 << 14)
+    _check(st, ctx)
+    return out
+
+
+def sfe_gapped_ydrop(ctx: Context, idx: Index, queries, hsps: np.ndarray, scoring: dict):
+    seqs, keep = _seq_arrays(queries)
+    hsps = np.ascontiguousarray(hsps, HSP_DTYPE)
+    sc = scoring_struct(scoring)
+    out = np.zeros(hsps.shape[0], ALN_DTYPE)
+    n = ctypes.c_int64()
+    cap = 1 << 16
+    while True:
+        ops = np.zeros(cap, np.uint32)
+        st = lib().sfe_gapped_ydrop(ctx.ptr, idx.ptr, seqs, len(queries), _ptr(hsps), hsps.shape[0],
+                                    ctypes.byref(sc), _ptr(out), _ptr(ops), cap, ctypes.byref(n))
+        if st == SFE_ECAPACITY and n.value > cap:
+            cap = n.value
+            continue
+        _check(st, ctx)
+        return out, ops[:n.value]
+
+
+def sfe_align(ctx: Context, idx: Index, queries, scoring: dict, round_k: int = 0, schedule: int = SFE_SCHED_PLAIN,
+              strands: int = 3, max_cells_per_lane: int = 0, arena_bytes: int = 0, cap: int = 1 << 12,
+              ops_cap: int = 1 << 18):
+    """Whole pipeline; returns (alignments, ops, stats dict)."""
+    seqs, keep = _seq_arrays(queries)
+    sc = scoring_struct(scoring)
+    opts = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(arena_bytes))
+    na, no = ctypes.c_int64(), ctypes.c_int64()
+    stats = _Stats()
+    while True:
+        out = np.zeros(cap, ALN_DTYPE)
+        ops = np.zeros(ops_cap, np.uint32)
+        st = lib().sfe_align(ctx.ptr, idx.ptr, seqs, len(queries), ctypes.byref(sc), ctypes.byref(opts),
+                             _ptr(out), cap, ctypes.byref(na), _ptr(ops), ops_cap, ctypes.byref(no),
+                             ctypes.byref(stats))
+        if st == SFE_ECAPACITY and (na.value > cap or no.value > ops_cap):
+            cap, ops_cap = max(cap, na.value), max(ops_cap, no.value)
+            continue
+        _check(st, ctx)
+        s = {f: getattr(stats, f) for f, _ in _Stats._fields_}
+        return out[:na.value], ops[:no.value], s

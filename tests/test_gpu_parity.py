@@ -1,0 +1,262 @@
+"""Parity of the HIP path with the CPU oracle, element by element, through the
+C ABI.  Integer results must be bit-exact.  Sizes are chosen so the oracle
+finishes in seconds while the GPU path still spans many 64-window chunks,
+several batches and ragged tails."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_06811_amd import sfe, synth
+
+pytestmark = pytest.mark.gpu
+
+PATTERN = synth.SEED_PATTERN
+
+
+def log(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    log("creating context on device 0")
+    c = sfe.sfe_ctx_create(0)
+    yield c
+    c.close()
+
+
+def decorate(seq: np.ndarray, rng, n_runs=3, soft_runs=3):
+    """Adds N runs and soft-masked (lower-case) runs to an ASCII sequence."""
+    s = seq.copy()
+    L = s.shape[0]
+    for _ in range(n_runs):
+        a = int(rng.integers(0, max(1, L - 40)))
+        s[a:a + int(rng.integers(1, 30))] = ord("N")
+    for _ in range(soft_runs):
+        a = int(rng.integers(0, max(1, L - 200)))
+        b = a + int(rng.integers(20, 200))
+        seg = s[a:b]
+        up = (seg >= ord("A")) & (seg <= ord("Z")) & (seg != ord("N"))
+        seg[up] += 32
+        s[a:b] = seg
+    return s
+
+
+def make_pair(n=50_000, seed=3, div=0.15, nq=1):
+    rng = synth.rng_for(seed + 100)
+    T, Q = synth.pair_small(n=n, divergence=div, seed=seed, seg_len=max(1000, n // 20))
+    T = decorate(T, rng)
+    qs = [decorate(Q[0], rng)]
+    for k in range(1, nq):
+        a = int(rng.integers(0, n // 2))
+        piece = T[a:a + n // 3].copy()
+        qs.append(piece[::-1].copy() if k % 2 else piece)
+    return T, qs
+
+
+def oracle_units(T, Q, strands=3):
+    tc, ts = oracle.encode(T)
+    for qid, q in enumerate(Q):
+        qc, qs = oracle.encode(q)
+        for s in (0, 1):
+            if not (strands >> s) & 1:
+                continue
+            c, m = (qc, qs) if s == 0 else oracle.revcomp(qc, qs)
+            yield qid, s, tc, ts, c, m
+
+
+# ---------------------------------------------------------------------------
+# seeds
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("transitions,step,strands", [(1, 1, 3), (0, 1, 3), (1, 3, 1), (1, 1, 2)])
+def test_seed_hits_parity(ctx, transitions, step, strands):
+    log(f"seed parity transitions={transitions} step={step} strands={strands}")
+    T, Q = make_pair(n=40_000, seed=5, nq=2)
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, transitions, step)
+    got = sfe.sfe_seed_hits(ctx, idx, Q, strands)
+    want = []
+    for qid, s, tc, ts, c, m in oracle_units(T, Q, strands):
+        t, q = oracle.seed_hits(tc, ts, c, m, PATTERN, transitions, step)
+        w = np.zeros(t.shape[0], sfe.HIT_DTYPE)
+        w["t"], w["q"], w["query_id"], w["strand"] = t, q, qid, s
+        want.append(w)
+    want = np.concatenate(want)
+    assert want.shape[0] > 1000
+    assert got.shape == want.shape
+    for f in ("t", "q", "query_id", "strand"):
+        assert np.array_equal(got[f], want[f]), f
+
+
+def test_seed_hits_edge_sequences(ctx):
+    log("seed edge sequences")
+    rng = synth.rng_for(9)
+    T = synth.to_ascii(synth.iid_codes(rng, 5000))
+    Q = [np.zeros(0, np.uint8), T[:10].copy(), np.full(300, ord("N"), np.uint8),
+         (T[100:400] + 32).astype(np.uint8),
+         T[4981:].copy(), T[:19].copy()]
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    got = sfe.sfe_seed_hits(ctx, idx, Q, 3)
+    want = []
+    for qid, s, tc, ts, c, m in oracle_units(T, Q):
+        t, q = oracle.seed_hits(tc, ts, c, m, PATTERN, 1, 1)
+        want += [(int(a), int(b), qid, s) for a, b in zip(t, q)]
+    assert [(int(h["t"]), int(h["q"]), int(h["query_id"]), int(h["strand"])) for h in got] == want
+    assert any(w[2] == 4 for w in want) and any(w[2] == 5 for w in want)   # windows ending at sequence ends
+
+
+def test_bad_inputs_return_errors(ctx):
+    T = np.frombuffer(b"ACGTX" * 10, np.uint8)
+    with pytest.raises(sfe.SfeError) as e:
+        sfe.sfe_build_index(ctx, T)
+    assert e.value.status == sfe.SFE_EINVAL
+    good = np.frombuffer(b"ACGT" * 20, np.uint8)
+    with pytest.raises(sfe.SfeError):
+        sfe.sfe_build_index(ctx, good, "0110")
+    with pytest.raises(sfe.SfeError):
+        sfe.sfe_build_index(ctx, good, "1" * 15)
+
+
+# ---------------------------------------------------------------------------
+# X-drop and the HSP set
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def seeded(ctx):
+    T, Q = make_pair(n=60_000, seed=7, nq=2)
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    hits = sfe.sfe_seed_hits(ctx, idx, Q, 3)
+    return T, Q, idx, hits
+
+
+def test_xdrop_raw_parity(ctx, seeded):
+    log("x-drop raw parity")
+    T, Q, idx, hits = seeded
+    sc = dict(synth.SCORING)
+    got = sfe.sfe_ungapped_xdrop(ctx, idx, Q, hits, sc, raw=True)
+    assert got.shape[0] == hits.shape[0]
+    for qid, s, tc, ts, c, m in oracle_units(T, Q):
+        sel = (hits["query_id"] == qid) & (hits["strand"] == s)
+        ref = oracle.xdrop(tc, c, hits["t"][sel], hits["q"][sel], 19, sc)
+        g = got[sel]
+        for f in ("t0", "q0", "len", "score"):
+            assert np.array_equal(g[f].astype(np.int64), ref[f]), f
+
+
+@pytest.mark.parametrize("xdrop", [910, 0, 1 << 28])
+def test_hsp_set_parity(ctx, seeded, xdrop):
+    log(f"hsp set parity xdrop={xdrop}")
+    T, Q, idx, hits = seeded
+    sc = dict(synth.SCORING, xdrop=xdrop, hsp_thresh=2000)
+    got = sfe.sfe_ungapped_xdrop(ctx, idx, Q, hits, sc)
+    total = 0
+    for qid, s, tc, ts, c, m in oracle_units(T, Q):
+        sel = (hits["query_id"] == qid) & (hits["strand"] == s)
+        ref = oracle.hsp_set(oracle.xdrop(tc, c, hits["t"][sel], hits["q"][sel], 19, sc), sc["hsp_thresh"])
+        g = got[(got["query_id"] == qid) & (got["strand"] == s)]
+        assert g.shape[0] == ref.shape[0]
+        for f in ("t0", "q0", "len", "score"):
+            assert np.array_equal(g[f].astype(np.int64), ref[f]), f
+        total += g.shape[0]
+    assert total > 20
+    # global order: query, score descending, strand, t0, q0, len
+    key = list(zip(got["query_id"].tolist(), (-got["score"].astype(np.int64)).tolist(), got["strand"].tolist(),
+                   got["t0"].tolist(), got["q0"].tolist(), got["len"].tolist()))
+    assert key == sorted(key)
+
+
+# ---------------------------------------------------------------------------
+# gapped extension (pure, speculative)
+# ---------------------------------------------------------------------------
+def compare_extensions(T, Q, hsps, alns, ops, sc):
+    tcodes = oracle.encode(T)[0]
+    qcodes = {}
+    for x in range(hsps.shape[0]):
+        h = hsps[x]
+        key = (int(h["query_id"]), int(h["strand"]))
+        if key not in qcodes:
+            qc, qs = oracle.encode(Q[key[0]])
+            qcodes[key] = qc if key[1] == 0 else oracle.revcomp(qc, qs)[0]
+        off = (int(h["len"]) - 1) // 2
+        ra, rops = oracle.extend(tcodes, qcodes[key], int(h["t0"]) + off, int(h["q0"]) + off, sc)
+        a = alns[x]
+        got = [int(a[f]) for f in ("t_start", "t_end", "q_start", "q_end", "score", "anchor_t", "anchor_q", "cells")]
+        want = [int(ra[f]) for f in ("t_start", "t_end", "q_start", "q_end", "score", "anchor_t", "anchor_q", "cells")]
+        assert got == want, (x, got, want)
+        passed = int(ra["score"]) >= sc["gapped_thresh"]
+        assert bool(a["flags"] & 1) == passed
+        if passed:
+            g = ops[int(a["ops_offset"]):int(a["ops_offset"]) + int(a["ops_len"])]
+            assert np.array_equal(g, rops), x
+
+
+def test_gapped_ydrop_parity(ctx, seeded):
+    log("gapped y-drop parity")
+    T, Q, idx, hits = seeded
+    sc = dict(synth.SCORING)
+    hsps = sfe.sfe_ungapped_xdrop(ctx, idx, Q, hits, sc)
+    rng = synth.rng_for(1)
+    pick = np.sort(rng.choice(hsps.shape[0], size=min(120, hsps.shape[0]), replace=False))
+    sub = hsps[pick]
+    alns, ops = sfe.sfe_gapped_ydrop(ctx, idx, Q, sub, sc)
+    compare_extensions(T, Q, sub, alns, ops, sc)
+
+
+@pytest.mark.parametrize("ydrop,gap_open,gap_extend", [(9400, 400, 30), (0, 400, 30), (300, 100, 5),
+                                                      (2000, 0, 1), (1 << 20, 400, 30)])
+def test_gapped_ydrop_scoring_variants(ctx, ydrop, gap_open, gap_extend):
+    """Narrow, pruned-to-nothing and very wide bands (the last two force the
+    wider register window and the workgroup kernel)."""
+    log(f"y-drop variant Y={ydrop} o={gap_open} e={gap_extend}")
+    rng = synth.rng_for(ydrop % 97 + gap_extend)
+    n = 2500
+    t = synth.iid_codes(rng, n)
+    q, _ = synth.mutate(rng, t, np.zeros(n, bool), 0.2)
+    T, Qs = synth.to_ascii(t), [synth.to_ascii(q)]
+    sc = dict(synth.SCORING, ydrop=ydrop, gap_open=gap_open, gap_extend=gap_extend, gapped_thresh=-(1 << 29))
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    h = np.zeros(6, sfe.HSP_DTYPE)
+    for x, (t0, q0) in enumerate([(0, 0), (1200, 1190), (2400, 2380), (50, 60), (1000, 1020), (2480, 2480)]):
+        q0 = min(q0, Qs[0].shape[0] - 2)
+        h[x] = (t0, q0, 1, 0, 0, 0, (0, 0, 0))
+    alns, ops = sfe.sfe_gapped_ydrop(ctx, idx, Qs, h, sc)
+    compare_extensions(T, Qs, h, alns, ops, sc)
+
+
+# ---------------------------------------------------------------------------
+# whole pipeline
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def align_case():
+    T, Q = make_pair(n=60_000, seed=13, nq=2)
+    ref = oracle.pipeline(T, Q, dict(synth.SCORING))
+    return T, Q, ref
+
+
+def compare_alignments(alns, ops, ref):
+    ra = ref["alns"]
+    assert alns.shape[0] == ra.shape[0], (alns.shape[0], ra.shape[0])
+    for f in ("query_id", "strand", "t_start", "t_end", "q_start", "q_end", "score", "anchor_t", "anchor_q", "cells"):
+        assert np.array_equal(alns[f].astype(np.int64), ra[f].astype(np.int64)), f
+    for x in range(alns.shape[0]):
+        g = ops[int(alns["ops_offset"][x]):int(alns["ops_offset"][x]) + int(alns["ops_len"][x])]
+        assert np.array_equal(g, oracle.aln_ops(ref, x)), x
+
+
+@pytest.mark.parametrize("K,cpl", [(1, 0), (7, 0), (64, 0), (1000, 0), (64, 16)])
+def test_align_parity(ctx, align_case, K, cpl):
+    log(f"align parity K={K} cells_per_lane={cpl}")
+    T, Q, ref = align_case
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    alns, ops, st = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), round_k=K, max_cells_per_lane=cpl)
+    assert alns.shape[0] >= 3
+    compare_alignments(alns, ops, ref)
+    assert st["committed"] == alns.shape[0]
+    assert st["extensions"] >= ref["n_extensions"]
+
+
+def test_align_tiny_arena_reruns(ctx, align_case):
+    """A small traceback arena forces re-runs; results must not change."""
+    log("align with a tiny arena")
+    T, Q, ref = align_case
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    alns, ops, st = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), round_k=64, arena_bytes=1 << 20)
+    compare_alignments(alns, ops, ref)
