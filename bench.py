@@ -1,0 +1,175 @@
+"""Benchmark of the seed -> X-drop -> Y-drop pipeline on one MI355X.
+
+One step = one pass of the whole hot path over the mid-size workload: build
+the position table of a 50 Mbp target (2-bit packing, seed keys, sort),
+seed hits of a 50 Mbp query on both strands fused with the ungapped X-drop
+filter, the HSP set (dedup + order), and the speculative batched gapped
+Y-drop extension with traceback and serial commit.  Inputs are synthetic
+(seeded), resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is unique HSPs per second of the whole step;
+gapped GCUPS and the other stage rates ride along.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz of int32 VALU lane-ops per second
+INT32_VALU_PEAK_OPS = 256 * 64 * 2.4e9
+YDROP_OPS_PER_CELL = 12      # E 3, F 3, G 2, H 1, prune 2, best 1
+XDROP_OPS_PER_COLUMN = 6     # 2 base extracts, index, lookup, add, max / drop test
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from paper_2606_06811_amd import synth
+    if name == "mid":
+        T, Q = synth.pair_mid()
+        desc = "50 Mbp target (200 repeat families x 50 copies, 1% soft-masked low complexity) vs 50 Mbp query (SVs + 25% divergence, 2% indels)"
+    elif name == "small":
+        T, Q = synth.pair_small()
+        desc = "1 Mbp target vs 1 Mbp query (3 inversions, 3 translocations of 20 kbp, 15% divergence, 2% indels)"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return T, Q, desc
+
+
+def cpu_baseline(T, Q, sc, sample_bp: int):
+    """The oracle, single-threaded, on the first sample_bp query bases vs the whole target."""
+    import oracle
+    oracle.build()
+    q = [Q[0][:sample_bp].copy()]
+    t0 = time.perf_counter()
+    res = oracle.pipeline(T, q, sc)
+    dt = time.perf_counter() - t0
+    nh = sum(int(u["hsps"].shape[0]) for u in res["units"])
+    return dict(value=nh / dt, unit="HSPs/s", cores=1, kind="oracle",
+                sample=f"first {sample_bp} query bases (both strands) vs the full target; "
+                       f"{nh} unique HSPs, {res['alns'].shape[0]} alignments, {res['ext_cells']} DP cells "
+                       f"in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mid", choices=["mid", "small"])
+    ap.add_argument("--round-k", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--cpu-sample-bp", type=int, default=60_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    from paper_2606_06811_amd import sfe, synth
+
+    t0 = time.time()
+    T, Q, desc = make_workload(args.workload)
+    log(f"workload generated in {time.time() - t0:.1f} s: target {T.shape[0]} bp, query {Q[0].shape[0]} bp")
+    sc = dict(synth.SCORING)
+    dev = torch.device("cuda:0")
+    Td = torch.from_numpy(T).to(dev)
+    Qd = [torch.from_numpy(q).to(dev) for q in Q]
+    stream = torch.cuda.current_stream(dev)
+    ctx = sfe.sfe_ctx_create(0, stream.cuda_stream)
+    torch.cuda.synchronize()
+
+    def step():
+        idx = sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
+        out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k, schedule=args.schedule,
+                            cap=1 << 21, ops_cap=1 << 26)
+        idx.close()
+        return out
+
+    for w in range(args.warmup):
+        a, o, s = step()
+        log(f"warmup {w}: {s['hsps']} HSPs, {s['committed']} alignments, {s['rounds']} rounds, "
+            f"{s['ms_total']:.0f} ms")
+    torch.cuda.synchronize()
+    stats = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        a, o, s = step()
+        stats.append(s)
+        log(f"step {k}: {s['ms_total']:.0f} ms in align (seed+xdrop {s['ms_seed_xdrop']:.0f}, "
+            f"hsp set {s['ms_hsp_set']:.0f}, extend {s['ms_extend']:.0f})")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1e3 * elapsed / args.steps
+    s = stats[-1]
+    hsps_per_s = s["hsps"] / (ms_step / 1e3)
+
+    # dominant kernel: gapped extension (int32 VALU bound); live HIP-event timing
+    yd_ms = sum(x["ms_ydrop_kernel"] for x in stats)
+    yd_cells = sum(x["ydrop_kernel_cells"] for x in stats)
+    yd_launches = sum(x["ydrop_launches"] for x in stats)
+    sx_ms = sum(x["ms_seed_xdrop_kernel"] for x in stats)
+    sx_cols = sum(x["xdrop_columns"] for x in stats)
+    yd_ops_s = YDROP_OPS_PER_CELL * yd_cells / (yd_ms / 1e3) if yd_ms > 0 else 0.0
+    sx_ops_s = XDROP_OPS_PER_COLUMN * sx_cols / (sx_ms / 1e3) if sx_ms > 0 else 0.0
+    dominant = "ydrop" if yd_ms >= sx_ms else "seed_xdrop"
+    if dominant == "ydrop":
+        achieved = yd_ops_s / 1e12
+        note = (f"k_ydrop_wave: {YDROP_OPS_PER_CELL} int32 ops per DP cell x {yd_cells / max(yd_launches, 1):.3g} "
+                f"cells per launch / {yd_ms / max(yd_launches, 1):.3f} ms average launch")
+    else:
+        achieved = sx_ops_s / 1e12
+        note = (f"k_seed_xdrop: {XDROP_OPS_PER_COLUMN} int32 ops per scanned column x "
+                f"{sx_cols / max(len(stats), 1):.3g} columns per launch / {sx_ms / max(len(stats), 1):.3f} ms")
+    peak = INT32_VALU_PEAK_OPS / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved, 4), peak=round(peak, 2), unit="Tops/s (int32 lane-ops)",
+                    frac=round(achieved / peak, 5), traffic=None, kernel=dominant, note=note)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(T, Q, sc, args.cpu_sample_bp)
+
+    line = {
+        "metric": "HSPs/s + gapped GCUPS, 1 MI355X; learned-binned vs plain batch, bit-exact",
+        "value": round(hsps_per_s, 2),
+        "unit": "HSPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": desc, "schedule": "plain" if args.schedule == 0 else "persistent",
+                   "round_k": args.round_k or 256},
+        "gapped_gcups": round(s["cells"] / (s["ms_extend"] / 1e3) / 1e9, 3) if s["ms_extend"] > 0 else None,
+        "gapped_gcups_kernel": round(yd_cells / (yd_ms / 1e3) / 1e9, 3) if yd_ms > 0 else None,
+        "seed_hits_per_s": round(s["seed_hits"] / (s["ms_seed_xdrop"] / 1e3), 1) if s["ms_seed_xdrop"] > 0 else None,
+        "alignments_per_s": round(s["committed"] / (ms_step / 1e3), 2),
+        "counts": {k: s[k] for k in ("seed_hits", "hsps_raw", "hsps", "rounds", "extensions", "committed",
+                                     "shadow", "cells", "overflow_reruns", "xdrop_columns")},
+        "stage_ms": {k: round(s[k], 2) for k in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total",
+                                                 "ms_ydrop_kernel", "ms_seed_xdrop_kernel")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

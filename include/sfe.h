@@ -27,8 +27,9 @@
  * - Ownership: contexts and indexes belong to the library until destroyed;
  *   inputs are borrowed for the duration of the call; outputs belong to the
  *   caller.
- * - Scores are int32.  A sequence longer than (2^30 - 1) / max|sub| bases,
- *   or longer than 2^32 - 64 bases, is SFE_ERANGE.
+ * - Scores are int32.  A call in which any ungapped or gapped score reaches
+ *   2^29 stops with SFE_ERANGE (this keeps every intermediate value inside
+ *   int32); so does a sequence longer than 2^32 - 64 bases.
  * - No call throws; on failure the status is returned and sfe_last_error()
  *   describes it.
  */
@@ -118,11 +119,24 @@ typedef struct {
 #define SFE_SCHED_PLAIN 0       /* one wavefront per anchor-half, one launch per batch */
 #define SFE_SCHED_PERSISTENT 1  /* persistent work-stealing launch over a cost-ordered queue */
 
+/* Speculation policies of sfe_align; all give identical results.
+ * PREFIX: each batch is the next round_k HSPs of a (query, strand) whose
+ *   anchors are not contained in a committed alignment (Alg. 3 as printed).
+ * DEFER:  the scan also passes over (defers) an HSP whose anchor lies on an M
+ *   column of an earlier extension still waiting for commit, or whose diagonal
+ *   is within 128 of an earlier HSP already in the batch; deferred HSPs are
+ *   decided in later batches.  Commit still walks the HSPs in order and stops
+ *   at the first one without an extension. */
+#define SFE_POLICY_DEFER 0
+#define SFE_POLICY_PREFIX 1
+
 typedef struct {
-    int32_t round_k;        /* speculative batch size K per (query, strand); <= 0 picks a default */
+    int32_t round_k;        /* per (query, strand) extensions per batch; <= 0 picks a default */
     int32_t schedule;       /* SFE_SCHED_* */
     int32_t strands;        /* bit 0 plus, bit 1 minus; 0 means both */
-    int32_t max_cells_per_lane; /* 0 = automatic; 4 or 16 forces the register band width */
+    int32_t max_cells_per_lane; /* 0 = automatic (6); 4, 6 or 8 rows per lane in the first band window */
+    int32_t policy;         /* SFE_POLICY_* */
+    int32_t pad;
     int64_t arena_bytes;    /* traceback pointer arena per batch; 0 = default */
 } sfe_align_opts;
 
@@ -133,10 +147,16 @@ typedef struct {
     int64_t rounds;             /* speculative batches (Alg. 3 rounds) */
     int64_t extensions;         /* gapped extensions computed (both halves = one) */
     int64_t committed;          /* alignments committed */
-    int64_t shadow;             /* extensions computed but not committed */
+    int64_t shadow;             /* extensions discarded at commit because their anchor was contained */
     int64_t cells;              /* DP cells of all computed extensions */
     int64_t overflow_reruns;    /* halves re-run with a wider band or a larger arena */
-    double ms_seed_xdrop, ms_hsp_set, ms_extend, ms_total;
+    int64_t xdrop_columns;      /* columns scored by the X-drop filter (seed span included) */
+    int64_t ydrop_launches;     /* launches of the gapped-extension kernel */
+    int64_t ydrop_kernel_cells; /* DP cells computed by those launches */
+    int64_t seed_xdrop_launches;/* launches of the fused seed + X-drop kernel */
+    double ms_seed_xdrop, ms_hsp_set, ms_extend, ms_total;   /* host wall clock per stage */
+    double ms_ydrop_kernel;     /* sum of HIP-event durations of the gapped-extension launches */
+    double ms_seed_xdrop_kernel;/* sum of HIP-event durations of the fused seed + X-drop launches */
 } sfe_stats;
 
 /* Context on `device` using `hip_stream` (a hipStream_t, or NULL for a

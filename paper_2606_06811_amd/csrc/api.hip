@@ -7,8 +7,10 @@
 #include <algorithm>
 #include <chrono>
 #include <functional>
+#include <memory>
 #include <tuple>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -74,10 +76,17 @@ struct sfe_ctx {
     DBuf units_d, chunks_d, qdesc_d;
     DBuf hsp_raw, hsp_pass, hsp_sorted;
     DBuf items_d, tasks_d, hres_d, ids_d, aln_d, runoff_d, runs_d, nruns_d, opsoff_d, ops_d, nops_d, ring_d;
-    DBuf arena_d, arena_head;
-    int64_t arena_bytes = 0;
+    // traceback arenas: arena 0 takes every batch; a half that finds its arena
+    // full is re-run into the next one (allocated twice as large on demand)
+    std::vector<std::unique_ptr<DBuf>> arenas;
+    DBuf arena_heads;
+    int64_t arena_bytes = 0;            // size of arena 0
     SeqSet qplus, qminus;
     std::vector<QueryDesc> qdesc;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // per-call kernel accounting (reset by sfe_align)
+    double ydrop_ms = 0, sx_ms = 0;
+    int64_t ydrop_launches = 0, ydrop_cells = 0, sx_launches = 0;
 };
 
 struct sfe_index {
@@ -109,6 +118,13 @@ void copy_in(sfe_ctx *c, void *dst_dev, const void *src, size_t n) {
     HIPCHK(hipMemcpyAsync(dst_dev, src, n, hipMemcpyDefault, c->stream));
 }
 void sync(sfe_ctx *c) { HIPCHK(hipStreamSynchronize(c->stream)); }
+
+// Elapsed time between the context's two events (both already complete).
+double event_ms(sfe_ctx *c) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    return (double)ms;
+}
 
 unsigned grid(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -208,13 +224,9 @@ int max_abs_sub(const ScoreDesc &d) {
     return m;
 }
 
-void check_range(const sfe_index *idx, const sfe_seq *q, int32_t nq, const ScoreDesc &d) {
-    int64_t m = max_abs_sub(d);
-    for (int32_t i = 0; i < nq; i++) {
-        int64_t L = std::min<int64_t>(q[i].length, idx->nt);
-        if (L * m >= (1LL << 30) - 1) fail(SFE_ERANGE, "alignment scores could leave the int32 range");
-    }
-}
+// Scores are int32 throughout; the kernels stop and report SFE_ERANGE as soon
+// as any score reaches 2^29, which keeps every intermediate value in range.
+void check_range(const sfe_index *, const sfe_seq *, int32_t, const ScoreDesc &) {}
 
 template <class T>
 void cub_exclusive_sum(sfe_ctx *c, const T *in, T *out, int64_t n) {
@@ -311,18 +323,30 @@ struct BatchResult {
     int64_t reruns = 0;
 };
 
+// Arena 0 of `bytes` (kept if already that large); arenas 1.. grow from it.
 void ensure_arena(sfe_ctx *c, int64_t bytes) {
-    if (c->arena_bytes >= bytes && c->arena_d.p) return;
-    c->arena_d.ensure((size_t)bytes);
+    if (c->arenas.empty()) c->arenas.emplace_back(new DBuf);
+    if (c->arena_bytes >= bytes && c->arenas[0]->p) return;
+    c->arenas[0]->ensure((size_t)bytes);
     c->arena_bytes = bytes;
-    c->arena_head.ensure(8);
+    c->arena_heads.ensure(8 * 32);
 }
 
 void set_arena(sfe_ctx *c, int64_t bytes) {
-    if (c->arena_bytes == bytes && c->arena_d.p) return;
-    c->arena_d.reset((size_t)bytes);
+    if (c->arena_bytes == bytes && !c->arenas.empty() && c->arenas[0]->p) return;
+    c->arenas.clear();
+    c->arenas.emplace_back(new DBuf);
+    c->arenas[0]->reset((size_t)bytes);
     c->arena_bytes = bytes;
-    c->arena_head.ensure(8);
+    c->arena_heads.ensure(8 * 32);
+}
+
+Arena arena_at(sfe_ctx *c, size_t ai) {
+    if (ai >= 32) fail(SFE_ENOMEM, "traceback arenas exhausted");
+    while (c->arenas.size() <= ai) c->arenas.emplace_back(new DBuf);
+    const int64_t bytes = c->arena_bytes << ai;
+    if (!c->arenas[ai]->p || (int64_t)c->arenas[ai]->n < bytes) c->arenas[ai]->ensure((size_t)bytes);
+    return Arena{c->arenas[ai]->as<uint8_t>(), (uint64_t)bytes, c->arena_heads.as<unsigned long long>() + ai};
 }
 
 void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &items, const ScoreDesc &sc,
@@ -337,52 +361,76 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     copy_in(c, items_d, items.data(), (size_t)n * sizeof(ExtItem));
     launch_make_tasks(items_d, n, c->units_d.as<UnitDesc>(), idx->nt, tasks, c->stream);
     SeqSetView T = idx->target.view(), Qp = c->qplus.view(), Qm = c->qminus.view();
+    bool perm = true;                   // every score fits in int8: scores come from packed row profiles
+    for (int a = 0; a < 5; a++)
+        for (int b = 0; b < 5; b++) perm = perm && sc.sub[a][b] >= -128 && sc.sub[a][b] <= 127;
     std::vector<HalfResult> hr(2 * n);
-    for (int attempt = 0;; attempt++) {
-        Arena ar{c->arena_d.as<uint8_t>(), (uint64_t)c->arena_bytes, c->arena_head.as<unsigned long long>()};
-        HIPCHK(hipMemsetAsync(c->arena_head.p, 0, 8, c->stream));
-        launch_ydrop(cells_per_lane, tasks, nullptr, 2 * n, T, Qp, Qm, sc, ar, hres, c->stream);
+    // Stages of a half: 0 the register window of cells_per_lane rows per lane,
+    // 1 the 8-rows-per-lane window, 2.. the workgroup kernel with a ring of
+    // 4096 * 4^(stage-2) rows.  A half whose band outgrows its stage moves to the
+    // next; a half whose arena fills up is re-run into the next arena.
+    HIPCHK(hipMemsetAsync(c->arena_heads.p, 0, 8 * 32, c->stream));
+    std::vector<int> stage(2 * n, cells_per_lane < 8 ? 0 : 1);
+    std::vector<int32_t> todo;
+    size_t ai = 0;
+    bool all = true;
+    for (;;) {
+        std::vector<int32_t> group, rest;
+        int sg = 1 << 20;
+        if (all) {
+            sg = stage[0];
+        } else {
+            for (int32_t h : todo) sg = std::min(sg, stage[h]);
+            for (int32_t h : todo) (stage[h] == sg ? group : rest).push_back(h);
+        }
+        Arena ar = arena_at(c, ai);
+        const int32_t *ids = nullptr;
+        int64_t cnt = 2 * n;
+        if (!all) {
+            int32_t *idd = (int32_t *)c->ids_d.ensure(group.size() * 4);
+            copy_in(c, idd, group.data(), group.size() * 4);
+            ids = idd;
+            cnt = (int64_t)group.size();
+            out.reruns += cnt;
+        }
+        const bool timed = sg <= 1;
+        if (timed) HIPCHK(hipEventRecord(c->ev0, c->stream));
+        if (sg <= 1) {
+            launch_ydrop(sg == 0 ? cells_per_lane : 8, perm, tasks, ids, cnt, T, Qp, Qm, sc, ar, hres, c->stream);
+        } else {
+            const int32_t cap = 4096 << (2 * (sg - 2));
+            if (sg - 2 > 10) fail(SFE_EINTERNAL, "band width beyond 2^24 rows");
+            int32_t *ring = (int32_t *)c->ring_d.ensure((size_t)cnt * 7 * cap * 4);
+            launch_ydrop_ring(tasks, ids, cnt, T, Qp, Qm, sc, ar, ring, cap, hres, c->stream);
+        }
         HIPCHK(hipGetLastError());
+        if (timed) HIPCHK(hipEventRecord(c->ev1, c->stream));
         copy_out(c, hr.data(), hres, hr.size() * sizeof(HalfResult));
         sync(c);
-        // halves whose band outgrew the window: wider window, then the workgroup kernel
-        std::vector<int32_t> wide;
+        if (timed) {
+            c->ydrop_ms += event_ms(c);
+            c->ydrop_launches++;
+        }
+        std::vector<int32_t> next = rest;
         bool arena_full = false;
-        for (int64_t h = 0; h < 2 * n; h++) {
-            if (hr[h].status == HALF_WIDTH_OVERFLOW) wide.push_back((int32_t)h);
-            if (hr[h].status == HALF_ARENA_OVERFLOW) arena_full = true;
-        }
-        int32_t cap = 4096;
-        int stage = cells_per_lane <= 4 ? 0 : 1;
-        while (!wide.empty() && !arena_full) {
-            out.reruns += (int64_t)wide.size();
-            int32_t *ids = (int32_t *)c->ids_d.ensure(wide.size() * 4);
-            copy_in(c, ids, wide.data(), wide.size() * 4);
-            if (stage == 0) {
-                launch_ydrop(16, tasks, ids, (int64_t)wide.size(), T, Qp, Qm, sc, ar, hres, c->stream);
-                stage = 1;
-            } else {
-                int32_t *ring = (int32_t *)c->ring_d.ensure((size_t)wide.size() * 7 * cap * 4);
-                launch_ydrop_ring(tasks, ids, (int64_t)wide.size(), T, Qp, Qm, sc, ar, ring, cap, hres, c->stream);
-                cap *= 4;
+        auto check = [&](int32_t h) {
+            if (timed) c->ydrop_cells += (int64_t)hr[h].cells;
+            switch (hr[h].status) {
+            case HALF_OK: break;
+            case HALF_WIDTH_OVERFLOW: stage[h]++; next.push_back(h); break;
+            case HALF_ARENA_OVERFLOW: arena_full = true; next.push_back(h); break;
+            case HALF_SCORE_RANGE: fail(SFE_ERANGE, "a gapped score reached 2^29");
+            default: fail(SFE_EINTERNAL, "unknown half status");
             }
-            HIPCHK(hipGetLastError());
-            copy_out(c, hr.data(), hres, hr.size() * sizeof(HalfResult));
-            sync(c);
-            std::vector<int32_t> still;
-            for (int32_t h : wide) {
-                if (hr[h].status == HALF_WIDTH_OVERFLOW) still.push_back(h);
-                if (hr[h].status == HALF_ARENA_OVERFLOW) arena_full = true;
-            }
-            wide.swap(still);
-            if (cap > (1 << 26)) fail(SFE_EINTERNAL, "band width beyond 2^26 rows");
-        }
-        if (!arena_full) break;
-        if (attempt > 8) fail(SFE_ENOMEM, "traceback arena cannot hold one batch");
-        out.reruns += 2 * n;
-        ensure_arena(c, c->arena_bytes * 2);
+        };
+        if (all) for (int32_t h = 0; h < 2 * n; h++) check(h);
+        else for (int32_t h : group) check(h);
+        if (arena_full) ai++;
+        all = false;
+        todo.swap(next);
+        if (todo.empty()) break;
     }
-    Arena ar{c->arena_d.as<uint8_t>(), (uint64_t)c->arena_bytes, c->arena_head.as<unsigned long long>()};
+    Arena ar = arena_at(c, 0);
     sfe_aln *aln_d = (sfe_aln *)c->aln_d.ensure((size_t)n * sizeof(sfe_aln));
     launch_assemble(items_d, n, c->units_d.as<UnitDesc>(), hres, T, Qp, Qm, sc, aln_d, c->stream);
     copy_out(c, out.alns.data(), aln_d, (size_t)n * sizeof(sfe_aln));
@@ -439,6 +487,58 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         out.ops.insert(out.ops.end(), ops_all.begin() + ops_off[p], ops_all.begin() + ops_off[p] + nops[p]);
     }
 }
+
+// Bounding boxes of committed alignments of one unit, binned by target position.
+struct BoxGrid {
+    static const int SH = 14;
+    std::unordered_map<int64_t, std::vector<int32_t>> bins;
+    std::vector<sfe_aln> boxes;
+    void add(const sfe_aln &a) {
+        int32_t id = (int32_t)boxes.size();
+        boxes.push_back(a);
+        for (int64_t b = a.t_start >> SH; b <= ((int64_t)a.t_end - 1) >> SH; b++) bins[b].push_back(id);
+    }
+    bool inside(uint32_t t, uint32_t q) const {
+        auto it = bins.find((int64_t)t >> SH);
+        if (it == bins.end()) return false;
+        for (int32_t id : it->second) {
+            const sfe_aln &a = boxes[id];
+            if (a.t_start <= t && t < a.t_end && a.q_start <= q && q < a.q_end) return true;
+        }
+        return false;
+    }
+};
+
+// M runs of computed extensions of one unit, each tagged with the position of
+// its HSP in the walking order.
+struct PathIndex {
+    struct Run { uint32_t tb, te; size_t owner; };
+    std::unordered_map<int64_t, std::vector<Run>> diag;
+    void add(const sfe_aln &a, const uint32_t *ops, size_t owner) {
+        uint32_t t = a.t_start, q = a.q_start;
+        for (uint32_t x = 0; x < a.ops_len; x++) {
+            uint32_t len = ops[x] >> 2, op = ops[x] & 3u;
+            if (op == 0) {
+                diag[(int64_t)t - (int64_t)q].push_back(Run{t, t + len, owner});
+                t += len;
+                q += len;
+            } else if (op == 1) {
+                q += len;
+            } else {
+                t += len;
+            }
+        }
+    }
+    // (t, q) lies on an M column of an extension, still waiting for commit,
+    // whose HSP comes before `pos` (state[owner] == 2)
+    bool contains_before(uint32_t t, uint32_t q, size_t pos, const std::vector<uint8_t> &state) const {
+        auto it = diag.find((int64_t)t - (int64_t)q);
+        if (it == diag.end()) return false;
+        for (const Run &r : it->second)
+            if (r.owner < pos && r.tb <= t && t < r.te && state[r.owner] == 2) return true;
+        return false;
+    }
+};
 
 // Committed M columns of one (query, strand) unit, by diagonal t - q.
 struct SegList {
@@ -505,8 +605,10 @@ sfe_status sfe_ctx_create(int device, void *hip_stream, sfe_ctx **out) {
             c->own_stream = true;
         }
         HIPCHK(upload_encoding_table(c->stream));
+        HIPCHK(hipEventCreate(&c->ev0));
+        HIPCHK(hipEventCreate(&c->ev1));
         c->counters.ensure(64);
-        ensure_arena(c, (int64_t)1 << 30);
+        ensure_arena(c, (int64_t)8 << 30);
         sync(c);
     });
     if (st != SFE_OK) {
@@ -521,6 +623,8 @@ void sfe_ctx_destroy(sfe_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -630,9 +734,16 @@ sfe_status sfe_ungapped_xdrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *qu
         sfe_hit *hd = (sfe_hit *)c->tmp_e.ensure((size_t)n * sizeof(sfe_hit));
         copy_in(c, hd, hh.data(), (size_t)n * sizeof(sfe_hit));
         sfe_hsp *raw = (sfe_hsp *)c->hsp_raw.ensure((size_t)n * sizeof(sfe_hsp));
+        int *err = (int *)c->counters.as<char>() + 8;
+        HIPCHK(hipMemsetAsync(err, 0, 4, c->stream));
         k_xdrop_raw<<<grid(n, 256), 256, 0, c->stream>>>(hd, n, c->qdesc_d.as<QueryDesc>(), nq, ix->target.view(), 0,
-                                                        ix->nt, c->qplus.view(), c->qminus.view(), sc, ix->sd.span, raw);
+                                                        ix->nt, c->qplus.view(), c->qminus.view(), sc, ix->sd.span, raw,
+                                                        err);
         HIPCHK(hipGetLastError());
+        int herr = 0;
+        HIPCHK(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        if (herr) fail(SFE_ERANGE, "an ungapped score reached 2^29");
         if (flags & SFE_XDROP_RAW) {
             *n_hsps = n;
             if (n > cap) fail(SFE_ECAPACITY, "hsp buffer too small");
@@ -682,7 +793,7 @@ sfe_status sfe_gapped_ydrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *quer
             items[x] = ExtItem{h.t0 + off, h.q0 + off, (int32_t)(2 * h.query_id + h.strand), 0};
         }
         BatchResult br;
-        run_batch(c, ix, items, sc, 4, br);
+        run_batch(c, ix, items, sc, 6, br);
         int64_t need = (int64_t)br.ops.size();
         *n_ops = need;
         if (need > ops_cap) fail(SFE_ECAPACITY, "ops buffer too small");
@@ -704,10 +815,12 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         if (opts) o = *opts;
         int strands = o.strands ? o.strands : 3;
         if (strands < 1 || strands > 3) fail(SFE_EINVAL, "strands must be 1, 2 or 3");
-        const int64_t K = o.round_k > 0 ? o.round_k : 256;
-        const int cpl = o.max_cells_per_lane == 16 ? 16 : 4;
+        const int64_t K = o.round_k > 0 ? o.round_k : (o.policy == SFE_POLICY_DEFER ? (1 << 20) : 256);
+        const int cpl = o.max_cells_per_lane > 0 ? std::min(8, std::max(4, o.max_cells_per_lane)) : 6;
         if (o.arena_bytes > 0) set_arena(c, std::max<int64_t>(o.arena_bytes, 2 * ARENA_PAGE));
         sfe_stats st{};
+        c->ydrop_ms = c->sx_ms = 0;
+        c->ydrop_launches = c->ydrop_cells = c->sx_launches = 0;
         QueryLayout L;
         upload_queries(c, queries, nq, strands, ix->sd.span, L);
         check_range(ix, queries, nq, sc);
@@ -720,23 +833,32 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             for (;;) {
                 sfe_hsp *raw = (sfe_hsp *)c->hsp_raw.ensure(capraw * sizeof(sfe_hsp));
                 unsigned long long *cnt = c->counters.as<unsigned long long>();
-                HIPCHK(hipMemsetAsync(cnt, 0, 16, c->stream));
+                HIPCHK(hipMemsetAsync(cnt, 0, 32, c->stream));
+                HIPCHK(hipEventRecord(c->ev0, c->stream));
                 k_seed_xdrop<<<(unsigned)nch, 256, 0, c->stream>>>(c->units_d.as<UnitDesc>(), c->chunks_d.as<Chunk>(),
                                                                   ix->target.view(), 0, ix->nt, c->qplus.view(),
                                                                   c->qminus.view(), ix->offsets.as<uint32_t>(),
                                                                   ix->pos.as<uint32_t>(), ix->sd, sc, raw, capraw, cnt);
                 HIPCHK(hipGetLastError());
-                unsigned long long hc[2];
-                HIPCHK(hipMemcpyAsync(hc, cnt, 16, hipMemcpyDeviceToHost, c->stream));
+                HIPCHK(hipEventRecord(c->ev1, c->stream));
+                unsigned long long hc[4];
+                HIPCHK(hipMemcpyAsync(hc, cnt, 32, hipMemcpyDeviceToHost, c->stream));
                 sync(c);
+                if (hc[3]) fail(SFE_ERANGE, "an ungapped score reached 2^29");
+                c->sx_ms += event_ms(c);
+                c->sx_launches++;
                 st.seed_hits = (int64_t)hc[0];
                 nraw = (int64_t)hc[1];
+                st.xdrop_columns = (int64_t)hc[2];
                 if ((uint64_t)nraw <= capraw) break;
                 capraw = (uint64_t)nraw + nraw / 8 + 1024;
             }
         }
         st.hsps_raw = nraw;
         const double t2 = now_ms();
+        if (getenv("SFE_PROGRESS"))
+            fprintf(stderr, "[sfe] seeds + x-drop: %lld hits, %lld passing, %.1f ms\n", (long long)st.seed_hits,
+                    (long long)nraw, t2 - t1);
         int64_t nh = hsp_set(c, c->hsp_raw.as<sfe_hsp>(), nraw);
         st.hsps = nh;
         std::vector<sfe_hsp> hs((size_t)nh);
@@ -746,50 +868,142 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         // --- Alg. 3 rounds ------------------------------------------------------------
         std::vector<int32_t> unit_of(2 * (size_t)std::max(nq, 1), -1);
         for (size_t u = 0; u < L.units.size(); u++) unit_of[2 * L.units[u].query_id + L.units[u].strand] = (int32_t)u;
-        std::vector<std::vector<int64_t>> per_unit(L.units.size());
+        const size_t NU = L.units.size();
+        std::vector<std::vector<int64_t>> per_unit(NU);
         for (int64_t x = 0; x < nh; x++) per_unit[unit_of[2 * hs[x].query_id + hs[x].strand]].push_back(x);
-        std::vector<size_t> cursor(L.units.size(), 0);
-        std::vector<SegList> seg(L.units.size());
+        // per HSP state: 0 unresolved, 1 skipped (contained), 2 extension pending, 3 resolved, 4 in this batch
+        std::vector<std::vector<uint8_t>> state(NU);
+        std::vector<std::unordered_map<size_t, std::pair<sfe_aln, std::vector<uint32_t>>>> pending(NU);
+        std::vector<std::vector<size_t>> open(NU);               // positions in state 0, ascending
+        for (size_t u = 0; u < NU; u++) {
+            state[u].assign(per_unit[u].size(), 0);
+            open[u].resize(per_unit[u].size());
+            for (size_t p = 0; p < per_unit[u].size(); p++) open[u][p] = p;
+        }
+        std::vector<size_t> cursor(NU, 0);
+        std::vector<SegList> seg(NU);
+        std::vector<BoxGrid> boxes(NU);
+        std::vector<PathIndex> paths(NU);                        // M runs of every passing extension computed
         std::vector<sfe_aln> committed;
         std::vector<uint32_t> cops;
         std::vector<ExtItem> items;
-        std::vector<int32_t> item_unit;
+        std::vector<std::pair<int32_t, size_t>> item_ref;
         BatchResult br;
+        const bool defer = o.policy == SFE_POLICY_DEFER;
+        const bool progress = getenv("SFE_PROGRESS") != nullptr;
+        const int64_t DB = 128;                                   // diagonal band of the nearness rule
+        auto anchor_of = [&](const sfe_hsp &h, uint32_t &ta, uint32_t &qa) {
+            uint32_t off = (h.len - 1) / 2;
+            ta = h.t0 + off;
+            qa = h.q0 + off;
+        };
+        double host_ms = 0;
         for (;;) {
+            const double th = now_ms();
             items.clear();
-            item_unit.clear();
-            for (size_t u = 0; u < L.units.size(); u++) {         // phase 1: serial scan per unit
-                int64_t taken = 0;
+            item_ref.clear();
+            for (size_t u = 0; u < NU; u++) {                      // phase 1: serial scan per unit
                 auto &lst = per_unit[u];
-                while (taken < K && cursor[u] < lst.size()) {
-                    const sfe_hsp &h = hs[lst[cursor[u]++]];
-                    uint32_t off = (h.len - 1) / 2;
-                    uint32_t ta = h.t0 + off, qa = h.q0 + off;
-                    if (seg[u].contains(ta, qa)) continue;
+                auto &stt = state[u];
+                int64_t taken = 0;
+                std::unordered_map<int64_t, std::vector<int64_t>> near;   // diagonal bucket -> selected diagonals
+                std::vector<size_t> still;
+                still.reserve(open[u].size());
+                size_t q = 0;
+                for (; q < open[u].size() && taken < K; q++) {
+                    const size_t p = open[u][q];
+                    if (stt[p] != 0) continue;
+                    uint32_t ta, qa;
+                    anchor_of(hs[lst[p]], ta, qa);
+                    if (seg[u].contains(ta, qa)) { stt[p] = 1; continue; }
+                    if (defer) {
+                        // on the path of an earlier extension that may still commit: wait for it
+                        if (paths[u].contains_before(ta, qa, p, stt)) { still.push_back(p); continue; }
+                        // inside a committed alignment but off its path: such HSPs are extended
+                        // side by side (each may start a separate alignment of the region)
+                        const bool known_region = boxes[u].inside(ta, qa);
+                        const int64_t d = (int64_t)ta - (int64_t)qa;
+                        const int64_t b = d >= 0 ? d / DB : -((-d + DB - 1) / DB);
+                        bool close = false;
+                        for (int64_t bb = b - 1; bb <= b + 1 && !close; bb++) {
+                            auto it = near.find(bb);
+                            if (it == near.end()) continue;
+                            for (int64_t dd : it->second)
+                                if (std::llabs(dd - d) <= DB) { close = true; break; }
+                        }
+                        if (close && !known_region) { still.push_back(p); continue; }   // likely the same region
+                        near[b].push_back(d);
+                    }
                     items.push_back(ExtItem{ta, qa, (int32_t)u, 0});
-                    item_unit.push_back((int32_t)u);
+                    item_ref.push_back({(int32_t)u, p});
+                    stt[p] = 4;
                     taken++;
                 }
+                for (; q < open[u].size(); q++)
+                    if (stt[open[u][q]] == 0) still.push_back(open[u][q]);
+                open[u].swap(still);
             }
+            host_ms += now_ms() - th;
             if (items.empty()) break;
             st.rounds++;
+            const double tr = now_ms();
             run_batch(c, ix, items, sc, cpl, br);                 // phase 2: speculative extensions
+            if (progress)
+                fprintf(stderr, "[sfe] batch %lld: %zu extensions, %.1f ms, %zu committed so far\n",
+                        (long long)st.rounds, items.size(), now_ms() - tr, committed.size());
+            const double th2 = now_ms();
             st.overflow_reruns += br.reruns;
             st.extensions += (int64_t)items.size();
-            for (size_t x = 0; x < items.size(); x++) {          // phase 3: serial commit
+            for (size_t x = 0; x < items.size(); x++) {
                 const sfe_aln &a = br.alns[x];
+                const int32_t u = item_ref[x].first;
+                const size_t p = item_ref[x].second;
                 st.cells += (int64_t)a.cells;
-                SegList &sl = seg[item_unit[x]];
-                if (sl.contains(a.anchor_t, a.anchor_q) || !(a.flags & SFE_ALN_PASSED)) continue;
-                sfe_aln k = a;
-                k.ops_offset = cops.size();
-                cops.insert(cops.end(), br.ops.begin() + a.ops_offset, br.ops.begin() + a.ops_offset + a.ops_len);
-                sl.add(k, cops.data() + k.ops_offset);
-                committed.push_back(k);
+                auto &pe = pending[u][p];
+                pe.first = a;
+                pe.second.assign(br.ops.begin() + (a.flags & SFE_ALN_PASSED ? a.ops_offset : 0),
+                                 br.ops.begin() + (a.flags & SFE_ALN_PASSED ? a.ops_offset + a.ops_len : 0));
+                pe.first.ops_offset = 0;
+                if (defer && (a.flags & SFE_ALN_PASSED)) paths[u].add(pe.first, pe.second.data(), p);
+                state[u][p] = 2;
             }
+            for (size_t u = 0; u < NU; u++) {                      // phase 3: serial commit, in order
+                auto &lst = per_unit[u];
+                auto &stt = state[u];
+                size_t &cur = cursor[u];
+                while (cur < lst.size()) {
+                    const size_t p = cur;
+                    if (stt[p] == 1 || stt[p] == 3) { cur++; continue; }
+                    if (stt[p] == 2) {
+                        auto it = pending[u].find(p);
+                        const sfe_aln &a = it->second.first;
+                        if (seg[u].contains(a.anchor_t, a.anchor_q)) {
+                            st.shadow++;
+                        } else if (a.flags & SFE_ALN_PASSED) {
+                            sfe_aln k = a;
+                            k.ops_offset = cops.size();
+                            cops.insert(cops.end(), it->second.second.begin(), it->second.second.end());
+                            seg[u].add(k, cops.data() + k.ops_offset);
+                            if (defer) boxes[u].add(k);
+                            committed.push_back(k);
+                        }
+                        pending[u].erase(it);
+                        stt[p] = 3;
+                        cur++;
+                        continue;
+                    }
+                    uint32_t ta, qa;
+                    anchor_of(hs[lst[p]], ta, qa);
+                    if (seg[u].contains(ta, qa)) { stt[p] = 1; cur++; continue; }
+                    break;                                          // needs an extension first
+                }
+            }
+            host_ms += now_ms() - th2;
         }
+        if (progress) fprintf(stderr, "[sfe] host scan/commit time %.1f ms\n", host_ms);
+        for (size_t u = 0; u < NU; u++)
+            if (!pending[u].empty() || cursor[u] != per_unit[u].size()) fail(SFE_EINTERNAL, "commit did not finish");
         st.committed = (int64_t)committed.size();
-        st.shadow = st.extensions - st.committed;
         const double t4 = now_ms();
         // --- output in (query, strand, t_start, q_start, t_end, q_end, anchor) order ---
         std::vector<int64_t> order(committed.size());
@@ -807,6 +1021,11 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             st.ms_hsp_set = t3 - t2;
             st.ms_extend = t4 - t3;
             st.ms_total = now_ms() - t0;
+            st.ydrop_launches = c->ydrop_launches;
+            st.ydrop_kernel_cells = c->ydrop_cells;
+            st.seed_xdrop_launches = c->sx_launches;
+            st.ms_ydrop_kernel = c->ydrop_ms;
+            st.ms_seed_xdrop_kernel = c->sx_ms;
             *stats = st;
         }
         if (*n_alns > cap || *n_ops > ops_cap) fail(SFE_ECAPACITY, "alignment or ops buffer too small");

@@ -88,203 +88,316 @@ void launch_make_tasks(const ExtItem *items, int64_t n, const UnitDesc *units, i
 // by one thread of a workgroup)
 // ---------------------------------------------------------------------------
 struct PageCursor {
-    uint64_t page;      // arena offset of the current allocation, ~0 if none
-    uint32_t fill;      // bytes used in it
-    uint32_t size;      // bytes in it
+    uint64_t page;      // device address of the current allocation, ~0 if none
+    uint32_t fill;      // bytes used by the header and records
+    uint32_t size;      // bytes in the allocation
+    uint32_t nrec;      // records in it (their index entries fill it from the end)
 };
 
-// Makes room for `need` bytes; returns false when the arena is exhausted.
-// Called by one thread (the caller broadcasts the cursor).
-__device__ __forceinline__ bool arena_reserve_1t(Arena &ar, PageCursor &pc, uint32_t need) {
-    if (pc.page != ~0ull && pc.fill + need <= pc.size) return true;
-    uint32_t pages = (need + ARENA_HDR + ARENA_PAGE - 1) / ARENA_PAGE;
+// Makes room for a record of `need` bytes for antidiagonal k (plus its index
+// entry); returns false when the arena is exhausted.  Called by one thread.
+__device__ __forceinline__ bool arena_reserve_1t(Arena &ar, PageCursor &pc, uint32_t need, int64_t k) {
+    if (pc.page != ~0ull && pc.fill + need + 4 * (pc.nrec + 1) <= pc.size) return true;
+    uint32_t pages = (need + ARENA_HDR + 4 + ARENA_PAGE - 1) / ARENA_PAGE;
     unsigned long long off = atomicAdd(ar.head, (unsigned long long)pages * ARENA_PAGE);
     if (off + (unsigned long long)pages * ARENA_PAGE > ar.bytes) return false;
     uint32_t *hdr = (uint32_t *)(ar.base + off);
     uint64_t prev = pc.page;
     hdr[0] = (uint32_t)prev;
     hdr[1] = (uint32_t)(prev >> 32);
-    hdr[2] = pc.fill;
+    hdr[2] = (uint32_t)k;
     hdr[3] = pages;
-    pc.page = off;
+    pc.page = (uint64_t)(ar.base + off);
     pc.fill = ARENA_HDR;
     pc.size = pages * ARENA_PAGE;
+    pc.nrec = 0;
     return true;
 }
 
 // ---------------------------------------------------------------------------
 // Wave kernel
 // ---------------------------------------------------------------------------
-template <int C>
+// Cross-lane helpers (DPP): lane l receives lane l-1 (shr) or l+1 (shl); the
+// lane without a source keeps `old`.
+__device__ __forceinline__ int dpp_shr1(int old, int src) {
+    return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_shl1(int old, int src) {
+    return __builtin_amdgcn_update_dpp(old, src, 0x130, 0xf, 0xf, false);
+}
+// Maximum over the wave (uniform result): in-row shifts, then the four row maxima.
+__device__ __forceinline__ int wave_max_dpp(int v) {
+    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));
+    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));
+    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));
+    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));
+    int a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
+    int c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
+    return imax(imax(a, b), imax(c, d));
+}
+
+#define ROW_LIMIT (1 << 30)       // antidiagonals beyond this stop the half with HALF_SCORE_RANGE
+#define RING 2048                 // sequence codes staged in LDS per side
+#define RING_CHUNK 512            // codes loaded per refill
+
+// Substitution scores.  PERM: every entry fits in int8, a row carries the
+// packed scores of its target base against A, C, G, T (lo) and N (hi), and a
+// query code travels as a v_perm selector picking its byte into bits 24..31.
+// Otherwise rows carry the target code * 8 and the score is read from LDS.
+template <bool PERM> struct Scorer;
+template <> struct Scorer<true> {
+    static __device__ __forceinline__ int bsel(int code) { return (code << 24) | 0x000c0c0c; }
+    static __device__ __forceinline__ int score(int plo, int phi, int bsel, const int *) {
+        return (int)__builtin_amdgcn_perm((uint32_t)phi, (uint32_t)plo, (uint32_t)bsel) >> 24;
+    }
+};
+template <> struct Scorer<false> {
+    static __device__ __forceinline__ int bsel(int code) { return code; }
+    static __device__ __forceinline__ int score(int plo, int, int bsel, const int *sub) { return sub[plo + bsel]; }
+};
+
+// Loads codes of positions [from, from + RING_CHUNK) of one side of a half into
+// its LDS ring (index & (RING - 1)); positions outside [0, n) read as N.
+__device__ __forceinline__ void ring_fill(uint8_t *ring, const SeqSetView &S, int64_t p0, int64_t dir, int64_t n,
+                                          int64_t from, int lane) {
+#pragma unroll 4
+    for (int x = lane; x < RING_CHUNK; x += 64) {
+        const int64_t j = from + x;
+        int c = 4;
+        if (j >= 0 && j < n) c = base_code(S, p0 + dir * j);
+        ring[j & (RING - 1)] = (uint8_t)c;
+    }
+    __syncthreads();
+}
+
+template <int C, bool PERM>
 __global__ void __launch_bounds__(64) k_ydrop_wave(const HalfTask *__restrict__ tasks, const int32_t *__restrict__ ids,
                                                    SeqSetView T, SeqSetView Qp, SeqSetView Qm, ScoreDesc sc,
                                                    Arena ar, HalfResult *__restrict__ res) {
+    static_assert(C <= 8, "one 32-bit record word per lane");
+    typedef Scorer<PERM> S;
     __shared__ int sub[40];
+    __shared__ int prof[2][8];        // PERM: packed row profiles per target code
+    __shared__ uint8_t aring[RING], bring[RING];
     const int lane = threadIdx.x;
     if (lane < 40) sub[lane] = (lane & 7) < 5 ? sc.sub[lane >> 3][lane & 7] : 0;
-    __syncthreads();
+    if (lane < 5) {
+        uint32_t lo = 0;
+        for (int b = 0; b < 4; b++) lo |= ((uint32_t)sc.sub[lane][b] & 0xffu) << (8 * b);
+        prof[0][lane] = (int)lo;
+        prof[1][lane] = (int)((uint32_t)sc.sub[lane][4] & 0xffu);
+    }
     const int64_t tid = ids ? ids[blockIdx.x] : blockIdx.x;
     const HalfTask tk = tasks[tid];
     const SeqSetView Q = tk.qset ? Qm : Qp;
     const int e = sc.gap_extend, oe = sc.gap_open + sc.gap_extend, Y = sc.ydrop;
     const int64_t nA = tk.nA, nB = tk.nB;
+    const int64_t kmax = nA + nB;
+    // A index i-1 of row i is staged in aring; B index j in bring
+    int64_t a_hi = 0, b_hi = 0;       // first index not yet staged
+    while (a_hi < 64 * C + 64) { ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane); a_hi += RING_CHUNK; }
+    while (b_hi < 128) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
+    auto acode = [&](int64_t ia) { return ia < 0 ? 4 : (int)aring[ia & (RING - 1)]; };          // A(ia)
+    auto bcode = [&](int64_t jb) {      // B(jb); indices that left the ring are read from memory
+        if (jb < 0) return 4;
+        if (jb < b_hi - RING) return codeB(Q, tk, jb);
+        return (int)bring[jb & (RING - 1)];
+    };
+    auto plo_of = [&](int a) { return PERM ? prof[0][a] : a * 8; };
+    auto phi_of = [&](int a) { return PERM ? prof[1][a] : 0; };
 
-    int H1[C], H2[C], E1[C], F1[C], A8[C], Bc[C];
-    int64_t base = 0;
+    // rows base + lane*C + r
+    int H1[C], H2[C], E1[C], F1[C], Plo[C], Phi[C], Bs[C];
+    int base = 0;
 #pragma unroll
     for (int r = 0; r < C; r++) {
-        int64_t i = (int64_t)lane * C + r;
+        const int i = lane * C + r;
         H1[r] = (i == 0) ? 0 : NEG;
         H2[r] = NEG;
         E1[r] = NEG;
         F1[r] = NEG;
-        A8[r] = (i >= 1 ? codeA(T, tk, i - 1) : 4) * 8;
-        Bc[r] = codeB(Q, tk, 1 - i - 1);
+        const int a = acode(i - 1);
+        Plo[r] = plo_of(a);
+        Phi[r] = phi_of(a);
+        Bs[r] = S::bsel(i == 0 ? bcode(0) : 4);
     }
-    int best = 0;
-    int64_t bi = 0, bj = 0;
+    int best = 0, bi = 0, bj = 0;
     uint64_t cells = 1;
-    int64_t lmin1 = 0, lmax1 = 0;           // live rows of antidiagonal k-1 (lmin > lmax: none)
-    int64_t lmin2 = 1, lmax2 = 0;           // live rows of antidiagonal k-2
-    PageCursor pc;
-    pc.page = ~0ull; pc.fill = 0; pc.size = 0;
+    int lmin1 = 0, lmax1 = 0;            // live rows of antidiagonal k-1 (lmin > lmax: none)
+    int lmin2 = 1, lmax2 = 0;            // live rows of antidiagonal k-2
+    uint64_t pg = ~0ull;                 // arena cursor (uniform)
+    uint32_t fill = 0, psize = 0, nrec = 0, rec_off = 0;
     uint64_t tb_page = ~0ull;
     uint32_t tb_end = 0;
     int status = HALF_OK;
-    int64_t k = 1;
-    const int64_t kmax = nA + nB;
-    for (; k <= kmax; k++) {
+    int k = 1;
+    for (; (int64_t)k <= kmax; k++) {
+        if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
         // candidate rows of antidiagonal k
-        int64_t lo = INT64_MAX, hi = INT64_MIN;
+        int lo = 0x7fffffff, hi = -1;
         if (lmin1 <= lmax1) { lo = lmin1; hi = lmax1 + 1; }
         if (lmin2 <= lmax2) { lo = min(lo, lmin2 + 1); hi = max(hi, lmax2 + 1); }
-        const int64_t clo = max((int64_t)0, k - nB), chi = min(nA, k);
-        bool nonempty = false;
-        if (lo != INT64_MAX) {
-            lo = max(lo, clo);
-            hi = min(hi, chi);
-            nonempty = lo <= hi;
-        }
+        const int clo = (int)max((int64_t)0, (int64_t)k - nB);
+        const int chi = (int)min(nA, (int64_t)k);
+        lo = max(lo, clo);
+        hi = min(hi, chi);
+        const bool nonempty = lo <= hi;
         if (nonempty) {
             // slide the window: rows below lo-1 are never read again
-            int64_t s = (lo - 1 - base) / C;
-            if (s > 0) {
-                const int sl = (int)min(s, (int64_t)64);
-#pragma unroll
-                for (int r = 0; r < C; r++) {
-                    H1[r] = __shfl(H1[r], lane + sl, 64);
-                    H2[r] = __shfl(H2[r], lane + sl, 64);
-                    E1[r] = __shfl(E1[r], lane + sl, 64);
-                    F1[r] = __shfl(F1[r], lane + sl, 64);
-                    A8[r] = __shfl(A8[r], lane + sl, 64);
-                    Bc[r] = __shfl(Bc[r], lane + sl, 64);
+            const int s = (lo - 1 - base) / C;
+            if (s >= 1) {
+                while (a_hi < (int64_t)base + (s + 64) * C + 64) {
+                    ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane);
+                    a_hi += RING_CHUNK;
                 }
-                base += s * C;
-                if (lane + sl >= 64) {
+                if (s == 1) {
 #pragma unroll
                     for (int r = 0; r < C; r++) {
-                        int64_t i = base + (int64_t)lane * C + r;
-                        H1[r] = NEG; H2[r] = NEG; E1[r] = NEG; F1[r] = NEG;
-                        A8[r] = codeA(T, tk, i - 1) * 8;
-                        Bc[r] = codeB(Q, tk, k - i - 1);
+                        const int i_new = base + 64 * C + r;        // row entering lane 63
+                        const int a = acode(i_new - 1);
+                        const int fb = S::bsel(bcode((int64_t)k - i_new - 1));
+                        H1[r] = dpp_shl1(NEG, H1[r]);
+                        H2[r] = dpp_shl1(NEG, H2[r]);
+                        E1[r] = dpp_shl1(NEG, E1[r]);
+                        F1[r] = dpp_shl1(NEG, F1[r]);
+                        Plo[r] = dpp_shl1(plo_of(a), Plo[r]);
+                        Phi[r] = dpp_shl1(phi_of(a), Phi[r]);
+                        Bs[r] = dpp_shl1(fb, Bs[r]);
+                    }
+                } else {
+                    const int sl = min(s, 64);
+                    const int src = (lane + sl) & 63;
+                    const bool from_next = lane + sl >= 64;
+#pragma unroll
+                    for (int r = 0; r < C; r++) {
+                        const int i_new = base + s * C + lane * C + r;
+                        const int h1 = __shfl(H1[r], src, 64), h2 = __shfl(H2[r], src, 64);
+                        const int e1 = __shfl(E1[r], src, 64), f1 = __shfl(F1[r], src, 64);
+                        const int pl = __shfl(Plo[r], src, 64), ph = __shfl(Phi[r], src, 64);
+                        const int bs = __shfl(Bs[r], src, 64);
+                        const int a = acode(i_new - 1);
+                        H1[r] = from_next ? NEG : h1;
+                        H2[r] = from_next ? NEG : h2;
+                        E1[r] = from_next ? NEG : e1;
+                        F1[r] = from_next ? NEG : f1;
+                        Plo[r] = from_next ? plo_of(a) : pl;
+                        Phi[r] = from_next ? phi_of(a) : ph;
+                        Bs[r] = from_next ? S::bsel(bcode((int64_t)k - i_new - 1)) : bs;
                     }
                 }
+                base += s * C;
             }
             if (hi > base + 64 * C - 1) { status = HALF_WIDTH_OVERFLOW; break; }
         }
         const int thr = best - Y;
-        // values of row i-1 for each lane's first row
-        int upH = __shfl_up(H1[C - 1], 1, 64);
-        int upF = __shfl_up(F1[C - 1], 1, 64);
-        int upD = __shfl_up(H2[C - 1], 1, 64);
-        if (lane == 0) { upH = NEG; upF = NEG; upD = NEG; }
+        const int upH = dpp_shr1(NEG, H1[C - 1]);
+        const int upF = dpp_shr1(NEG, F1[C - 1]);
+        const int upD = dpp_shr1(NEG, H2[C - 1]);
         int Hn[C], En[C], Fn[C];
-        typedef typename std::conditional<(C > 8), uint64_t, uint32_t>::type NibT;   // 4 bits per row
-        NibT nib = 0;
+        uint32_t nib = 0;
         int lmax = NEG;
-        int64_t larg = 0, lfirst = INT64_MAX, llast = -1;
+        int fr = 0x7fffffff, lr = -1;    // first and last live row (relative to base)
+        // rows past the end of A, or whose column is past the end of B, are outside
+        // the matrix; rows above the antidiagonal need no mask (their neighbours are never live)
+        auto cell_pass = [&](auto edge_tag) {
+            constexpr bool EDGE = decltype(edge_tag)::value;
+            const int i0 = base + lane * C;
 #pragma unroll
-        for (int r = 0; r < C; r++) {
-            const int64_t i = base + (int64_t)lane * C + r;
-            const int Hu = r ? H1[r - 1] : upH;
-            const int Fu = r ? F1[r - 1] : upF;
-            const int Hd = r ? H2[r - 1] : upD;
-            const int hlo = H1[r] - oe, ele = E1[r] - e;
-            const int huo = Hu - oe, fue = Fu - e;
-            const int E = imax3(hlo, ele, NEG);
-            const int F = imax3(huo, fue, NEG);
-            const int G = Hd + sub[A8[r] + Bc[r]];
-            const int H = imax3(G, E, F);
-            const bool v = i >= clo && i <= chi;
-            const bool live = v && H >= thr;
-            Hn[r] = live ? H : NEG;
-            En[r] = v ? E : NEG;
-            Fn[r] = v ? F : NEG;
-            NibT code = (H == G ? 0u : (H == E ? 1u : 2u)) | (hlo >= ele ? 4u : 0u) | (huo >= fue ? 8u : 0u);
-            nib |= code << (4 * r);
-            if (live) {
-                if (H > lmax) { lmax = H; larg = i; }
-                if (lfirst == INT64_MAX) lfirst = i;
-                llast = i;
+            for (int r = 0; r < C; r++) {
+                const int Hu = r ? H1[r - 1] : upH;
+                const int Fu = r ? F1[r - 1] : upF;
+                const int Hd = r ? H2[r - 1] : upD;
+                const int hlo = H1[r] - oe, ele = E1[r] - e;
+                const int huo = Hu - oe, fue = Fu - e;
+                const int E = imax3(hlo, ele, NEG);
+                const int F = imax3(huo, fue, NEG);
+                const int G = Hd + S::score(Plo[r], Phi[r], Bs[r], sub);
+                const int H = imax3(G, E, F);
+                bool live = H >= thr;
+                if (EDGE) {
+                    const bool v = (unsigned)(i0 + r - clo) <= (unsigned)(chi - clo);
+                    live = live && v;
+                    En[r] = v ? E : NEG;
+                    Fn[r] = v ? F : NEG;
+                } else {
+                    En[r] = E;
+                    Fn[r] = F;
+                }
+                Hn[r] = live ? H : NEG;
+                const uint64_t m = __ballot(live);
+                if (m) {
+                    fr = min(fr, __builtin_ctzll(m) * C + r);
+                    lr = max(lr, (63 - __builtin_clzll(m)) * C + r);
+                }
+                const uint32_t code = (H == G ? 0u : (H == E ? 1u : 2u)) | (hlo >= ele ? 4u : 0u) |
+                                      (huo >= fue ? 8u : 0u);
+                nib |= code << (4 * r);
+                lmax = imax(lmax, Hn[r]);
             }
-        }
-        // live rows of this antidiagonal
-        const uint64_t anylive = __ballot(llast >= 0);
-        int64_t lmin0 = 1, lmax0 = 0;
-        if (anylive) {
-            int fl = __ffsll((unsigned long long)anylive) - 1;
-            int ll = 63 - __clzll((unsigned long long)anylive);
-            lmin0 = __shfl(lfirst, fl, 64);
-            lmax0 = __shfl(llast, ll, 64);
-        }
-        // traceback record of this antidiagonal: rows of the lanes covering [lo, hi]
+        };
+        const bool edge = base < clo || (int64_t)base + 64 * C - 1 > nA;
+        if (edge) cell_pass(std::true_type());
+        else cell_pass(std::false_type());
+        int lmin0 = 1, lmax0 = 0;
+        if (lr >= 0) { lmin0 = base + fr; lmax0 = base + lr; }
+        // traceback record: rows of the lanes covering [lo, hi]
         {
-            int64_t l_lo = 0, l_hi = -1;
+            int l_lo = 0, l_hi = -1;
             if (nonempty) {
                 l_lo = (lo - base) / C;
                 l_hi = (hi - base) / C;
             }
-            const uint32_t n = (uint32_t)((l_hi - l_lo + 1) * C);
-            const uint32_t pbytes = rec_payload_bytes(n);
-            const uint32_t need = pbytes + 8;
-            bool ok = true;
-            if (lane == 0) ok = arena_reserve_1t(ar, pc, need);
-            ok = __shfl(ok ? 1 : 0, 0, 64) != 0;
-            pc.page = __shfl(pc.page, 0, 64);
-            pc.fill = __shfl(pc.fill, 0, 64);
-            pc.size = __shfl(pc.size, 0, 64);
-            if (!ok) { status = HALF_ARENA_OVERFLOW; break; }
-            uint8_t *rec = ar.base + pc.page + pc.fill;
-            if (lane >= l_lo && lane <= l_hi) {
-                uint8_t *dst = rec + (lane - l_lo) * (C / 2);
-                if (C == 4) {
-                    *(uint16_t *)dst = (uint16_t)nib;
-                } else {
-#pragma unroll
-                    for (int b = 0; b < C / 2; b++) dst[b] = (uint8_t)(nib >> (8 * b));
+            const uint32_t ng = (uint32_t)(l_hi - l_lo + 1);
+            const uint32_t need = 8 + 4 * ng;
+            if (pg == ~0ull || fill + need + 4 * (nrec + 1) > psize) {
+                const uint32_t pages = (need + ARENA_HDR + 4 + ARENA_PAGE - 1) / ARENA_PAGE;
+                unsigned long long off = 0;
+                if (lane == 0) off = atomicAdd(ar.head, (unsigned long long)pages * ARENA_PAGE);
+                const uint32_t olo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off);
+                const uint32_t ohi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(off >> 32));
+                off = ((unsigned long long)ohi << 32) | olo;
+                if (off + (unsigned long long)pages * ARENA_PAGE > ar.bytes) { status = HALF_ARENA_OVERFLOW; break; }
+                if (lane == 0) {
+                    uint32_t *hdr = (uint32_t *)(ar.base + off);
+                    hdr[0] = (uint32_t)pg;
+                    hdr[1] = (uint32_t)(pg >> 32);
+                    hdr[2] = (uint32_t)k;
+                    hdr[3] = pages;
                 }
+                pg = (uint64_t)(ar.base + off);
+                fill = ARENA_HDR;
+                psize = pages * ARENA_PAGE;
+                nrec = 0;
             }
+            uint32_t *rec = (uint32_t *)((uint8_t *)pg + fill);
+            if (lane >= l_lo && lane <= l_hi) rec[2 + lane - l_lo] = nib;
             if (lane == 0) {
-                uint32_t *ft = (uint32_t *)(rec + pbytes);
-                ft[0] = (uint32_t)(nonempty ? base + l_lo * C : 0);
-                ft[1] = n;
+                rec[0] = nonempty ? (uint32_t)(base + l_lo * C) : 0u;
+                rec[1] = rec_head_word(ng, C);
+                ((uint32_t *)((uint8_t *)pg + psize))[-(int)(nrec + 1)] = fill;
             }
-            pc.fill += need;
+            rec_off = fill;
+            fill += need;
+            nrec++;
             if (nonempty) cells += (uint64_t)(hi - lo + 1);
         }
         // best over this antidiagonal; end cell = smallest row reaching it
-        const int admax = wave_max(lmax);
+        const int admax = wave_max_dpp(lmax);
         if (admax > best) {
-            const uint64_t m = __ballot(lmax == admax);
-            const int fl = __ffsll((unsigned long long)m) - 1;
-            const int64_t row = __shfl(larg, fl, 64);
+            int row = 0x7fffffff;
+#pragma unroll
+            for (int r = 0; r < C; r++) {
+                const uint64_t m = __ballot(Hn[r] == admax);
+                if (m) row = min(row, __builtin_ctzll(m) * C + r);
+            }
             best = admax;
-            bi = row;
-            bj = k - row;
-            tb_page = pc.page;
-            tb_end = pc.fill;
+            bi = base + row;
+            bj = k - bi;
+            tb_page = pg;
+            tb_end = rec_off;
+            if (best >= SFE_SCORE_LIMIT) { status = HALF_SCORE_RANGE; break; }
         }
-        // advance
+        // advance to antidiagonal k+1
 #pragma unroll
         for (int r = 0; r < C; r++) {
             H2[r] = H1[r];
@@ -292,11 +405,15 @@ __global__ void __launch_bounds__(64) k_ydrop_wave(const HalfTask *__restrict__ 
             E1[r] = En[r];
             F1[r] = Fn[r];
         }
-        const int64_t bnew = k - base;       // B index of row `base` on antidiagonal k+1
-        int carry = __shfl_up(Bc[C - 1], 1, 64);
+        // query code entering row `base` on antidiagonal k+1: B(k - base)
+        const int64_t bnew = (int64_t)k - base;
+        while (b_hi < bnew + 64) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
+        {
+            const int carry = dpp_shr1(S::bsel(bcode(bnew)), Bs[C - 1]);
 #pragma unroll
-        for (int r = C - 1; r > 0; r--) Bc[r] = Bc[r - 1];
-        Bc[0] = lane == 0 ? codeB(Q, tk, bnew) : carry;
+            for (int r = C - 1; r > 0; r--) Bs[r] = Bs[r - 1];
+            Bs[0] = carry;
+        }
         const bool stop = (lmin0 > lmax0) && (lmin1 > lmax1);
         lmin2 = lmin1; lmax2 = lmax1;
         lmin1 = lmin0; lmax1 = lmax0;
@@ -305,24 +422,31 @@ __global__ void __launch_bounds__(64) k_ydrop_wave(const HalfTask *__restrict__ 
     if (lane == 0) {
         HalfResult o;
         o.best = best;
-        o.i_end = (int32_t)bi;
-        o.j_end = (int32_t)bj;
+        o.i_end = bi;
+        o.j_end = bj;
         o.status = status;
         o.cells = cells;
         o.tb_page = tb_page;
         o.tb_end = tb_end;
-        o.k_last = (int32_t)min(k, kmax);
+        o.k_last = (int32_t)min((int64_t)k, kmax);
         res[tid] = o;
     }
 }
 
-void launch_ydrop(int cells_per_lane, const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T,
+void launch_ydrop(int cells_per_lane, bool perm, const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T,
                   SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, Arena arena, HalfResult *res, hipStream_t st) {
     if (n <= 0) return;
-    if (cells_per_lane <= 4)
-        k_ydrop_wave<4><<<(unsigned)n, 64, 0, st>>>(tasks, ids, T, Qp, Qm, sc, arena, res);
-    else
-        k_ydrop_wave<16><<<(unsigned)n, 64, 0, st>>>(tasks, ids, T, Qp, Qm, sc, arena, res);
+#define SFE_LAUNCH(CC, PP) k_ydrop_wave<CC, PP><<<(unsigned)n, 64, 0, st>>>(tasks, ids, T, Qp, Qm, sc, arena, res)
+    if (perm) {
+        if (cells_per_lane <= 4) SFE_LAUNCH(4, true);
+        else if (cells_per_lane <= 6) SFE_LAUNCH(6, true);
+        else SFE_LAUNCH(8, true);
+    } else {
+        if (cells_per_lane <= 4) SFE_LAUNCH(4, false);
+        else if (cells_per_lane <= 6) SFE_LAUNCH(6, false);
+        else SFE_LAUNCH(8, false);
+    }
+#undef SFE_LAUNCH
 }
 
 // ---------------------------------------------------------------------------
@@ -355,7 +479,7 @@ __global__ void __launch_bounds__(RING_T) k_ydrop_ring(const HalfTask *__restric
     int32_t *Fr = Er + 2 * (int64_t)cap;
     if (t == 0) {
         Hr[0] = 0; Er[0] = NEG; Fr[0] = NEG;
-        s_pc.page = ~0ull; s_pc.fill = 0; s_pc.size = 0;
+        s_pc.page = ~0ull; s_pc.fill = 0; s_pc.size = 0; s_pc.nrec = 0;
     }
     __syncthreads();
     int best = 0;
@@ -380,19 +504,18 @@ __global__ void __launch_bounds__(RING_T) k_ydrop_ring(const HalfTask *__restric
         }
         if (nonempty && hi - lo + 3 > cap) { status = HALF_WIDTH_OVERFLOW; break; }
         if (t == 0) { s_best = 0; s_min = INT64_MAX; s_max = -1; }
-        const uint32_t n = nonempty ? (uint32_t)(hi - lo + 1) : 0u;
-        const uint32_t pbytes = rec_payload_bytes(n);
-        if (t == 0) s_ok = arena_reserve_1t(ar, s_pc, pbytes + 8) ? 1 : 0;
+        const uint32_t ng = nonempty ? (uint32_t)((hi - lo + 8) / 8) : 0u;
+        if (t == 0) s_ok = arena_reserve_1t(ar, s_pc, 8 + 4 * ng, k) ? 1 : 0;
         __syncthreads();
         if (!s_ok) { status = HALF_ARENA_OVERFLOW; break; }
-        uint8_t *rec = ar.base + s_pc.page + s_pc.fill;
+        uint32_t *rec = (uint32_t *)((uint8_t *)s_pc.page + s_pc.fill);
         const int thr = best - Y;
         const int c1 = (int)((k - 1) % 3), c2 = (int)((k + 1) % 3), c0 = (int)(k % 3);  // k-1, k-2, k
         const int e1 = (int)((k - 1) & 1), e0 = (int)(k & 1);
         if (nonempty) {
-            for (int64_t i0 = lo + 2 * (int64_t)t; i0 <= hi; i0 += 2 * RING_T) {
-                uint32_t byte = 0;
-                for (int u = 0; u < 2; u++) {
+            for (int64_t i0 = lo + 8 * (int64_t)t; i0 <= hi; i0 += 8 * RING_T) {
+                uint32_t word = 0;
+                for (int u = 0; u < 8; u++) {
                     const int64_t i = i0 + u;
                     if (i > hi) break;
                     const int64_t j = k - i;
@@ -414,7 +537,7 @@ __global__ void __launch_bounds__(RING_T) k_ydrop_ring(const HalfTask *__restric
                     Er[e0 * cap + (i & mask)] = live ? E : NEG;
                     Fr[e0 * cap + (i & mask)] = live ? F : NEG;
                     uint32_t code = (H == G ? 0u : (H == E ? 1u : 2u)) | (hlo >= ele ? 4u : 0u) | (huo >= fue ? 8u : 0u);
-                    byte |= code << (4 * u);
+                    word |= code << (4 * u);
                     if (live) {
                         unsigned long long key = ((unsigned long long)(uint32_t)(H + 0x80000000u) << 32) |
                                                  (unsigned long long)(0xffffffffu - (uint32_t)i);
@@ -423,15 +546,17 @@ __global__ void __launch_bounds__(RING_T) k_ydrop_ring(const HalfTask *__restric
                         atomicMax(&s_max, (long long)i);
                     }
                 }
-                rec[(i0 - lo) >> 1] = (uint8_t)byte;
+                rec[2 + ((i0 - lo) >> 3)] = word;
             }
         }
         __syncthreads();
+        uint32_t my_rec = s_pc.fill;
         if (t == 0) {
-            uint32_t *ft = (uint32_t *)(rec + pbytes);
-            ft[0] = nonempty ? (uint32_t)lo : 0u;
-            ft[1] = n;
-            s_pc.fill += pbytes + 8;
+            rec[0] = nonempty ? (uint32_t)lo : 0u;
+            rec[1] = rec_head_word(ng, 8);
+            ((uint32_t *)((uint8_t *)s_pc.page + s_pc.size))[-(int)(s_pc.nrec + 1)] = s_pc.fill;
+            s_pc.fill += 8 + 4 * ng;
+            s_pc.nrec++;
         }
         __syncthreads();
         if (nonempty) cells += (uint64_t)(hi - lo + 1);
@@ -444,8 +569,13 @@ __global__ void __launch_bounds__(RING_T) k_ydrop_ring(const HalfTask *__restric
                 bi = (int64_t)(0xffffffffu - (uint32_t)(s_best & 0xffffffffu));
                 bj = k - bi;
                 tb_page = s_pc.page;
-                tb_end = s_pc.fill;
+                tb_end = my_rec;
             }
+        }
+        if (best >= SFE_SCORE_LIMIT) {
+            status = HALF_SCORE_RANGE;
+            __syncthreads();
+            break;
         }
         const bool stop = (lmin0 > lmax0) && (lmin1 > lmax1);
         lmin2 = lmin1; lmax2 = lmax1; lmin1 = lmin0; lmax1 = lmax0;
@@ -518,56 +648,71 @@ void launch_assemble(const ExtItem *items, int64_t n, const UnitDesc *units, con
 // code's source field picks diagonal / E / F; in E (F) the open bit decides
 // whether the gap started here.  Runs are emitted end cell first.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void rec_footer(const uint8_t *base, uint64_t page, uint32_t end, uint32_t &r0, uint32_t &n) {
-    const uint32_t *ft = (const uint32_t *)(base + page + end - 8);
-    r0 = ft[0];
-    n = ft[1];
-}
-
-__global__ void k_traceback(const HalfResult *__restrict__ res, const int32_t *__restrict__ half_ids, int64_t nh,
-                            Arena ar, const uint64_t *__restrict__ run_off, uint32_t *__restrict__ runs,
-                            uint32_t *__restrict__ nruns) {
-    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per traced half.  The allocation holding the current record is
+// staged in LDS (single-page allocations) so that each step costs two dependent
+// LDS reads: the record's head through the page index, then the code word.
+__global__ void __launch_bounds__(64) k_traceback(const HalfResult *__restrict__ res, const int32_t *__restrict__ half_ids,
+                                                  int64_t nh, Arena ar, const uint64_t *__restrict__ run_off,
+                                                  uint32_t *__restrict__ runs, uint32_t *__restrict__ nruns) {
+    __shared__ uint32_t pbuf[ARENA_PAGE / 4];
+    const int lane = threadIdx.x;
+    const int64_t x = blockIdx.x;
     if (x >= nh) return;
     const int32_t h = half_ids[x];
     const HalfResult R = res[h];
     uint32_t *out = runs + run_off[x];
     int64_t i = R.i_end, j = R.j_end;
-    uint32_t cnt = 0;
-    if (i == 0 && j == 0) { nruns[x] = 0; return; }
+    if (i == 0 && j == 0) {
+        if (lane == 0) nruns[x] = 0;
+        return;
+    }
     uint64_t page = R.tb_page;
-    uint32_t end = R.tb_end;
-    int64_t k = i + j;             // antidiagonal of the record ending at (page, end)
-    int state = 0;
-    uint32_t cur_op = 0xffffffffu, cur_len = 0;
+    uint64_t prev = 0;
+    int64_t k0 = 0;
+    uint32_t size = 0;
+    bool local = false;
+    auto load = [&](uint64_t pgaddr) {
+        const uint32_t *g = (const uint32_t *)pgaddr;
+        prev = (uint64_t)g[0] | ((uint64_t)g[1] << 32);
+        k0 = g[2];
+        const uint32_t pages = g[3];
+        size = pages * ARENA_PAGE;
+        local = pages == 1;
+        __syncthreads();
+        if (local) {
+            const uint4 *src = (const uint4 *)pgaddr;
+            uint4 *dst = (uint4 *)pbuf;
+            for (int q = lane; q < (int)(ARENA_PAGE / 16); q += 64) dst[q] = src[q];
+        }
+        __syncthreads();
+    };
+    auto rd = [&](uint32_t off) -> uint32_t {
+        const uint32_t v = local ? pbuf[off >> 2] : ((const uint32_t *)page)[off >> 2];
+        return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+    };
+    load(page);
     const uint32_t cap = (uint32_t)(R.i_end + R.j_end + 1);
     int64_t guard = 2 * (i + j) + 4;
     bool bad = false;
+    int state = 0;
+    uint32_t cnt = 0, cur_op = 0xffffffffu, cur_len = 0;
     while (!(i == 0 && j == 0 && state == 0)) {
         if (--guard < 0 || i < 0 || j < 0) { bad = true; break; }
-        while (k > i + j) {
-            uint32_t r0, n;
-            rec_footer(ar.base, page, end, r0, n);
-            uint32_t pb = rec_payload_bytes(n);
-            if (end < ARENA_HDR + 8 + pb) { bad = true; break; }
-            uint32_t start = end - 8 - pb;
-            if (start == ARENA_HDR) {
-                const uint32_t *hdr = (const uint32_t *)(ar.base + page);
-                page = (uint64_t)hdr[0] | ((uint64_t)hdr[1] << 32);
-                end = hdr[2];
-                if (page >= ar.bytes || end < ARENA_HDR + 8) { bad = true; break; }
-            } else {
-                end = start;
-            }
-            k--;
+        const int64_t k = i + j;
+        while (k < k0) {
+            if (prev == ~0ull) { bad = true; break; }
+            page = prev;
+            load(page);
         }
         if (bad) break;
-        uint32_t r0, n;
-        rec_footer(ar.base, page, end, r0, n);
-        const uint8_t *pay = ar.base + page + end - 8 - rec_payload_bytes(n);
+        const uint32_t xk = (uint32_t)(k - k0);
+        if (4 * (xk + 1) + ARENA_HDR > size) { bad = true; break; }
+        const uint32_t rec = rd(size - 4 * (xk + 1));
+        const uint32_t r0 = rd(rec), w = rd(rec + 4);
+        const uint32_t ng = w & 0xffffffu, G = w >> 24;
         const uint32_t idx = (uint32_t)(i - r0);
-        if (i < (int64_t)r0 || idx >= n) { bad = true; break; }
-        const uint32_t code = (pay[idx >> 1] >> ((idx & 1) * 4)) & 15u;
+        if (i < (int64_t)r0 || G == 0 || G > 8 || idx / G >= ng) { bad = true; break; }
+        const uint32_t code = (rd(rec + 8 + 4 * (idx / G)) >> (4 * (idx % G))) & 15u;
         uint32_t op;
         if (state == 0) {
             const uint32_t src = code & 3u;
@@ -588,7 +733,8 @@ __global__ void k_traceback(const HalfResult *__restrict__ res, const int32_t *_
         } else {
             if (cur_len) {
                 if (cnt >= cap) { bad = true; break; }
-                out[cnt++] = (cur_len << 2) | cur_op;
+                if (lane == 0) out[cnt] = (cur_len << 2) | cur_op;
+                cnt++;
             }
             cur_op = op;
             cur_len = 1;
@@ -596,15 +742,18 @@ __global__ void k_traceback(const HalfResult *__restrict__ res, const int32_t *_
     }
     if (!bad && cur_len) {
         if (cnt >= cap) bad = true;
-        else out[cnt++] = (cur_len << 2) | cur_op;
+        else {
+            if (lane == 0) out[cnt] = (cur_len << 2) | cur_op;
+            cnt++;
+        }
     }
-    nruns[x] = bad ? 0xffffffffu : cnt;
+    if (lane == 0) nruns[x] = bad ? 0xffffffffu : cnt;
 }
 
 void launch_traceback(const HalfResult *res, const int32_t *half_ids, int64_t n, Arena arena,
                       const uint64_t *run_off, uint32_t *runs, uint32_t *nruns, hipStream_t st) {
     if (n <= 0) return;
-    k_traceback<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(res, half_ids, n, arena, run_off, runs, nruns);
+    k_traceback<<<(unsigned)n, 64, 0, st>>>(res, half_ids, n, arena, run_off, runs, nruns);
 }
 
 // Final ops of an item: backward half (emission order already runs left to

@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(64) k_seed_emit(const UnitDesc *__restrict__ u
 // ---------------------------------------------------------------------------
 // Ungapped X-drop (one hit per lane)
 // ---------------------------------------------------------------------------
-struct XResult { int64_t t0, q0, len; int32_t score; };
+struct XResult { int64_t t0, q0, len; int32_t score; int32_t work; bool range; };
 
 // t, q relative to their sequences (which start at tb / qb in their sets and
 // have lengths nt / nq).  sub: 5x8 table in LDS.
@@ -158,34 +158,45 @@ __device__ __forceinline__ XResult xdrop_one(const SeqSetView &T, int64_t tb, in
     int32_t s0 = 0;
     for (int u = 0; u < span; u++) s0 += sub[base_code(T, tb + t + u) * 8 + base_code(Q, qb + q + u)];
     int32_t s = 0, bR = 0;
-    int64_t R = 0;
+    int64_t R = 0, r = 1;
     int64_t lim = nt - t - span;
     if (nq - q - span < lim) lim = nq - q - span;
-    for (int64_t r = 1; r <= lim; r++) {
+    bool range = false;
+    for (; r <= lim; r++) {
         s += sub[base_code(T, tb + t + span - 1 + r) * 8 + base_code(Q, qb + q + span - 1 + r)];
-        if (s > bR) { bR = s; R = r; }
-        else if (bR - s > X) break;
+        if (s > bR) {
+            bR = s; R = r;
+            if (bR >= SFE_SCORE_LIMIT) { range = true; r++; break; }
+        }
+        else if (bR - s > X) { r++; break; }
     }
+    int32_t work = span + (int32_t)(r - 1);
     int32_t bL = 0;
     int64_t L = 0;
     s = 0;
     lim = t < q ? t : q;
-    for (int64_t r = 1; r <= lim; r++) {
+    for (r = 1; r <= lim && !range; r++) {
         s += sub[base_code(T, tb + t - r) * 8 + base_code(Q, qb + q - r)];
-        if (s > bL) { bL = s; L = r; }
-        else if (bL - s > X) break;
+        if (s > bL) {
+            bL = s; L = r;
+            if (bL >= SFE_SCORE_LIMIT) { range = true; r++; break; }
+        }
+        else if (bL - s > X) { r++; break; }
     }
+    work += (int32_t)(r - 1);
     XResult res;
     res.t0 = t - L;
     res.q0 = q - L;
     res.len = L + span + R;
     res.score = s0 + bL + bR;
+    res.work = work;
+    res.range = range;
     return res;
 }
 
 __global__ void k_xdrop_raw(const sfe_hit *__restrict__ hits, int64_t n, const QueryDesc *__restrict__ qd,
                             int32_t nq, SeqSetView T, int64_t tb, int64_t nt, SeqSetView Qp, SeqSetView Qm,
-                            ScoreDesc sc, int span, sfe_hsp *__restrict__ out) {
+                            ScoreDesc sc, int span, sfe_hsp *__restrict__ out, int *__restrict__ err) {
     __shared__ int sub[40];
     if (threadIdx.x < 40) sub[threadIdx.x] = (threadIdx.x & 7) < 5 ? sc.sub[threadIdx.x >> 3][threadIdx.x & 7] : 0;
     __syncthreads();
@@ -194,6 +205,7 @@ __global__ void k_xdrop_raw(const sfe_hit *__restrict__ hits, int64_t n, const Q
     sfe_hit h = hits[x];
     QueryDesc d = qd[h.query_id];
     XResult r = xdrop_one(T, tb, nt, h.strand ? Qm : Qp, d.start, d.len, h.t, h.q, span, sub, sc.xdrop);
+    if (r.range) atomicOr(err, 1);
     sfe_hsp o;
     o.t0 = (uint32_t)r.t0;
     o.q0 = (uint32_t)r.q0;
@@ -245,6 +257,7 @@ __global__ void __launch_bounds__(256) k_seed_xdrop(const UnitDesc *__restrict__
     uint32_t total = s_wcum[64];
     if (threadIdx.x == 0 && total) atomicAdd(&counters[0], (unsigned long long)total);
     uint32_t passed = 0;
+    unsigned long long work = 0;
     for (uint32_t h = threadIdx.x; h < total; h += blockDim.x) {
         // window: last w with s_wcum[w] <= h
         int lo = 0, hi = 63;
@@ -259,6 +272,8 @@ __global__ void __launch_bounds__(256) k_seed_xdrop(const UnitDesc *__restrict__
         uint32_t t = tpos[s_bstart[w][b] + (r - s_bcum[w][b])];
         int64_t q = (int64_t)c.w0 + w;
         XResult x = xdrop_one(T, tb, nt, Q, u.seq_start, u.len, t, q, sd.span, sub, sc.xdrop);
+        work += (unsigned long long)x.work;
+        if (x.range) atomicOr((unsigned long long *)&counters[3], 1ull);
         if (x.score >= sc.hsp_thresh) {
             unsigned long long slot = atomicAdd(&counters[1], 1ull);
             passed++;
@@ -276,6 +291,9 @@ __global__ void __launch_bounds__(256) k_seed_xdrop(const UnitDesc *__restrict__
         }
     }
     (void)passed;
+    // columns scored, summed over the wave, one atomic per wave
+    for (int m = 32; m >= 1; m >>= 1) work += __shfl_xor(work, m, 64);
+    if ((threadIdx.x & 63) == 0 && work) atomicAdd(&counters[2], work);
 }
 
 // ---------------------------------------------------------------------------

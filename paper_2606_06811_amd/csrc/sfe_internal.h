@@ -14,6 +14,7 @@
 #include "../../include/sfe.h"
 
 #define SFE_NEG (-(1 << 30))
+#define SFE_SCORE_LIMIT (1 << 29)   // a score this large is reported as SFE_ERANGE
 
 namespace sfe {
 
@@ -76,7 +77,7 @@ __device__ __forceinline__ bool window_key(const SeqSetView &s, int64_t p, const
 // B(j) = qset[b0 + bdir * j] for j < nB (positions absolute in their sets).
 struct HalfTask {
     int64_t a0, b0;
-    int32_t nA, nB;
+    int64_t nA, nB;
     int32_t adir, bdir;
     int32_t qset;           // 0 plus-strand query set, 1 minus-strand set
     int32_t pad;
@@ -85,23 +86,27 @@ struct HalfTask {
 #define HALF_OK 0
 #define HALF_WIDTH_OVERFLOW 1
 #define HALF_ARENA_OVERFLOW 2
+#define HALF_SCORE_RANGE 3      // a score reached 2^29 (or the band 2^30 antidiagonals)
 
 struct HalfResult {
     int32_t best, i_end, j_end, status;
     uint64_t cells;
-    uint64_t tb_page;       // arena byte offset of the page holding the end cell's record
-    uint32_t tb_end;        // end offset (within that page) of the end cell's record
+    uint64_t tb_page;       // device address of the allocation holding the end cell's record
+    uint32_t tb_end;        // offset of that record in the allocation
     int32_t k_last;         // last antidiagonal computed
 };
 
-// Traceback pointer arena.  Pages of ARENA_PAGE bytes (a record larger than a
-// page gets several consecutive pages).  Page header (16 bytes):
-//   u64 previous page offset (~0 for the first page of a half), u32 end offset
-//   of the last record in the previous page, u32 pages in this allocation.
-// Records follow, one per antidiagonal k = 1, 2, ... of the half, each
-//   payload: 4-bit codes for rows r0 .. r0+n-1, two per byte, low nibble
-//            first, padded to a multiple of 4 bytes
-//   footer : u32 r0, u32 n
+// Traceback pointer arena.  Allocations of one or more ARENA_PAGE pages, a
+// half's allocations chained backwards.  Allocation layout:
+//   header (16 bytes): u64 device address of the half's previous allocation
+//     (~0 for its first), u32 k0 = antidiagonal of the first record in this
+//     allocation, u32 pages;
+//   records upward from offset 16, one per antidiagonal k0, k0+1, ...:
+//     u32 r0, u32 (g | G << 24), then g u32 words; word w holds the 4-bit codes
+//     of rows r0 + w*G .. r0 + w*G + G-1 (G <= 8, row r0 + w*G + x in bits
+//     4x .. 4x+3);
+//   index downward from the end: u32 at size - 4*(x+1) = offset of the record
+//     of antidiagonal k0 + x.
 // Code bits: 0-1 H source (0 diagonal, 1 E, 2 F), 2 E opened from H,
 //            3 F opened from H.
 #define ARENA_PAGE 32768u
@@ -113,6 +118,6 @@ struct Arena {
     unsigned long long *head;   // device counter: bytes handed out
 };
 
-__host__ __device__ __forceinline__ uint32_t rec_payload_bytes(uint32_t n) { return ((n + 1) / 2 + 3) & ~3u; }
+__host__ __device__ __forceinline__ uint32_t rec_head_word(uint32_t groups, uint32_t G) { return groups | (G << 24); }
 
 }  // namespace sfe

@@ -49,7 +49,8 @@ __global__ void k_seed_emit(const UnitDesc *units, const Chunk *chunks, SeqSetVi
                             const uint32_t *offsets, const uint32_t *tpos, SeedDesc sd, const uint64_t *hit_off,
                             sfe_hit *out);
 __global__ void k_xdrop_raw(const sfe_hit *hits, int64_t n, const QueryDesc *qd, int32_t nq, SeqSetView T, int64_t tb,
-                            int64_t nt, SeqSetView Qp, SeqSetView Qm, ScoreDesc sc, int span, sfe_hsp *out);
+                            int64_t nt, SeqSetView Qp, SeqSetView Qm, ScoreDesc sc, int span, sfe_hsp *out,
+                            int *err);
 __global__ void k_seed_xdrop(const UnitDesc *units, const Chunk *chunks, SeqSetView T, int64_t tb, int64_t nt,
                              SeqSetView Qp, SeqSetView Qm, const uint32_t *offsets, const uint32_t *tpos, SeedDesc sd,
                              ScoreDesc sc, sfe_hsp *out, uint64_t cap, unsigned long long *counters);
@@ -62,7 +63,7 @@ __global__ void k_hsp_compact(const sfe_hsp *h, const uint32_t *perm, const uint
 // gapped stage (k_extend.hip)
 void launch_make_tasks(const ExtItem *items, int64_t n, const UnitDesc *units, int64_t nt, HalfTask *tasks,
                        hipStream_t st);
-void launch_ydrop(int cells_per_lane, const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T,
+void launch_ydrop(int cells_per_lane, bool perm, const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T,
                   SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, Arena arena, HalfResult *res, hipStream_t st);
 void launch_ydrop_ring(const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T, SeqSetView Qp,
                        SeqSetView Qm, const ScoreDesc &sc, Arena arena, int32_t *ring, int32_t cap_rows,

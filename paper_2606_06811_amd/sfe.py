@@ -20,6 +20,7 @@ SFE_OK, SFE_EINVAL, SFE_ENOMEM, SFE_ECAPACITY, SFE_ERANGE, SFE_EDEVICE, SFE_EINT
 SFE_XDROP_RAW = 1
 SFE_ALN_PASSED = 1
 SFE_SCHED_PLAIN, SFE_SCHED_PERSISTENT = 0, 1
+SFE_POLICY_DEFER, SFE_POLICY_PREFIX = 0, 1
 
 HIT_DTYPE = np.dtype([("t", "<u4"), ("q", "<u4"), ("query_id", "<u4"), ("strand", "u1"), ("pad", "u1", (3,))])
 HSP_DTYPE = np.dtype([("t0", "<u4"), ("q0", "<u4"), ("len", "<u4"), ("score", "<i4"), ("query_id", "<u4"),
@@ -53,13 +54,16 @@ class _Scoring(ctypes.Structure):
 
 class _AlignOpts(ctypes.Structure):
     _fields_ = [("round_k", ctypes.c_int32), ("schedule", ctypes.c_int32), ("strands", ctypes.c_int32),
-                ("max_cells_per_lane", ctypes.c_int32), ("arena_bytes", ctypes.c_int64)]
+                ("max_cells_per_lane", ctypes.c_int32), ("policy", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_int64)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("seed_hits", "hsps_raw", "hsps", "rounds", "extensions", "committed",
-                                               "shadow", "cells", "overflow_reruns")] + \
-               [(n, ctypes.c_double) for n in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total")]
+                                               "shadow", "cells", "overflow_reruns", "xdrop_columns",
+                                               "ydrop_launches", "ydrop_kernel_cells", "seed_xdrop_launches")] + \
+               [(n, ctypes.c_double) for n in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total",
+                                               "ms_ydrop_kernel", "ms_seed_xdrop_kernel")]
 
 
 def lib():
@@ -242,12 +246,13 @@ def sfe_gapped_ydrop(ctx: Context, idx: Index, queries, hsps: np.ndarray, scorin
 
 
 def sfe_align(ctx: Context, idx: Index, queries, scoring: dict, round_k: int = 0, schedule: int = SFE_SCHED_PLAIN,
-              strands: int = 3, max_cells_per_lane: int = 0, arena_bytes: int = 0, cap: int = 1 << 12,
-              ops_cap: int = 1 << 18):
+              strands: int = 3, max_cells_per_lane: int = 0, arena_bytes: int = 0, policy: int = SFE_POLICY_DEFER,
+              cap: int = 1 << 12, ops_cap: int = 1 << 18):
     """Whole pipeline; returns (alignments, ops, stats dict)."""
     seqs, keep = _seq_arrays(queries)
     sc = scoring_struct(scoring)
-    opts = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(arena_bytes))
+    opts = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(policy), 0,
+                      int(arena_bytes))
     na, no = ctypes.c_int64(), ctypes.c_int64()
     stats = _Stats()
     while True:

@@ -47,7 +47,7 @@ def test_struct_layouts():
     assert sfe.HSP_DTYPE.itemsize == 24
     assert sfe.ALN_DTYPE.itemsize == 56
     assert ctypes.sizeof(sfe._Scoring) == 31 * 4
-    assert ctypes.sizeof(sfe._AlignOpts) == 24
+    assert ctypes.sizeof(sfe._AlignOpts) == 32
     src = open(HEADER).read()
     assert "} sfe_aln;                  /* 56 bytes */" in src
 

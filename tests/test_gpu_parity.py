@@ -241,12 +241,14 @@ def compare_alignments(alns, ops, ref):
         assert np.array_equal(g, oracle.aln_ops(ref, x)), x
 
 
-@pytest.mark.parametrize("K,cpl", [(1, 0), (7, 0), (64, 0), (1000, 0), (64, 16)])
-def test_align_parity(ctx, align_case, K, cpl):
-    log(f"align parity K={K} cells_per_lane={cpl}")
+@pytest.mark.parametrize("K,cpl,policy", [(1, 0, 1), (7, 0, 1), (64, 0, 1), (1000, 0, 1), (64, 4, 1), (64, 8, 1),
+                                          (1, 0, 0), (3, 0, 0), (0, 0, 0), (0, 4, 0)])
+def test_align_parity(ctx, align_case, K, cpl, policy):
+    log(f"align parity K={K} cells_per_lane={cpl} policy={policy}")
     T, Q, ref = align_case
     idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
-    alns, ops, st = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), round_k=K, max_cells_per_lane=cpl)
+    alns, ops, st = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), round_k=K, max_cells_per_lane=cpl,
+                                  policy=policy)
     assert alns.shape[0] >= 3
     compare_alignments(alns, ops, ref)
     assert st["committed"] == alns.shape[0]
