@@ -76,7 +76,11 @@ struct sfe_ctx {
     DBuf units_d, chunks_d, qdesc_d;
     DBuf hsp_raw, hsp_pass, hsp_sorted;
     DBuf items_d, tasks_d, hres_d, ids_d, aln_d, runoff_d, runs_d, nruns_d, opsoff_d, ops_d, nops_d, ring_d;
-    // traceback arenas: arena 0 takes every batch; a half that finds its arena
+    DBuf sched_d;                       // u64 run-arena head, u32 work-queue head
+    DBuf busy_d;                        // bitmap of the traceback chunk pool
+    int cu_count = 0;
+    // traceback arenas: arena 0 holds the fused kernel's chunk pool and the
+    // workgroup kernel's pages; a workgroup-kernel half that finds its arena
     // full is re-run into the next one (allocated twice as large on demand)
     std::vector<std::unique_ptr<DBuf>> arenas;
     DBuf arena_heads;
@@ -349,8 +353,64 @@ Arena arena_at(sfe_ctx *c, size_t ai) {
     return Arena{c->arenas[ai]->as<uint8_t>(), (uint64_t)bytes, c->arena_heads.as<unsigned long long>() + ai};
 }
 
+// Run arena of at least `runs` entries; the first `keep` entries survive a regrowth.
+RunArena run_arena(sfe_ctx *c, uint64_t runs, uint64_t keep) {
+    if (c->runs_d.n < runs * 4 || !c->runs_d.p) {
+        DBuf grown;
+        grown.ensure((size_t)std::max<uint64_t>(runs, 2 * (c->runs_d.n / 4)) * 4);
+        if (keep) HIPCHK(hipMemcpyAsync(grown.p, c->runs_d.p, (size_t)keep * 4, hipMemcpyDeviceToDevice, c->stream));
+        sync(c);
+        std::swap(c->runs_d.p, grown.p);
+        std::swap(c->runs_d.n, grown.n);
+    }
+    return RunArena{c->runs_d.as<uint32_t>(), (uint64_t)(c->runs_d.n / 4), c->sched_d.as<unsigned long long>()};
+}
+
+uint64_t run_head(sfe_ctx *c) {
+    uint64_t h = 0;
+    HIPCHK(hipMemcpyAsync(&h, c->sched_d.p, 8, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    return h;
+}
+void set_run_head(sfe_ctx *c, uint64_t h) {
+    HIPCHK(hipMemcpyAsync(c->sched_d.p, &h, 8, hipMemcpyHostToDevice, c->stream));
+    sync(c);
+}
+
+// Blocks of the fused kernel the device holds at once.
+int64_t fused_resident(sfe_ctx *c, int cells_per_lane, bool perm, bool persistent) {
+    if (c->cu_count <= 0) {
+        int n = 0;
+        HIPCHK(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, c->device));
+        c->cu_count = n;
+    }
+    const int per_cu = ydrop_fused_blocks_per_cu(cells_per_lane, perm, persistent);
+    if (per_cu <= 0) fail(SFE_EDEVICE, "occupancy query of the extension kernel failed");
+    return (int64_t)per_cu * c->cu_count;
+}
+
+// Chunk pool over arena 0: chunks of 256 KB (smaller for a small arena, so
+// that it holds at least 256 of them), all free.
+ChunkPool make_pool(sfe_ctx *c) {
+    int shift = 18;
+    while (shift > 12 && ((uint64_t)c->arena_bytes >> shift) < 256) shift--;
+    const uint64_t nchunks = std::min<uint64_t>((uint64_t)c->arena_bytes >> shift, (uint64_t)1 << 30);
+    const int32_t nwords = (int32_t)(nchunks / 32);
+    if (nwords < 1) fail(SFE_EINVAL, "traceback arena too small");
+    uint32_t *bits = (uint32_t *)c->busy_d.ensure((size_t)nwords * 4);
+    HIPCHK(hipMemsetAsync(bits, 0, (size_t)nwords * 4, c->stream));
+    return ChunkPool{c->arenas[0]->as<uint8_t>(), bits, nwords, shift};
+}
+
+// Extends the 2n halves of the batch items and traces back every half that
+// ends away from its anchor.  Fused kernel first (rows-per-lane window of
+// cells_per_lane, then 8): a half whose band outgrows the window moves on,
+// finally to the workgroup kernel (ring of 4096 * 4^(stage-2) rows) with the
+// separate traceback.  A half that finds the chunk pool dry is re-run with
+// four times fewer waves in flight (persistent schedule); with one wave, the
+// arena grows.
 void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &items, const ScoreDesc &sc,
-               int cells_per_lane, BatchResult &out) {
+               int cells_per_lane, int schedule, BatchResult &out) {
     const int64_t n = (int64_t)items.size();
     out.alns.assign(n, sfe_aln{});
     out.ops.clear();
@@ -364,28 +424,31 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     bool perm = true;                   // every score fits in int8: scores come from packed row profiles
     for (int a = 0; a < 5; a++)
         for (int b = 0; b < 5; b++) perm = perm && sc.sub[a][b] >= -128 && sc.sub[a][b] <= 127;
-    std::vector<HalfResult> hr(2 * n);
-    // Stages of a half: 0 the register window of cells_per_lane rows per lane,
-    // 1 the 8-rows-per-lane window, 2.. the workgroup kernel with a ring of
-    // 4096 * 4^(stage-2) rows.  A half whose band outgrows its stage moves to the
-    // next; a half whose arena fills up is re-run into the next arena.
-    HIPCHK(hipMemsetAsync(c->arena_heads.p, 0, 8 * 32, c->stream));
-    std::vector<int> stage(2 * n, cells_per_lane < 8 ? 0 : 1);
+    const int64_t nh = 2 * n;
+    std::vector<HalfResult> hr(nh);
+    std::vector<uint64_t> roff(nh, 0);
+    std::vector<uint32_t> nrun(nh, 0);
+    std::vector<int> stage(nh, cells_per_lane < 8 ? 0 : 1), level(nh, 0);
+    c->sched_d.ensure(64);
+    set_run_head(c, 0);
+    RunArena ra = run_arena(c, std::max<uint64_t>(1 << 12, (uint64_t)c->arena_bytes / 256), 0);
     std::vector<int32_t> todo;
-    size_t ai = 0;
+    size_t ai = 0;                      // workgroup-kernel arena
     bool all = true;
     for (;;) {
         std::vector<int32_t> group, rest;
-        int sg = 1 << 20;
+        int sg = 1 << 20, lv = 1 << 20;
         if (all) {
             sg = stage[0];
+            lv = 0;
         } else {
             for (int32_t h : todo) sg = std::min(sg, stage[h]);
-            for (int32_t h : todo) (stage[h] == sg ? group : rest).push_back(h);
+            for (int32_t h : todo)
+                if (stage[h] == sg) lv = std::min(lv, level[h]);
+            for (int32_t h : todo) (stage[h] == sg && (sg >= 2 || level[h] == lv) ? group : rest).push_back(h);
         }
-        Arena ar = arena_at(c, ai);
         const int32_t *ids = nullptr;
-        int64_t cnt = 2 * n;
+        int64_t cnt = nh;
         if (!all) {
             int32_t *idd = (int32_t *)c->ids_d.ensure(group.size() * 4);
             copy_in(c, idd, group.data(), group.size() * 4);
@@ -393,77 +456,143 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
             cnt = (int64_t)group.size();
             out.reruns += cnt;
         }
-        const bool timed = sg <= 1;
-        if (timed) HIPCHK(hipEventRecord(c->ev0, c->stream));
-        if (sg <= 1) {
-            launch_ydrop(sg == 0 ? cells_per_lane : 8, perm, tasks, ids, cnt, T, Qp, Qm, sc, ar, hres, c->stream);
+        const bool fused = sg <= 1;
+        int64_t nwaves = 0;
+        uint64_t chunk_bytes = 0;
+        Arena ar{};
+        if (fused) {
+            const int C = sg == 0 ? cells_per_lane : 8;
+            bool persistent = schedule == SFE_SCHED_PERSISTENT || lv > 0;
+            // level L > 0 (the pool ran dry at level L - 1): 4^L times fewer
+            // waves than the device holds, pulling from the queue
+            int64_t count = fused_resident(c, C, perm, persistent);
+            if (lv > 0) count = std::max<int64_t>(1, count >> std::min(62, 2 * lv));
+            ChunkPool pool = make_pool(c);
+            nwaves = persistent ? count : 0;
+            chunk_bytes = (uint64_t)1 << pool.shift;
+            unsigned int *qhead = (unsigned int *)(c->sched_d.as<uint8_t>() + 8);
+            HIPCHK(hipMemsetAsync(qhead, 0, 4, c->stream));
+            WorkQueue wq{ids, cnt, qhead};
+            HIPCHK(hipEventRecord(c->ev0, c->stream));
+            launch_ydrop_fused(C, perm, persistent, tasks, wq, persistent ? count : cnt, T, Qp, Qm, sc, pool, ra,
+                               hres, c->stream);
         } else {
             const int32_t cap = 4096 << (2 * (sg - 2));
             if (sg - 2 > 10) fail(SFE_EINTERNAL, "band width beyond 2^24 rows");
+            ar = arena_at(c, ai);
+            HIPCHK(hipMemsetAsync(ar.head, 0, 8, c->stream));
             int32_t *ring = (int32_t *)c->ring_d.ensure((size_t)cnt * 7 * cap * 4);
             launch_ydrop_ring(tasks, ids, cnt, T, Qp, Qm, sc, ar, ring, cap, hres, c->stream);
         }
         HIPCHK(hipGetLastError());
-        if (timed) HIPCHK(hipEventRecord(c->ev1, c->stream));
+        if (fused) HIPCHK(hipEventRecord(c->ev1, c->stream));
         copy_out(c, hr.data(), hres, hr.size() * sizeof(HalfResult));
         sync(c);
-        if (timed) {
+        if (fused) {
             c->ydrop_ms += event_ms(c);
             c->ydrop_launches++;
         }
-        std::vector<int32_t> next = rest;
-        bool arena_full = false;
+        std::vector<int32_t> next = rest, traced;
+        bool arena_full = false, runs_full = false, pool_full = false;
         auto check = [&](int32_t h) {
-            if (timed) c->ydrop_cells += (int64_t)hr[h].cells;
-            switch (hr[h].status) {
-            case HALF_OK: break;
-            case HALF_WIDTH_OVERFLOW: stage[h]++; next.push_back(h); break;
-            case HALF_ARENA_OVERFLOW: arena_full = true; next.push_back(h); break;
+            const HalfResult &r = hr[h];
+            if (fused) c->ydrop_cells += (int64_t)r.cells;
+            switch (r.status) {
+            case HALF_OK:
+                if (fused) {
+                    roff[h] = r.tb_page;
+                    nrun[h] = r.tb_end;
+                } else if (r.i_end || r.j_end) {
+                    traced.push_back(h);
+                }
+                break;
+            case HALF_WIDTH_OVERFLOW: stage[h]++; level[h] = 0; next.push_back(h); break;
+            case HALF_ARENA_OVERFLOW:
+                if (fused) {
+                    if (nwaves == 1) pool_full = true;    // one wave already: grow the arena
+                    else level[h] = lv + 1;
+                } else {
+                    arena_full = true;
+                }
+                next.push_back(h);
+                break;
+            case HALF_RUNS_OVERFLOW: runs_full = true; next.push_back(h); break;
             case HALF_SCORE_RANGE: fail(SFE_ERANGE, "a gapped score reached 2^29");
+            case HALF_TRACE_ERROR: fail(SFE_EINTERNAL, "traceback codes are inconsistent");
             default: fail(SFE_EINTERNAL, "unknown half status");
             }
         };
-        if (all) for (int32_t h = 0; h < 2 * n; h++) check(h);
+        if (all) for (int32_t h = 0; h < nh; h++) check(h);
         else for (int32_t h : group) check(h);
+        if (runs_full) {
+            // allocations past the end failed; everything handed out below cap is in use
+            const uint64_t used = ra.cap;
+            ra = run_arena(c, 2 * ra.cap, used);
+            set_run_head(c, used);
+        }
+        if (!traced.empty()) {
+            // workgroup-kernel halves: trace from the paged arena into the run arena
+            uint64_t head = run_head(c);
+            std::vector<uint64_t> off(traced.size());
+            for (size_t x = 0; x < traced.size(); x++) {
+                off[x] = head;
+                head += (uint64_t)hr[traced[x]].i_end + (uint64_t)hr[traced[x]].j_end + 1;
+            }
+            ra = run_arena(c, head, run_head(c));
+            set_run_head(c, head);
+            int32_t *hid_d = (int32_t *)c->ids_d.ensure(traced.size() * 4);
+            uint64_t *off_d = (uint64_t *)c->runoff_d.ensure(traced.size() * 8);
+            uint32_t *cnt_d = (uint32_t *)c->nruns_d.ensure(traced.size() * 4);
+            copy_in(c, hid_d, traced.data(), traced.size() * 4);
+            copy_in(c, off_d, off.data(), traced.size() * 8);
+            launch_traceback(hres, hid_d, (int64_t)traced.size(), ar, off_d, ra.base, cnt_d, c->stream);
+            HIPCHK(hipGetLastError());
+            std::vector<uint32_t> got(traced.size());
+            copy_out(c, got.data(), cnt_d, got.size() * 4);
+            sync(c);
+            for (size_t x = 0; x < traced.size(); x++) {
+                if (got[x] == 0xffffffffu) fail(SFE_EINTERNAL, "traceback records are inconsistent");
+                roff[traced[x]] = off[x];
+                nrun[traced[x]] = got[x];
+            }
+        }
         if (arena_full) ai++;
+        if (pool_full) ensure_arena(c, c->arena_bytes * 4);
+        if (getenv("SFE_PROGRESS")) {
+            if (fused)
+                fprintf(stderr, "[sfe]   launch: fused C=%d level %d, %lld halves, %lld waves, %llu KiB chunks, next %zu\n",
+                        sg == 0 ? cells_per_lane : 8, lv, (long long)cnt, (long long)nwaves,
+                        (unsigned long long)(chunk_bytes >> 10), next.size());
+            else
+                fprintf(stderr, "[sfe]   launch: workgroup stage %d, %lld halves, arena %zu%s, next %zu\n", sg,
+                        (long long)cnt, ai, arena_full ? " (full)" : "", next.size());
+        }
         all = false;
         todo.swap(next);
         if (todo.empty()) break;
     }
-    Arena ar = arena_at(c, 0);
     sfe_aln *aln_d = (sfe_aln *)c->aln_d.ensure((size_t)n * sizeof(sfe_aln));
     launch_assemble(items_d, n, c->units_d.as<UnitDesc>(), hres, T, Qp, Qm, sc, aln_d, c->stream);
     copy_out(c, out.alns.data(), aln_d, (size_t)n * sizeof(sfe_aln));
     sync(c);
-    // traceback of the passing items
-    std::vector<int32_t> pass, half_ids;
+    // edit operations of the passing items
+    std::vector<int32_t> pass;
     std::vector<uint64_t> run_off;
-    uint64_t roff = 0;
+    std::vector<uint32_t> nruns;
     for (int64_t x = 0; x < n; x++) {
         if (!(out.alns[x].flags & SFE_ALN_PASSED)) continue;
         pass.push_back((int32_t)x);
         for (int s = 0; s < 2; s++) {
-            const HalfResult &r = hr[2 * x + s];
-            half_ids.push_back((int32_t)(2 * x + s));
-            run_off.push_back(roff);
-            roff += (uint64_t)r.i_end + (uint64_t)r.j_end + 1;
+            run_off.push_back(roff[2 * x + s]);
+            nruns.push_back(nrun[2 * x + s]);
         }
     }
     if (pass.empty()) return;
     const int64_t np = (int64_t)pass.size();
-    int32_t *hid_d = (int32_t *)c->ids_d.ensure(half_ids.size() * 4);
     uint64_t *roff_d = (uint64_t *)c->runoff_d.ensure(run_off.size() * 8);
-    uint32_t *runs_d = (uint32_t *)c->runs_d.ensure((size_t)roff * 4);
-    uint32_t *nruns_d = (uint32_t *)c->nruns_d.ensure(half_ids.size() * 4);
-    copy_in(c, hid_d, half_ids.data(), half_ids.size() * 4);
+    uint32_t *nruns_d = (uint32_t *)c->nruns_d.ensure(nruns.size() * 4);
     copy_in(c, roff_d, run_off.data(), run_off.size() * 8);
-    launch_traceback(hres, hid_d, (int64_t)half_ids.size(), ar, roff_d, runs_d, nruns_d, c->stream);
-    HIPCHK(hipGetLastError());
-    std::vector<uint32_t> nruns(half_ids.size());
-    copy_out(c, nruns.data(), nruns_d, nruns.size() * 4);
-    sync(c);
-    for (uint32_t v : nruns)
-        if (v == 0xffffffffu) fail(SFE_EINTERNAL, "traceback records are inconsistent");
+    copy_in(c, nruns_d, nruns.data(), nruns.size() * 4);
     std::vector<uint64_t> ops_off(np);
     uint64_t ooff = 0;
     for (int64_t p = 0; p < np; p++) {
@@ -474,7 +603,7 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     uint32_t *ops_d = (uint32_t *)c->ops_d.ensure((size_t)ooff * 4);
     uint32_t *nops_d = (uint32_t *)c->nops_d.ensure((size_t)np * 4);
     copy_in(c, ooff_d, ops_off.data(), (size_t)np * 8);
-    launch_ops_assemble(nullptr, np, roff_d, runs_d, nruns_d, ooff_d, ops_d, nops_d, c->stream);
+    launch_ops_assemble(nullptr, np, roff_d, ra.base, nruns_d, ooff_d, ops_d, nops_d, c->stream);
     HIPCHK(hipGetLastError());
     std::vector<uint32_t> nops(np), ops_all(ooff);
     copy_out(c, nops.data(), nops_d, (size_t)np * 4);
@@ -793,7 +922,7 @@ sfe_status sfe_gapped_ydrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *quer
             items[x] = ExtItem{h.t0 + off, h.q0 + off, (int32_t)(2 * h.query_id + h.strand), 0};
         }
         BatchResult br;
-        run_batch(c, ix, items, sc, 6, br);
+        run_batch(c, ix, items, sc, 6, SFE_SCHED_PLAIN, br);
         int64_t need = (int64_t)br.ops.size();
         *n_ops = need;
         if (need > ops_cap) fail(SFE_ECAPACITY, "ops buffer too small");
@@ -947,7 +1076,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             if (items.empty()) break;
             st.rounds++;
             const double tr = now_ms();
-            run_batch(c, ix, items, sc, cpl, br);                 // phase 2: speculative extensions
+            run_batch(c, ix, items, sc, cpl, o.schedule, br);                 // phase 2: speculative extensions
             if (progress)
                 fprintf(stderr, "[sfe] batch %lld: %zu extensions, %.1f ms, %zu committed so far\n",
                         (long long)st.rounds, items.size(), now_ms() - tr, committed.size());

@@ -35,23 +35,9 @@
 // and no pointer on a traceback path depends on them.
 #include <type_traits>
 
-#include "sfe_kernels.h"
+#include "ydrop_common.h"
 
 namespace sfe {
-
-#define NEG SFE_NEG
-
-__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
-__device__ __forceinline__ int imax3(int a, int b, int c) { return imax(imax(a, b), c); }
-
-__device__ __forceinline__ int codeA(const SeqSetView &T, const HalfTask &tk, int64_t i) {
-    if (i < 0 || i >= tk.nA) return 4;
-    return base_code(T, tk.a0 + (int64_t)tk.adir * i);
-}
-__device__ __forceinline__ int codeB(const SeqSetView &Q, const HalfTask &tk, int64_t j) {
-    if (j < 0 || j >= tk.nB) return 4;
-    return base_code(Q, tk.b0 + (int64_t)tk.bdir * j);
-}
 
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
@@ -112,341 +98,6 @@ __device__ __forceinline__ bool arena_reserve_1t(Arena &ar, PageCursor &pc, uint
     pc.size = pages * ARENA_PAGE;
     pc.nrec = 0;
     return true;
-}
-
-// ---------------------------------------------------------------------------
-// Wave kernel
-// ---------------------------------------------------------------------------
-// Cross-lane helpers (DPP): lane l receives lane l-1 (shr) or l+1 (shl); the
-// lane without a source keeps `old`.
-__device__ __forceinline__ int dpp_shr1(int old, int src) {
-    return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);
-}
-__device__ __forceinline__ int dpp_shl1(int old, int src) {
-    return __builtin_amdgcn_update_dpp(old, src, 0x130, 0xf, 0xf, false);
-}
-// Maximum over the wave (uniform result): in-row shifts, then the four row maxima.
-__device__ __forceinline__ int wave_max_dpp(int v) {
-    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));
-    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));
-    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));
-    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));
-    int a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
-    int c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
-    return imax(imax(a, b), imax(c, d));
-}
-
-#define ROW_LIMIT (1 << 30)       // antidiagonals beyond this stop the half with HALF_SCORE_RANGE
-#define RING 2048                 // sequence codes staged in LDS per side
-#define RING_CHUNK 512            // codes loaded per refill
-
-// Substitution scores.  PERM: every entry fits in int8, a row carries the
-// packed scores of its target base against A, C, G, T (lo) and N (hi), and a
-// query code travels as a v_perm selector picking its byte into bits 24..31.
-// Otherwise rows carry the target code * 8 and the score is read from LDS.
-template <bool PERM> struct Scorer;
-template <> struct Scorer<true> {
-    static __device__ __forceinline__ int bsel(int code) { return (code << 24) | 0x000c0c0c; }
-    static __device__ __forceinline__ int score(int plo, int phi, int bsel, const int *) {
-        return (int)__builtin_amdgcn_perm((uint32_t)phi, (uint32_t)plo, (uint32_t)bsel) >> 24;
-    }
-};
-template <> struct Scorer<false> {
-    static __device__ __forceinline__ int bsel(int code) { return code; }
-    static __device__ __forceinline__ int score(int plo, int, int bsel, const int *sub) { return sub[plo + bsel]; }
-};
-
-// Loads codes of positions [from, from + RING_CHUNK) of one side of a half into
-// its LDS ring (index & (RING - 1)); positions outside [0, n) read as N.
-__device__ __forceinline__ void ring_fill(uint8_t *ring, const SeqSetView &S, int64_t p0, int64_t dir, int64_t n,
-                                          int64_t from, int lane) {
-#pragma unroll 4
-    for (int x = lane; x < RING_CHUNK; x += 64) {
-        const int64_t j = from + x;
-        int c = 4;
-        if (j >= 0 && j < n) c = base_code(S, p0 + dir * j);
-        ring[j & (RING - 1)] = (uint8_t)c;
-    }
-    __syncthreads();
-}
-
-template <int C, bool PERM>
-__global__ void __launch_bounds__(64) k_ydrop_wave(const HalfTask *__restrict__ tasks, const int32_t *__restrict__ ids,
-                                                   SeqSetView T, SeqSetView Qp, SeqSetView Qm, ScoreDesc sc,
-                                                   Arena ar, HalfResult *__restrict__ res) {
-    static_assert(C <= 8, "one 32-bit record word per lane");
-    typedef Scorer<PERM> S;
-    __shared__ int sub[40];
-    __shared__ int prof[2][8];        // PERM: packed row profiles per target code
-    __shared__ uint8_t aring[RING], bring[RING];
-    const int lane = threadIdx.x;
-    if (lane < 40) sub[lane] = (lane & 7) < 5 ? sc.sub[lane >> 3][lane & 7] : 0;
-    if (lane < 5) {
-        uint32_t lo = 0;
-        for (int b = 0; b < 4; b++) lo |= ((uint32_t)sc.sub[lane][b] & 0xffu) << (8 * b);
-        prof[0][lane] = (int)lo;
-        prof[1][lane] = (int)((uint32_t)sc.sub[lane][4] & 0xffu);
-    }
-    const int64_t tid = ids ? ids[blockIdx.x] : blockIdx.x;
-    const HalfTask tk = tasks[tid];
-    const SeqSetView Q = tk.qset ? Qm : Qp;
-    const int e = sc.gap_extend, oe = sc.gap_open + sc.gap_extend, Y = sc.ydrop;
-    const int64_t nA = tk.nA, nB = tk.nB;
-    const int64_t kmax = nA + nB;
-    // A index i-1 of row i is staged in aring; B index j in bring
-    int64_t a_hi = 0, b_hi = 0;       // first index not yet staged
-    while (a_hi < 64 * C + 64) { ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane); a_hi += RING_CHUNK; }
-    while (b_hi < 128) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
-    auto acode = [&](int64_t ia) { return ia < 0 ? 4 : (int)aring[ia & (RING - 1)]; };          // A(ia)
-    auto bcode = [&](int64_t jb) {      // B(jb); indices that left the ring are read from memory
-        if (jb < 0) return 4;
-        if (jb < b_hi - RING) return codeB(Q, tk, jb);
-        return (int)bring[jb & (RING - 1)];
-    };
-    auto plo_of = [&](int a) { return PERM ? prof[0][a] : a * 8; };
-    auto phi_of = [&](int a) { return PERM ? prof[1][a] : 0; };
-
-    // rows base + lane*C + r
-    int H1[C], H2[C], E1[C], F1[C], Plo[C], Phi[C], Bs[C];
-    int base = 0;
-#pragma unroll
-    for (int r = 0; r < C; r++) {
-        const int i = lane * C + r;
-        H1[r] = (i == 0) ? 0 : NEG;
-        H2[r] = NEG;
-        E1[r] = NEG;
-        F1[r] = NEG;
-        const int a = acode(i - 1);
-        Plo[r] = plo_of(a);
-        Phi[r] = phi_of(a);
-        Bs[r] = S::bsel(i == 0 ? bcode(0) : 4);
-    }
-    int best = 0, bi = 0, bj = 0;
-    uint64_t cells = 1;
-    int lmin1 = 0, lmax1 = 0;            // live rows of antidiagonal k-1 (lmin > lmax: none)
-    int lmin2 = 1, lmax2 = 0;            // live rows of antidiagonal k-2
-    uint64_t pg = ~0ull;                 // arena cursor (uniform)
-    uint32_t fill = 0, psize = 0, nrec = 0, rec_off = 0;
-    uint64_t tb_page = ~0ull;
-    uint32_t tb_end = 0;
-    int status = HALF_OK;
-    int k = 1;
-    for (; (int64_t)k <= kmax; k++) {
-        if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
-        // candidate rows of antidiagonal k
-        int lo = 0x7fffffff, hi = -1;
-        if (lmin1 <= lmax1) { lo = lmin1; hi = lmax1 + 1; }
-        if (lmin2 <= lmax2) { lo = min(lo, lmin2 + 1); hi = max(hi, lmax2 + 1); }
-        const int clo = (int)max((int64_t)0, (int64_t)k - nB);
-        const int chi = (int)min(nA, (int64_t)k);
-        lo = max(lo, clo);
-        hi = min(hi, chi);
-        const bool nonempty = lo <= hi;
-        if (nonempty) {
-            // slide the window: rows below lo-1 are never read again
-            const int s = (lo - 1 - base) / C;
-            if (s >= 1) {
-                while (a_hi < (int64_t)base + (s + 64) * C + 64) {
-                    ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane);
-                    a_hi += RING_CHUNK;
-                }
-                if (s == 1) {
-#pragma unroll
-                    for (int r = 0; r < C; r++) {
-                        const int i_new = base + 64 * C + r;        // row entering lane 63
-                        const int a = acode(i_new - 1);
-                        const int fb = S::bsel(bcode((int64_t)k - i_new - 1));
-                        H1[r] = dpp_shl1(NEG, H1[r]);
-                        H2[r] = dpp_shl1(NEG, H2[r]);
-                        E1[r] = dpp_shl1(NEG, E1[r]);
-                        F1[r] = dpp_shl1(NEG, F1[r]);
-                        Plo[r] = dpp_shl1(plo_of(a), Plo[r]);
-                        Phi[r] = dpp_shl1(phi_of(a), Phi[r]);
-                        Bs[r] = dpp_shl1(fb, Bs[r]);
-                    }
-                } else {
-                    const int sl = min(s, 64);
-                    const int src = (lane + sl) & 63;
-                    const bool from_next = lane + sl >= 64;
-#pragma unroll
-                    for (int r = 0; r < C; r++) {
-                        const int i_new = base + s * C + lane * C + r;
-                        const int h1 = __shfl(H1[r], src, 64), h2 = __shfl(H2[r], src, 64);
-                        const int e1 = __shfl(E1[r], src, 64), f1 = __shfl(F1[r], src, 64);
-                        const int pl = __shfl(Plo[r], src, 64), ph = __shfl(Phi[r], src, 64);
-                        const int bs = __shfl(Bs[r], src, 64);
-                        const int a = acode(i_new - 1);
-                        H1[r] = from_next ? NEG : h1;
-                        H2[r] = from_next ? NEG : h2;
-                        E1[r] = from_next ? NEG : e1;
-                        F1[r] = from_next ? NEG : f1;
-                        Plo[r] = from_next ? plo_of(a) : pl;
-                        Phi[r] = from_next ? phi_of(a) : ph;
-                        Bs[r] = from_next ? S::bsel(bcode((int64_t)k - i_new - 1)) : bs;
-                    }
-                }
-                base += s * C;
-            }
-            if (hi > base + 64 * C - 1) { status = HALF_WIDTH_OVERFLOW; break; }
-        }
-        const int thr = best - Y;
-        const int upH = dpp_shr1(NEG, H1[C - 1]);
-        const int upF = dpp_shr1(NEG, F1[C - 1]);
-        const int upD = dpp_shr1(NEG, H2[C - 1]);
-        int Hn[C], En[C], Fn[C];
-        uint32_t nib = 0;
-        int lmax = NEG;
-        int fr = 0x7fffffff, lr = -1;    // first and last live row (relative to base)
-        // rows past the end of A, or whose column is past the end of B, are outside
-        // the matrix; rows above the antidiagonal need no mask (their neighbours are never live)
-        auto cell_pass = [&](auto edge_tag) {
-            constexpr bool EDGE = decltype(edge_tag)::value;
-            const int i0 = base + lane * C;
-#pragma unroll
-            for (int r = 0; r < C; r++) {
-                const int Hu = r ? H1[r - 1] : upH;
-                const int Fu = r ? F1[r - 1] : upF;
-                const int Hd = r ? H2[r - 1] : upD;
-                const int hlo = H1[r] - oe, ele = E1[r] - e;
-                const int huo = Hu - oe, fue = Fu - e;
-                const int E = imax3(hlo, ele, NEG);
-                const int F = imax3(huo, fue, NEG);
-                const int G = Hd + S::score(Plo[r], Phi[r], Bs[r], sub);
-                const int H = imax3(G, E, F);
-                bool live = H >= thr;
-                if (EDGE) {
-                    const bool v = (unsigned)(i0 + r - clo) <= (unsigned)(chi - clo);
-                    live = live && v;
-                    En[r] = v ? E : NEG;
-                    Fn[r] = v ? F : NEG;
-                } else {
-                    En[r] = E;
-                    Fn[r] = F;
-                }
-                Hn[r] = live ? H : NEG;
-                const uint64_t m = __ballot(live);
-                if (m) {
-                    fr = min(fr, __builtin_ctzll(m) * C + r);
-                    lr = max(lr, (63 - __builtin_clzll(m)) * C + r);
-                }
-                const uint32_t code = (H == G ? 0u : (H == E ? 1u : 2u)) | (hlo >= ele ? 4u : 0u) |
-                                      (huo >= fue ? 8u : 0u);
-                nib |= code << (4 * r);
-                lmax = imax(lmax, Hn[r]);
-            }
-        };
-        const bool edge = base < clo || (int64_t)base + 64 * C - 1 > nA;
-        if (edge) cell_pass(std::true_type());
-        else cell_pass(std::false_type());
-        int lmin0 = 1, lmax0 = 0;
-        if (lr >= 0) { lmin0 = base + fr; lmax0 = base + lr; }
-        // traceback record: rows of the lanes covering [lo, hi]
-        {
-            int l_lo = 0, l_hi = -1;
-            if (nonempty) {
-                l_lo = (lo - base) / C;
-                l_hi = (hi - base) / C;
-            }
-            const uint32_t ng = (uint32_t)(l_hi - l_lo + 1);
-            const uint32_t need = 8 + 4 * ng;
-            if (pg == ~0ull || fill + need + 4 * (nrec + 1) > psize) {
-                const uint32_t pages = (need + ARENA_HDR + 4 + ARENA_PAGE - 1) / ARENA_PAGE;
-                unsigned long long off = 0;
-                if (lane == 0) off = atomicAdd(ar.head, (unsigned long long)pages * ARENA_PAGE);
-                const uint32_t olo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off);
-                const uint32_t ohi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(off >> 32));
-                off = ((unsigned long long)ohi << 32) | olo;
-                if (off + (unsigned long long)pages * ARENA_PAGE > ar.bytes) { status = HALF_ARENA_OVERFLOW; break; }
-                if (lane == 0) {
-                    uint32_t *hdr = (uint32_t *)(ar.base + off);
-                    hdr[0] = (uint32_t)pg;
-                    hdr[1] = (uint32_t)(pg >> 32);
-                    hdr[2] = (uint32_t)k;
-                    hdr[3] = pages;
-                }
-                pg = (uint64_t)(ar.base + off);
-                fill = ARENA_HDR;
-                psize = pages * ARENA_PAGE;
-                nrec = 0;
-            }
-            uint32_t *rec = (uint32_t *)((uint8_t *)pg + fill);
-            if (lane >= l_lo && lane <= l_hi) rec[2 + lane - l_lo] = nib;
-            if (lane == 0) {
-                rec[0] = nonempty ? (uint32_t)(base + l_lo * C) : 0u;
-                rec[1] = rec_head_word(ng, C);
-                ((uint32_t *)((uint8_t *)pg + psize))[-(int)(nrec + 1)] = fill;
-            }
-            rec_off = fill;
-            fill += need;
-            nrec++;
-            if (nonempty) cells += (uint64_t)(hi - lo + 1);
-        }
-        // best over this antidiagonal; end cell = smallest row reaching it
-        const int admax = wave_max_dpp(lmax);
-        if (admax > best) {
-            int row = 0x7fffffff;
-#pragma unroll
-            for (int r = 0; r < C; r++) {
-                const uint64_t m = __ballot(Hn[r] == admax);
-                if (m) row = min(row, __builtin_ctzll(m) * C + r);
-            }
-            best = admax;
-            bi = base + row;
-            bj = k - bi;
-            tb_page = pg;
-            tb_end = rec_off;
-            if (best >= SFE_SCORE_LIMIT) { status = HALF_SCORE_RANGE; break; }
-        }
-        // advance to antidiagonal k+1
-#pragma unroll
-        for (int r = 0; r < C; r++) {
-            H2[r] = H1[r];
-            H1[r] = Hn[r];
-            E1[r] = En[r];
-            F1[r] = Fn[r];
-        }
-        // query code entering row `base` on antidiagonal k+1: B(k - base)
-        const int64_t bnew = (int64_t)k - base;
-        while (b_hi < bnew + 64) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
-        {
-            const int carry = dpp_shr1(S::bsel(bcode(bnew)), Bs[C - 1]);
-#pragma unroll
-            for (int r = C - 1; r > 0; r--) Bs[r] = Bs[r - 1];
-            Bs[0] = carry;
-        }
-        const bool stop = (lmin0 > lmax0) && (lmin1 > lmax1);
-        lmin2 = lmin1; lmax2 = lmax1;
-        lmin1 = lmin0; lmax1 = lmax0;
-        if (stop) break;
-    }
-    if (lane == 0) {
-        HalfResult o;
-        o.best = best;
-        o.i_end = bi;
-        o.j_end = bj;
-        o.status = status;
-        o.cells = cells;
-        o.tb_page = tb_page;
-        o.tb_end = tb_end;
-        o.k_last = (int32_t)min((int64_t)k, kmax);
-        res[tid] = o;
-    }
-}
-
-void launch_ydrop(int cells_per_lane, bool perm, const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T,
-                  SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, Arena arena, HalfResult *res, hipStream_t st) {
-    if (n <= 0) return;
-#define SFE_LAUNCH(CC, PP) k_ydrop_wave<CC, PP><<<(unsigned)n, 64, 0, st>>>(tasks, ids, T, Qp, Qm, sc, arena, res)
-    if (perm) {
-        if (cells_per_lane <= 4) SFE_LAUNCH(4, true);
-        else if (cells_per_lane <= 6) SFE_LAUNCH(6, true);
-        else SFE_LAUNCH(8, true);
-    } else {
-        if (cells_per_lane <= 4) SFE_LAUNCH(4, false);
-        else if (cells_per_lane <= 6) SFE_LAUNCH(6, false);
-        else SFE_LAUNCH(8, false);
-    }
-#undef SFE_LAUNCH
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,535 @@
+// k_fused.hip -- gapped Y-drop extension of anchor halves fused with their
+// traceback, one 64-lane wave per half (Sec. 8 of the paper).
+//
+// The DP is the one described at the top of k_extend.hip.  The traceback
+// codes of a half (one record per antidiagonal: u32 first row, u32
+// (groups | G << 24), one u32 of 4-bit codes per lane-group of G rows) go to
+// a chain of fixed-size chunks taken from a pool shared by all waves.  When
+// the half stops, the same wave walks the codes back from the end cell
+// (staging index entries and records through LDS), returning each chunk to
+// the pool once the walk has left it; the run-length edit operations go to a
+// second chain and are finally copied, contiguous, to the run arena.  The
+// device thus holds codes only for the halves in flight, and a half never
+// has to be re-run because its traceback is long -- only when the whole pool
+// is exhausted.
+//
+// Work sources:
+//  * plain (one block per half, the paper's mapping): block b runs half ids[b];
+//  * persistent: a fixed grid of waves pulls halves from a queue (an atomic
+//    head over `ids`) until it is empty.
+#include "ydrop_common.h"
+
+namespace sfe {
+
+#define TB_IDX 512            // index entries staged in LDS during traceback
+#define TB_REC 1024           // record words staged in LDS during traceback
+
+// Takes a free chunk (wave-uniform; -1 if none was found).  Lanes read 64
+// bitmap words at once; lane 0 claims the first free bit seen.  The fence
+// after a claim (and before a release) orders the chunk's previous contents
+// against its new owner across the L2s of the chip.
+__device__ __forceinline__ int pool_alloc(const ChunkPool &p, int &hint, int lane) {
+    const int tries = 2 * (p.nwords / 64) + 16;
+    for (int t = 0; t < tries; t++) {
+        const int w = (hint + lane) % p.nwords;
+        const uint32_t word = __hip_atomic_load(&p.bits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t m = __ballot(word != 0xffffffffu);
+        if (!m) {
+            hint = (hint + 64) % p.nwords;
+            continue;
+        }
+        const int L = __builtin_ctzll(m);
+        const int wl = __builtin_amdgcn_readlane(w, L);
+        const uint32_t wd = (uint32_t)__builtin_amdgcn_readlane((int)word, L);
+        const uint32_t bit = 1u << __builtin_ctz(~wd);
+        uint32_t old = 0;
+        if (lane == 0) old = atomicOr(&p.bits[wl], bit);
+        old = (uint32_t)__builtin_amdgcn_readfirstlane((int)old);
+        hint = wl;
+        if (!(old & bit)) {
+            __threadfence();
+            return wl * 32 + __builtin_ctz(bit);
+        }
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void pool_free(const ChunkPool &p, int c, int lane) {
+    __threadfence();
+    if (lane == 0) atomicAnd(&p.bits[c >> 5], ~(1u << (c & 31)));
+}
+
+template <int C, bool PERM, bool PERSIST>
+__global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__ tasks, WorkQueue wq, SeqSetView T,
+                                                    SeqSetView Qp, SeqSetView Qm, ScoreDesc sc, ChunkPool pool,
+                                                    RunArena ra, HalfResult *__restrict__ res) {
+    static_assert(C <= 8, "one 32-bit record word per lane");
+    typedef Scorer<PERM> S;
+    __shared__ int sub[40];
+    __shared__ int prof[2][8];
+    __shared__ uint8_t aring[RING], bring[RING];
+    __shared__ uint32_t tb_idx[TB_IDX], tb_rec[TB_REC];
+    const int lane = threadIdx.x;
+    if (lane < 40) sub[lane] = (lane & 7) < 5 ? sc.sub[lane >> 3][lane & 7] : 0;
+    if (lane < 5) {
+        uint32_t lo = 0;
+        for (int b = 0; b < 4; b++) lo |= ((uint32_t)sc.sub[lane][b] & 0xffu) << (8 * b);
+        prof[0][lane] = (int)lo;
+        prof[1][lane] = (int)((uint32_t)sc.sub[lane][4] & 0xffu);
+    }
+    __syncthreads();
+    const int e = sc.gap_extend, oe = sc.gap_open + sc.gap_extend, Y = sc.ydrop;
+
+    int hint = (int)((blockIdx.x * 37u) % (unsigned)pool.nwords);
+    const uint32_t CH = 1u << pool.shift;
+    auto chunk = [&](int c) { return pool.base + ((uint64_t)(uint32_t)c << pool.shift); };
+    auto hdr = [&](int c, int w) {
+        return (uint32_t)__builtin_amdgcn_readfirstlane((int)((const uint32_t *)chunk(c))[w]);
+    };
+    auto free_chain = [&](int c) {
+        for (int guard = 0; c >= 0 && guard < (1 << 24); guard++) {
+            const int prev = (int)hdr(c, 0);
+            pool_free(pool, c, lane);
+            c = prev;
+        }
+    };
+
+    int64_t item = PERSIST ? -1 : (int64_t)blockIdx.x;
+    for (;;) {
+        if (PERSIST) {
+            unsigned int q = 0;
+            if (lane == 0) q = atomicAdd(wq.head, 1u);
+            q = (unsigned int)__builtin_amdgcn_readfirstlane((int)q);
+            if ((int64_t)q >= wq.n) break;
+            item = q;
+        }
+        const int64_t tid = wq.ids ? wq.ids[item] : item;
+        const HalfTask tk = tasks[tid];
+        const SeqSetView Q = tk.qset ? Qm : Qp;
+        const int64_t nA = tk.nA, nB = tk.nB;
+        const int64_t kmax = nA + nB;
+        __syncthreads();
+        int64_t a_hi = 0, b_hi = 0;
+        while (a_hi < 64 * C + 64) { ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane); a_hi += RING_CHUNK; }
+        while (b_hi < 128) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
+        auto acode = [&](int64_t ia) { return ia < 0 ? 4 : (int)aring[ia & (RING - 1)]; };
+        auto bcode = [&](int64_t jb) {
+            if (jb < 0) return 4;
+            if (jb < b_hi - RING) return codeB(Q, tk, jb);
+            return (int)bring[jb & (RING - 1)];
+        };
+        auto plo_of = [&](int a) { return PERM ? prof[0][a] : a * 8; };
+        auto phi_of = [&](int a) { return PERM ? prof[1][a] : 0; };
+
+        int H1[C], H2[C], E1[C], F1[C], Plo[C], Phi[C], Bs[C];
+        int base = 0;
+#pragma unroll
+        for (int r = 0; r < C; r++) {
+            const int i = lane * C + r;
+            H1[r] = (i == 0) ? 0 : NEG;
+            H2[r] = NEG;
+            E1[r] = NEG;
+            F1[r] = NEG;
+            const int a = acode(i - 1);
+            Plo[r] = plo_of(a);
+            Phi[r] = phi_of(a);
+            Bs[r] = S::bsel(i == 0 ? bcode(0) : 4);
+        }
+        int best = 0, bi = 0, bj = 0;
+        uint64_t cells = 1;
+        int lmin1 = 0, lmax1 = 0, lmin2 = 1, lmax2 = 0;
+        // current chunk of the code chain: index, address, first antidiagonal, bytes used
+        int cur = pool_alloc(pool, hint, lane);
+        uint8_t *cb = nullptr;
+        int k0 = 1;
+        uint32_t fill = 16;
+        int status = HALF_OK;
+        if (cur < 0) {
+            status = HALF_ARENA_OVERFLOW;
+        } else {
+            cb = chunk(cur);
+            if (lane == 0) {
+                ((uint32_t *)cb)[0] = 0xffffffffu;
+                ((uint32_t *)cb)[1] = 1u;
+            }
+        }
+        int k = 1;
+        for (; status == HALF_OK && (int64_t)k <= kmax; k++) {
+            if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
+            int lo = 0x7fffffff, hi = -1;
+            if (lmin1 <= lmax1) { lo = lmin1; hi = lmax1 + 1; }
+            if (lmin2 <= lmax2) { lo = min(lo, lmin2 + 1); hi = max(hi, lmax2 + 1); }
+            const int clo = (int)max((int64_t)0, (int64_t)k - nB);
+            const int chi = (int)min(nA, (int64_t)k);
+            lo = max(lo, clo);
+            hi = min(hi, chi);
+            const bool nonempty = lo <= hi;
+            if (nonempty) {
+                const int s = (lo - 1 - base) / C;
+                if (s >= 1) {
+                    while (a_hi < (int64_t)base + (s + 64) * C + 64) {
+                        ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane);
+                        a_hi += RING_CHUNK;
+                    }
+                    if (s == 1) {
+#pragma unroll
+                        for (int r = 0; r < C; r++) {
+                            const int i_new = base + 64 * C + r;
+                            const int a = acode(i_new - 1);
+                            const int fb = S::bsel(bcode((int64_t)k - i_new - 1));
+                            H1[r] = dpp_shl1(NEG, H1[r]);
+                            H2[r] = dpp_shl1(NEG, H2[r]);
+                            E1[r] = dpp_shl1(NEG, E1[r]);
+                            F1[r] = dpp_shl1(NEG, F1[r]);
+                            Plo[r] = dpp_shl1(plo_of(a), Plo[r]);
+                            Phi[r] = dpp_shl1(phi_of(a), Phi[r]);
+                            Bs[r] = dpp_shl1(fb, Bs[r]);
+                        }
+                    } else {
+                        const int sl_ = min(s, 64);
+                        const int src = (lane + sl_) & 63;
+                        const bool from_next = lane + sl_ >= 64;
+#pragma unroll
+                        for (int r = 0; r < C; r++) {
+                            const int i_new = base + s * C + lane * C + r;
+                            const int h1 = __shfl(H1[r], src, 64), h2 = __shfl(H2[r], src, 64);
+                            const int e1 = __shfl(E1[r], src, 64), f1 = __shfl(F1[r], src, 64);
+                            const int pl = __shfl(Plo[r], src, 64), ph = __shfl(Phi[r], src, 64);
+                            const int bs = __shfl(Bs[r], src, 64);
+                            const int a = acode(i_new - 1);
+                            H1[r] = from_next ? NEG : h1;
+                            H2[r] = from_next ? NEG : h2;
+                            E1[r] = from_next ? NEG : e1;
+                            F1[r] = from_next ? NEG : f1;
+                            Plo[r] = from_next ? plo_of(a) : pl;
+                            Phi[r] = from_next ? phi_of(a) : ph;
+                            Bs[r] = from_next ? S::bsel(bcode((int64_t)k - i_new - 1)) : bs;
+                        }
+                    }
+                    base += s * C;
+                }
+                if (hi > base + 64 * C - 1) { status = HALF_WIDTH_OVERFLOW; break; }
+            }
+            const int thr = best - Y;
+            const int upH = dpp_shr1(NEG, H1[C - 1]);
+            const int upF = dpp_shr1(NEG, F1[C - 1]);
+            const int upD = dpp_shr1(NEG, H2[C - 1]);
+            int Hn[C], En[C], Fn[C];
+            uint32_t nib = 0;
+            int lmax = NEG;
+            int fr = 0x7fffffff, lr = -1;
+            auto cell_pass = [&](auto edge_tag) {
+                constexpr bool EDGE = decltype(edge_tag)::value;
+                const int i0 = base + lane * C;
+#pragma unroll
+                for (int r = 0; r < C; r++) {
+                    const int Hu = r ? H1[r - 1] : upH;
+                    const int Fu = r ? F1[r - 1] : upF;
+                    const int Hd = r ? H2[r - 1] : upD;
+                    const int hlo = H1[r] - oe, ele = E1[r] - e;
+                    const int huo = Hu - oe, fue = Fu - e;
+                    const int E = imax3(hlo, ele, NEG);
+                    const int F = imax3(huo, fue, NEG);
+                    const int G = Hd + S::score(Plo[r], Phi[r], Bs[r], sub);
+                    const int H = imax3(G, E, F);
+                    bool live = H >= thr;
+                    if (EDGE) {
+                        const bool v = (unsigned)(i0 + r - clo) <= (unsigned)(chi - clo);
+                        live = live && v;
+                        En[r] = v ? E : NEG;
+                        Fn[r] = v ? F : NEG;
+                    } else {
+                        En[r] = E;
+                        Fn[r] = F;
+                    }
+                    Hn[r] = live ? H : NEG;
+                    const uint64_t m = __ballot(live);
+                    if (m) {
+                        fr = min(fr, __builtin_ctzll(m) * C + r);
+                        lr = max(lr, (63 - __builtin_clzll(m)) * C + r);
+                    }
+                    const uint32_t code = (H == G ? 0u : (H == E ? 1u : 2u)) | (hlo >= ele ? 4u : 0u) |
+                                          (huo >= fue ? 8u : 0u);
+                    nib |= code << (4 * r);
+                    lmax = imax(lmax, Hn[r]);
+                }
+            };
+            const bool edge = base < clo || (int64_t)base + 64 * C - 1 > nA;
+            if (edge) cell_pass(std::true_type());
+            else cell_pass(std::false_type());
+            int lmin0 = 1, lmax0 = 0;
+            if (lr >= 0) { lmin0 = base + fr; lmax0 = base + lr; }
+            // record of antidiagonal k: rows of the lanes covering [lo, hi]
+            {
+                int l_lo = 0, l_hi = -1;
+                if (nonempty) {
+                    l_lo = (lo - base) / C;
+                    l_hi = (hi - base) / C;
+                }
+                const uint32_t ng = (uint32_t)(l_hi - l_lo + 1);
+                const uint32_t need = 8 + 4 * ng;
+                if (fill + need + 4u * (uint32_t)(k - k0 + 1) > CH) {
+                    const int nc = pool_alloc(pool, hint, lane);
+                    if (nc < 0) { status = HALF_ARENA_OVERFLOW; break; }
+                    if (lane == 0) {
+                        ((uint32_t *)cb)[2] = fill;
+                        uint32_t *nh = (uint32_t *)chunk(nc);
+                        nh[0] = (uint32_t)cur;
+                        nh[1] = (uint32_t)k;
+                    }
+                    cur = nc;
+                    cb = chunk(nc);
+                    k0 = k;
+                    fill = 16;
+                }
+                uint32_t *rec = (uint32_t *)(cb + fill);
+                if (lane >= l_lo && lane <= l_hi) rec[2 + lane - l_lo] = nib;
+                if (lane == 0) {
+                    rec[0] = nonempty ? (uint32_t)(base + l_lo * C) : 0u;
+                    rec[1] = rec_head_word(ng, C);
+                    *(uint32_t *)(cb + CH - 4u * (uint32_t)(k - k0 + 1)) = fill;
+                }
+                fill += need;
+                if (nonempty) cells += (uint64_t)(hi - lo + 1);
+            }
+            const int admax = wave_max_dpp(lmax);
+            if (admax > best) {
+                int row = 0x7fffffff;
+#pragma unroll
+                for (int r = 0; r < C; r++) {
+                    const uint64_t m = __ballot(Hn[r] == admax);
+                    if (m) row = min(row, __builtin_ctzll(m) * C + r);
+                }
+                best = admax;
+                bi = base + row;
+                bj = k - bi;
+                if (best >= SFE_SCORE_LIMIT) { status = HALF_SCORE_RANGE; break; }
+            }
+#pragma unroll
+            for (int r = 0; r < C; r++) {
+                H2[r] = H1[r];
+                H1[r] = Hn[r];
+                E1[r] = En[r];
+                F1[r] = Fn[r];
+            }
+            const int64_t bnew = (int64_t)k - base;
+            while (b_hi < bnew + 64) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
+            {
+                const int carry = dpp_shr1(S::bsel(bcode(bnew)), Bs[C - 1]);
+#pragma unroll
+                for (int r = C - 1; r > 0; r--) Bs[r] = Bs[r - 1];
+                Bs[0] = carry;
+            }
+            const bool stop = (lmin0 > lmax0) && (lmin1 > lmax1);
+            lmin2 = lmin1; lmax2 = lmax1;
+            lmin1 = lmin0; lmax1 = lmax0;
+            if (stop) break;
+        }
+
+        if (cur >= 0 && lane == 0) ((uint32_t *)cb)[2] = fill;
+
+        // ---- traceback from the end cell, codes read through LDS ----
+        uint64_t run_off = 0;
+        uint32_t nruns = 0;
+        if (status == HALF_OK && (bi != 0 || bj != 0)) {
+            const uint32_t RC = (CH - 16) / 4;       // runs per chunk of the run chain
+            __syncthreads();
+            const int64_t kk0 = (int64_t)bi + bj;
+            bool bad = false, oom = false;
+            // chunks holding only antidiagonals past the end cell go back at once
+            while (cur >= 0 && (int64_t)hdr(cur, 1) > kk0) {
+                const int pc = (int)hdr(cur, 0);
+                pool_free(pool, cur, lane);
+                cur = pc;
+            }
+            if (cur < 0) bad = true;
+            else { cb = chunk(cur); k0 = (int)hdr(cur, 1); fill = hdr(cur, 2); }
+            int rcur = -1;
+            uint32_t rfill = RC, cnt = 0;
+            auto emit = [&](uint32_t w) {
+                if (rfill == RC) {
+                    const int nc = pool_alloc(pool, hint, lane);
+                    if (nc < 0) return false;
+                    if (lane == 0) ((uint32_t *)chunk(nc))[0] = (uint32_t)rcur;
+                    rcur = nc;
+                    rfill = 0;
+                }
+                if (lane == 0) ((uint32_t *)(chunk(rcur) + 16))[rfill] = w;
+                rfill++;
+                cnt++;
+                return true;
+            };
+            int64_t ic = -1;                 // antidiagonal of tb_idx[0] (-1: nothing staged)
+            int64_t rc = -1;                 // chunk offset of tb_rec[0]
+            int ti = bi, tj = bj, state = 0;
+            uint32_t cur_op = 0xffffffffu, cur_len = 0;
+            int64_t guard = 2 * kk0 + 4;
+            while (!bad && !(ti == 0 && tj == 0 && state == 0)) {
+                if (--guard < 0 || ti < 0 || tj < 0) { bad = true; break; }
+                const int64_t kk = (int64_t)ti + tj;
+                if (kk < 1) { bad = true; break; }
+                while (kk < k0) {            // the walk left this chunk
+                    const int pc = (int)hdr(cur, 0);
+                    pool_free(pool, cur, lane);
+                    cur = pc;
+                    if (cur < 0) break;
+                    cb = chunk(cur);
+                    k0 = (int)hdr(cur, 1);
+                    fill = hdr(cur, 2);
+                    ic = -1;
+                    rc = -1;
+                }
+                if (cur < 0) { bad = true; break; }
+                if (ic < 0 || kk < ic) {
+                    ic = max((int64_t)k0, kk - TB_IDX + 1);
+                    __syncthreads();
+                    for (int q = lane; q < TB_IDX; q += 64) {
+                        const int64_t kq = ic + q;
+                        tb_idx[q] = kq <= kk ? *(const uint32_t *)(cb + CH - 4u * (uint32_t)(kq - k0 + 1)) : 0u;
+                    }
+                    __syncthreads();
+                }
+                const uint32_t rec = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_idx[kk - ic]);
+                if (rec < 16 || rec + 8 > fill) { bad = true; break; }
+                const int64_t wend = min(rc + 4 * TB_REC, (int64_t)fill);   // end of the staged bytes
+                if (rc < 0 || (int64_t)rec < rc || ((int64_t)rec + 8 + 4 * 64 > wend && wend < (int64_t)fill)) {
+                    // stage the record bytes that end just past a full record at `rec`
+                    const int64_t top = min((int64_t)rec + 8 + 4 * 64, (int64_t)fill);
+                    rc = max((int64_t)0, top - 4 * TB_REC);
+                    __syncthreads();
+                    for (int q = lane; q < TB_REC; q += 64) {
+                        const int64_t bo = rc + 4 * q;
+                        tb_rec[q] = bo + 4 <= (int64_t)fill ? *(const uint32_t *)(cb + bo) : 0u;
+                    }
+                    __syncthreads();
+                }
+                const uint32_t w0 = (uint32_t)(rec - rc) >> 2;
+                const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0]);
+                const uint32_t hw = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0 + 1]);
+                const uint32_t ng = hw & 0xffffffu, G = hw >> 24;
+                const uint32_t idx = (uint32_t)(ti - (int)r0);
+                if ((uint32_t)ti < r0 || G == 0 || G > 8 || idx / G >= ng || w0 + 2 + idx / G >= TB_REC) {
+                    bad = true;
+                    break;
+                }
+                const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0 + 2 + idx / G]);
+                const uint32_t code = (word >> (4 * (idx % G))) & 15u;
+                uint32_t op;
+                if (state == 0) {
+                    const uint32_t src = code & 3u;
+                    if (src == 1) { state = 1; continue; }
+                    if (src == 2) { state = 2; continue; }
+                    op = 0; ti--; tj--;
+                } else if (state == 1) {
+                    op = 1;
+                    if (code & 4u) state = 0;
+                    tj--;
+                } else {
+                    op = 2;
+                    if (code & 8u) state = 0;
+                    ti--;
+                }
+                if (op == cur_op) {
+                    cur_len++;
+                } else {
+                    if (cur_len) {
+                        if (cnt >= (uint32_t)kk0) { bad = true; break; }     // runs <= operations <= bi + bj
+                        if (!emit((cur_len << 2) | cur_op)) { oom = true; break; }
+                    }
+                    cur_op = op;
+                    cur_len = 1;
+                }
+            }
+            if (!bad && !oom && cur_len) {
+                if (cnt >= (uint32_t)kk0) bad = true;
+                else if (!emit((cur_len << 2) | cur_op)) oom = true;
+            }
+            if (bad) status = HALF_TRACE_ERROR;
+            else if (oom) status = HALF_ARENA_OVERFLOW;
+            if (status == HALF_OK) {
+                unsigned long long off = 0;
+                if (lane == 0) off = atomicAdd(ra.head, (unsigned long long)cnt);
+                const uint32_t olo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off);
+                const uint32_t ohi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(off >> 32));
+                off = ((unsigned long long)ohi << 32) | olo;
+                if (off + cnt > ra.cap) {
+                    status = HALF_RUNS_OVERFLOW;
+                } else {
+                    // the run chain holds runs [j * RC, ...) in its j-th chunk, last chunk first
+                    __syncthreads();
+                    int64_t j = ((int64_t)cnt + RC - 1) / RC - 1;
+                    for (int c = rcur; c >= 0 && j >= 0; j--) {
+                        const uint64_t lo = (uint64_t)j * RC;
+                        const uint32_t m = (uint32_t)min((uint64_t)RC, (uint64_t)cnt - lo);
+                        const uint32_t *src = (const uint32_t *)(chunk(c) + 16);
+                        for (uint32_t q = lane; q < m; q += 64) ra.base[off + lo + q] = src[q];
+                        const int pc = (int)hdr(c, 0);
+                        pool_free(pool, c, lane);
+                        c = pc;
+                    }
+                    rcur = -1;
+                    run_off = off;
+                    nruns = cnt;
+                }
+            }
+            free_chain(rcur);
+        }
+        free_chain(cur);
+        if (lane == 0) {
+            HalfResult o;
+            o.best = best;
+            o.i_end = bi;
+            o.j_end = bj;
+            o.status = status;
+            o.cells = cells;
+            o.tb_page = run_off;
+            o.tb_end = nruns;
+            o.k_last = (int32_t)min((int64_t)k, kmax);
+            res[tid] = o;
+        }
+        if (!PERSIST) break;
+    }
+}
+
+void launch_ydrop_fused(int cells_per_lane, bool perm, bool persistent, const HalfTask *tasks, WorkQueue wq,
+                        int64_t grid, SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, ChunkPool pool,
+                        RunArena ra, HalfResult *res, hipStream_t st) {
+    if (grid <= 0) return;
+#define SFE_LAUNCH(CC, PP, QQ) \
+    k_ydrop_fused<CC, PP, QQ><<<(unsigned)grid, 64, 0, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res)
+#define SFE_BY_C(PP, QQ)                                  \
+    do {                                                  \
+        if (cells_per_lane <= 4) SFE_LAUNCH(4, PP, QQ);   \
+        else if (cells_per_lane <= 6) SFE_LAUNCH(6, PP, QQ); \
+        else SFE_LAUNCH(8, PP, QQ);                       \
+    } while (0)
+    if (perm) {
+        if (persistent) SFE_BY_C(true, true); else SFE_BY_C(true, false);
+    } else {
+        if (persistent) SFE_BY_C(false, true); else SFE_BY_C(false, false);
+    }
+#undef SFE_BY_C
+#undef SFE_LAUNCH
+}
+
+int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool persistent) {
+    int nb = 0;
+    hipError_t err = hipSuccess;
+#define SFE_OCC(CC, PP, QQ) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ydrop_fused<CC, PP, QQ>, 64, 0)
+#define SFE_OCC_C(PP, QQ)                                 \
+    do {                                                  \
+        if (cells_per_lane <= 4) SFE_OCC(4, PP, QQ);      \
+        else if (cells_per_lane <= 6) SFE_OCC(6, PP, QQ); \
+        else SFE_OCC(8, PP, QQ);                          \
+    } while (0)
+    if (perm) {
+        if (persistent) SFE_OCC_C(true, true); else SFE_OCC_C(true, false);
+    } else {
+        if (persistent) SFE_OCC_C(false, true); else SFE_OCC_C(false, false);
+    }
+#undef SFE_OCC_C
+#undef SFE_OCC
+    return err == hipSuccess ? nb : -1;
+}
+
+}  // namespace sfe

@@ -87,13 +87,49 @@ struct HalfTask {
 #define HALF_WIDTH_OVERFLOW 1
 #define HALF_ARENA_OVERFLOW 2
 #define HALF_SCORE_RANGE 3      // a score reached 2^29 (or the band 2^30 antidiagonals)
+#define HALF_RUNS_OVERFLOW 4    // the run arena is full
+#define HALF_TRACE_ERROR 5      // traceback codes inconsistent (internal error)
 
 struct HalfResult {
     int32_t best, i_end, j_end, status;
     uint64_t cells;
-    uint64_t tb_page;       // device address of the allocation holding the end cell's record
-    uint32_t tb_end;        // offset of that record in the allocation
+    // workgroup kernel: device address of the allocation holding the end
+    // cell's record, and the record's offset in it; fused kernel: first run
+    // in the run arena, and the number of runs
+    uint64_t tb_page;
+    uint32_t tb_end;
     int32_t k_last;         // last antidiagonal computed
+};
+
+// Chunk pool of the fused kernel: `nchunks` chunks of 2^shift bytes at base,
+// bit c of bits[] set while chunk c is held by a half.  A half keeps its
+// traceback codes in a backward-linked chain of chunks, each laid out as
+//   header (16 bytes): u32 previous chunk of the chain (~0 for the first),
+//     u32 k0 = antidiagonal of its first record, u32 bytes of records used;
+//   records upward from offset 16 (the arena record format above);
+//   index downward from the end: u32 at 2^shift - 4*(x+1) = offset of the
+//     record of antidiagonal k0 + x.
+// Edit runs being traced go to a second chain (header u32 previous chunk,
+// runs from offset 16).
+struct ChunkPool {
+    uint8_t *base;
+    uint32_t *bits;
+    int32_t nwords;         // nchunks / 32
+    int32_t shift;
+};
+
+// Edit runs of traced halves (u32 len << 2 | op), handed out by a device counter.
+struct RunArena {
+    uint32_t *base;
+    uint64_t cap;           // in runs
+    unsigned long long *head;
+};
+
+// Halves ids[0 .. n) (or 0 .. n with ids null), claimed in order through *head.
+struct WorkQueue {
+    const int32_t *ids;
+    int64_t n;
+    unsigned int *head;
 };
 
 // Traceback pointer arena.  Allocations of one or more ARENA_PAGE pages, a

@@ -63,8 +63,12 @@ __global__ void k_hsp_compact(const sfe_hsp *h, const uint32_t *perm, const uint
 // gapped stage (k_extend.hip)
 void launch_make_tasks(const ExtItem *items, int64_t n, const UnitDesc *units, int64_t nt, HalfTask *tasks,
                        hipStream_t st);
-void launch_ydrop(int cells_per_lane, bool perm, const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T,
-                  SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, Arena arena, HalfResult *res, hipStream_t st);
+// fused extension + traceback (k_fused.hip); plain: grid = wq.n blocks, one
+// half each; persistent: `grid` waves pulling halves from the queue
+void launch_ydrop_fused(int cells_per_lane, bool perm, bool persistent, const HalfTask *tasks, WorkQueue wq,
+                        int64_t grid, SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, ChunkPool pool,
+                        RunArena ra, HalfResult *res, hipStream_t st);
+int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool persistent);
 void launch_ydrop_ring(const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T, SeqSetView Qp,
                        SeqSetView Qm, const ScoreDesc &sc, Arena arena, int32_t *ring, int32_t cap_rows,
                        HalfResult *res, hipStream_t st);

@@ -241,24 +241,39 @@ def compare_alignments(alns, ops, ref):
         assert np.array_equal(g, oracle.aln_ops(ref, x)), x
 
 
-@pytest.mark.parametrize("K,cpl,policy", [(1, 0, 1), (7, 0, 1), (64, 0, 1), (1000, 0, 1), (64, 4, 1), (64, 8, 1),
-                                          (1, 0, 0), (3, 0, 0), (0, 0, 0), (0, 4, 0)])
-def test_align_parity(ctx, align_case, K, cpl, policy):
-    log(f"align parity K={K} cells_per_lane={cpl} policy={policy}")
+PLAIN, PERSIST = sfe.SFE_SCHED_PLAIN, sfe.SFE_SCHED_PERSISTENT
+
+
+@pytest.mark.parametrize("K,cpl,policy,schedule", [
+    (1, 0, 1, PLAIN), (7, 0, 1, PLAIN), (64, 0, 1, PLAIN), (1000, 0, 1, PLAIN), (64, 4, 1, PLAIN), (64, 8, 1, PLAIN),
+    (1, 0, 0, PLAIN), (3, 0, 0, PLAIN), (0, 0, 0, PLAIN), (0, 4, 0, PLAIN),
+    (1, 0, 1, PERSIST), (64, 0, 1, PERSIST), (0, 0, 0, PERSIST), (0, 8, 0, PERSIST)])
+def test_align_parity(ctx, align_case, K, cpl, policy, schedule):
+    log(f"align parity K={K} cells_per_lane={cpl} policy={policy} schedule={schedule}")
     T, Q, ref = align_case
     idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
     alns, ops, st = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), round_k=K, max_cells_per_lane=cpl,
-                                  policy=policy)
+                                  policy=policy, schedule=schedule)
     assert alns.shape[0] >= 3
     compare_alignments(alns, ops, ref)
     assert st["committed"] == alns.shape[0]
     assert st["extensions"] >= ref["n_extensions"]
 
 
-def test_align_tiny_arena_reruns(ctx, align_case):
-    """A small traceback arena forces re-runs; results must not change."""
-    log("align with a tiny arena")
+@pytest.mark.parametrize("arena,schedule", [(1 << 20, PLAIN), (1 << 20, PERSIST), (3 << 18, PLAIN)])
+def test_align_tiny_arena_reruns(align_case, arena, schedule):
+    """A small traceback arena (fresh context, so the run arena starts small
+    too) forces slice-overflow re-runs and run-arena regrowth; results must
+    not change."""
+    log(f"align with a {arena}-byte arena, schedule={schedule}")
     T, Q, ref = align_case
-    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
-    alns, ops, st = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), round_k=64, arena_bytes=1 << 20)
-    compare_alignments(alns, ops, ref)
+    c = sfe.sfe_ctx_create(0)
+    try:
+        idx = sfe.sfe_build_index(c, T, PATTERN, 1, 1)
+        alns, ops, st = sfe.sfe_align(c, idx, Q, dict(synth.SCORING), round_k=0, policy=0, arena_bytes=arena,
+                                      schedule=schedule)
+        compare_alignments(alns, ops, ref)
+        assert st["overflow_reruns"] > 0
+        idx.close()
+    finally:
+        c.close()
