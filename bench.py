@@ -64,12 +64,12 @@ def cpu_baseline(T, Q, sc, sample_bp: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mid", choices=["mid", "small"])
     ap.add_argument("--round-k", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
-    ap.add_argument("--cpu-sample-bp", type=int, default=60_000)
+    ap.add_argument("--cpu-sample-bp", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -127,8 +127,9 @@ def main():
     dominant = "ydrop" if yd_ms >= sx_ms else "seed_xdrop"
     if dominant == "ydrop":
         achieved = yd_ops_s / 1e12
-        note = (f"k_ydrop_wave: {YDROP_OPS_PER_CELL} int32 ops per DP cell x {yd_cells / max(yd_launches, 1):.3g} "
-                f"cells per launch / {yd_ms / max(yd_launches, 1):.3f} ms average launch")
+        note = (f"k_ydrop_fused (extension + traceback): {YDROP_OPS_PER_CELL} int32 ops per DP cell x "
+                f"{yd_cells / max(yd_launches, 1):.3g} cells per launch / {yd_ms / max(yd_launches, 1):.3f} ms "
+                f"average launch ({yd_launches} launches)")
     else:
         achieved = sx_ops_s / 1e12
         note = (f"k_seed_xdrop: {XDROP_OPS_PER_COLUMN} int32 ops per scanned column x "
@@ -156,7 +157,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": desc, "schedule": "plain" if args.schedule == 0 else "persistent",
-                   "round_k": args.round_k or 256},
+                   "policy": "defer", "round_k": args.round_k or (1 << 20)},
         "gapped_gcups": round(s["cells"] / (s["ms_extend"] / 1e3) / 1e9, 3) if s["ms_extend"] > 0 else None,
         "gapped_gcups_kernel": round(yd_cells / (yd_ms / 1e3) / 1e9, 3) if yd_ms > 0 else None,
         "seed_hits_per_s": round(s["seed_hits"] / (s["ms_seed_xdrop"] / 1e3), 1) if s["ms_seed_xdrop"] > 0 else None,

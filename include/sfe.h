@@ -137,7 +137,10 @@ typedef struct {
     int32_t max_cells_per_lane; /* 0 = automatic (6); 4, 6 or 8 rows per lane in the first band window */
     int32_t policy;         /* SFE_POLICY_* */
     int32_t pad;
-    int64_t arena_bytes;    /* traceback pointer arena per batch; 0 = default */
+    int64_t arena_bytes;    /* device memory for traceback codes of the halves in flight,
+                               allocated once per context; 0 = 32 GiB.  A batch whose halves
+                               need more at once runs with fewer in flight; a single half
+                               that needs more makes the arena grow. */
 } sfe_align_opts;
 
 typedef struct {

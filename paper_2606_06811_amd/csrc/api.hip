@@ -79,6 +79,7 @@ struct sfe_ctx {
     DBuf sched_d;                       // u64 run-arena head, u32 work-queue head
     DBuf busy_d;                        // bitmap of the traceback chunk pool
     int cu_count = 0;
+    int32_t pool_avail = 0;             // host copy of the pool's initial free count
     // traceback arenas: arena 0 holds the fused kernel's chunk pool and the
     // workgroup kernel's pages; a workgroup-kernel half that finds its arena
     // full is re-run into the next one (allocated twice as large on demand)
@@ -327,6 +328,9 @@ struct BatchResult {
     int64_t reruns = 0;
 };
 
+// Default traceback arena: 32 GiB of the 288 GB of HBM, allocated on first use.
+const int64_t kDefaultArena = (int64_t)32 << 30;
+
 // Arena 0 of `bytes` (kept if already that large); arenas 1.. grow from it.
 void ensure_arena(sfe_ctx *c, int64_t bytes) {
     if (c->arenas.empty()) c->arenas.emplace_back(new DBuf);
@@ -399,7 +403,10 @@ ChunkPool make_pool(sfe_ctx *c) {
     if (nwords < 1) fail(SFE_EINVAL, "traceback arena too small");
     uint32_t *bits = (uint32_t *)c->busy_d.ensure((size_t)nwords * 4);
     HIPCHK(hipMemsetAsync(bits, 0, (size_t)nwords * 4, c->stream));
-    return ChunkPool{c->arenas[0]->as<uint8_t>(), bits, nwords, shift};
+    int32_t *avail = (int32_t *)(c->sched_d.as<uint8_t>() + 16);
+    c->pool_avail = nwords * 32;
+    HIPCHK(hipMemcpyAsync(avail, &c->pool_avail, 4, hipMemcpyHostToDevice, c->stream));
+    return ChunkPool{c->arenas[0]->as<uint8_t>(), bits, avail, nwords, shift};
 }
 
 // Extends the 2n halves of the batch items and traces back every half that
@@ -430,6 +437,7 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     std::vector<uint32_t> nrun(nh, 0);
     std::vector<int> stage(nh, cells_per_lane < 8 ? 0 : 1), level(nh, 0);
     c->sched_d.ensure(64);
+    if (c->arenas.empty() || !c->arenas[0]->p) ensure_arena(c, kDefaultArena);
     set_run_head(c, 0);
     RunArena ra = run_arena(c, std::max<uint64_t>(1 << 12, (uint64_t)c->arena_bytes / 256), 0);
     std::vector<int32_t> todo;
@@ -737,7 +745,6 @@ sfe_status sfe_ctx_create(int device, void *hip_stream, sfe_ctx **out) {
         HIPCHK(hipEventCreate(&c->ev0));
         HIPCHK(hipEventCreate(&c->ev1));
         c->counters.ensure(64);
-        ensure_arena(c, (int64_t)8 << 30);
         sync(c);
     });
     if (st != SFE_OK) {
@@ -958,7 +965,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         int64_t nch = (int64_t)L.chunks.size();
         int64_t nraw = 0;
         if (nch > 0) {
-            uint64_t capraw = std::max<uint64_t>(c->hsp_raw.n / sizeof(sfe_hsp), 1u << 20);
+            uint64_t capraw = std::max<uint64_t>(c->hsp_raw.n / sizeof(sfe_hsp), 1u << 23);
             for (;;) {
                 sfe_hsp *raw = (sfe_hsp *)c->hsp_raw.ensure(capraw * sizeof(sfe_hsp));
                 unsigned long long *cnt = c->counters.as<unsigned long long>();

@@ -24,13 +24,27 @@ namespace sfe {
 #define TB_IDX 512            // index entries staged in LDS during traceback
 #define TB_REC 1024           // record words staged in LDS during traceback
 
-// Takes a free chunk (wave-uniform; -1 if none was found).  Lanes read 64
-// bitmap words at once; lane 0 claims the first free bit seen.  The fence
+// Takes a free chunk (wave-uniform; -1 if none came free in time).  A wave
+// first reserves one of the `avail` free chunks -- when none is left it
+// sleeps and retries for a bounded time, as other waves return chunks -- and
+// then looks for a clear bit: lanes read 64 bitmap words at once, lane 0
+// claims the first clear bit seen.  A reservation guarantees a clear bit
+// exists (a release clears its bit before it increments avail).  The fence
 // after a claim (and before a release) orders the chunk's previous contents
 // against its new owner across the L2s of the chip.
 __device__ __forceinline__ int pool_alloc(const ChunkPool &p, int &hint, int lane) {
-    const int tries = 2 * (p.nwords / 64) + 16;
-    for (int t = 0; t < tries; t++) {
+    bool reserved = false;
+    for (int wait = 0; wait < 8192; wait++) {
+        int got = 0;
+        if (lane == 0) {
+            got = atomicSub(p.avail, 1) > 0;
+            if (!got) atomicAdd(p.avail, 1);
+        }
+        if (__builtin_amdgcn_readfirstlane(got)) { reserved = true; break; }
+        __builtin_amdgcn_s_sleep(127);
+    }
+    if (!reserved) return -1;
+    for (int t = 0; t < (1 << 20); t++) {
         const int w = (hint + lane) % p.nwords;
         const uint32_t word = __hip_atomic_load(&p.bits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t m = __ballot(word != 0xffffffffu);
@@ -51,12 +65,17 @@ __device__ __forceinline__ int pool_alloc(const ChunkPool &p, int &hint, int lan
             return wl * 32 + __builtin_ctz(bit);
         }
     }
+    if (lane == 0) atomicAdd(p.avail, 1);     // not reached while reservations hold
     return -1;
 }
 
 __device__ __forceinline__ void pool_free(const ChunkPool &p, int c, int lane) {
     __threadfence();
-    if (lane == 0) atomicAnd(&p.bits[c >> 5], ~(1u << (c & 31)));
+    if (lane == 0) {
+        atomicAnd(&p.bits[c >> 5], ~(1u << (c & 31)));
+        __threadfence();
+        atomicAdd(p.avail, 1);
+    }
 }
 
 template <int C, bool PERM, bool PERSIST>

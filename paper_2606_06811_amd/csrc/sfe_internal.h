@@ -114,6 +114,7 @@ struct HalfResult {
 struct ChunkPool {
     uint8_t *base;
     uint32_t *bits;
+    int32_t *avail;         // free chunks not yet reserved
     int32_t nwords;         // nchunks / 32
     int32_t shift;
 };
