@@ -141,6 +141,9 @@ typedef struct {
                                allocated once per context; 0 = 32 GiB.  A batch whose halves
                                need more at once runs with fewer in flight; a single half
                                that needs more makes the arena grow. */
+    const struct sfe_model *model; /* NULL, or a cost model: with SFE_SCHED_PERSISTENT the halves of
+                               each batch are queued longest-predicted first.  Never changes
+                               the output. */
 } sfe_align_opts;
 
 typedef struct {
@@ -160,6 +163,9 @@ typedef struct {
     double ms_seed_xdrop, ms_hsp_set, ms_extend, ms_total;   /* host wall clock per stage */
     double ms_ydrop_kernel;     /* sum of HIP-event durations of the gapped-extension launches */
     double ms_seed_xdrop_kernel;/* sum of HIP-event durations of the fused seed + X-drop launches */
+    int64_t predicted_halves;   /* halves queued by a cost model */
+    int64_t mispredicted_halves;/* of those: predicted log2(1 + cells) off by more than 2 */
+    double ms_predict;          /* host wall clock of features + model inference */
 } sfe_stats;
 
 /* Context on `device` using `hip_stream` (a hipStream_t, or NULL for a
@@ -220,6 +226,59 @@ sfe_status sfe_align(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries,
                      const sfe_scoring *sc, const sfe_align_opts *opts,
                      sfe_aln *out, int64_t cap, int64_t *n_alns,
                      uint32_t *ops, int64_t ops_cap, int64_t *n_ops, sfe_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Learned cost model.  The cost of an anchor-half is unknown until it has run
+ * (Sec. 8) and sorting work by expected size up front is the load-balancing
+ * step Sec. 9 leaves open; this library predicts it with a small MLP of its
+ * own design.  Parameters (SFE_MLP_NPARAMS floats, FP32 master copy), in this
+ * order, row-major out x in: W1 64x16, b1 64, W2 64x64, b2 64, W3 64x64, b3 64,
+ * W4 4x64, b4 4.  Forward: parameters and inputs rounded to BF16 (nearest even),
+ * A = bf16(relu(X W^T + b)) per hidden layer with FP32 accumulation, linear
+ * FP32 output.  Loss: mean of (Y - T)^2 over the batch and the 4 outputs;
+ * back-propagated signals are rounded to BF16 before each product, gradients
+ * accumulate in FP32; Adam (0.9, 0.999, 1e-8) on the master weights.
+ * Outputs / targets per HSP: log2(1 + cells) and log2(1 + i* + j*) of the
+ * forward half, then the same of the backward half.
+ *
+ * Features (SFE_MLP_NFEAT floats per HSP; neighbours are the other HSPs of
+ * the same call with the same query and strand; anchors per the HSP anchor
+ * rule of sfe_gapped_ydrop; windows clip at sequence ends):
+ *   0 score/4096          1 log2(1+len)/16       2 identical columns/len
+ *   3 transition columns/len  4 other mismatch or N columns/len
+ *   5 (t0-q0)/target length   6 strand            7 anchor t/target length
+ *   8 anchor q/query length   9, 10 GC fraction of the non-N bases within
+ *   1000 of the anchor (target, query)  11 log2(1+#neighbours with |dt| <= 5000
+ *   and |d diagonal| <= 64)/8  12 log2(1+#neighbours with |dt| <= 10000)/8
+ *   13 log2(1+smallest dt in (0, 10000] with |d diagonal| <= 64)/16, else 1
+ *   14 the same upstream (dt < 0)   15 soft-masked fraction of the target
+ *   within 1000 of the anchor  (dt = anchor t difference). */
+#define SFE_MLP_NFEAT 16
+#define SFE_MLP_NOUT 4
+#define SFE_MLP_NPARAMS 9668
+typedef struct sfe_model sfe_model;
+
+/* features: n x SFE_MLP_NFEAT (host or device). */
+sfe_status sfe_hsp_features(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries, int32_t nq,
+                            const sfe_hsp *hsps, int64_t n, float *features);
+/* Training log of the plain pipeline: the features of each HSP and the
+ * targets (n x SFE_MLP_NOUT) of its gapped extension. */
+sfe_status sfe_extension_log(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries, int32_t nq,
+                             const sfe_hsp *hsps, int64_t n, const sfe_scoring *sc,
+                             float *features, float *targets);
+/* A model on ctx's device with the given initial parameters (host or device). */
+sfe_status sfe_model_create(sfe_ctx *ctx, const float *params, sfe_model **out);
+void sfe_model_destroy(sfe_model *m);
+sfe_status sfe_model_params(const sfe_model *m, float *params);
+/* y (n x SFE_MLP_NOUT) from x (n x SFE_MLP_NFEAT). */
+sfe_status sfe_model_predict(sfe_model *m, const float *x, int64_t n, float *y);
+/* Gradient (SFE_MLP_NPARAMS) and loss of the whole set (x, t) as one batch. */
+sfe_status sfe_model_grad(sfe_model *m, const float *x, const float *t, int64_t n, float *grad, float *loss);
+/* Adam steps over the batches of `order` (n_order sample ids in [0, n),
+ * consumed `batch` at a time, a short last batch used as is); losses (one per
+ * step, may be NULL) receives each batch's loss before its update. */
+sfe_status sfe_model_train(sfe_model *m, const float *x, const float *t, int64_t n, const int32_t *order,
+                           int64_t n_order, int32_t batch, float lr, float *losses);
 
 const char *sfe_status_str(sfe_status s);
 const char *sfe_last_error(const sfe_ctx *ctx);

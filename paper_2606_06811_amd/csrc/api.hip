@@ -5,6 +5,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <functional>
 #include <memory>
@@ -77,6 +78,7 @@ struct sfe_ctx {
     DBuf hsp_raw, hsp_pass, hsp_sorted;
     DBuf items_d, tasks_d, hres_d, ids_d, aln_d, runoff_d, runs_d, nruns_d, opsoff_d, ops_d, nops_d, ring_d;
     DBuf sched_d;                       // u64 run-arena head, u32 work-queue head
+    DBuf feat_unit, feat_key, feat_key2, feat_ids, feat_ids2, feat_okey, feat_range, feat_hsp, feat_out, feat_pred;
     DBuf busy_d;                        // bitmap of the traceback chunk pool
     int cu_count = 0;
     int32_t pool_avail = 0;             // host copy of the pool's initial free count
@@ -103,6 +105,13 @@ struct sfe_index {
     DBuf offsets, pos;
     int64_t n_valid = 0;
     int32_t max_abs_sub_guard = 0;
+};
+
+struct sfe_model {
+    sfe_ctx *ctx = nullptr;
+    DBuf master, m, v, p16;             // FP32 master weights, Adam moments, BF16 copy
+    DBuf part, sse, loss, x, t, ids, y, grad;
+    int64_t step = 0;                   // Adam steps taken
 };
 
 namespace {
@@ -325,7 +334,9 @@ __global__ void k_hsp_filter(const sfe_hsp *__restrict__ in, int64_t n, int32_t 
 struct BatchResult {
     std::vector<sfe_aln> alns;        // per item; ops_offset indexes `ops`, ops_len set for passing items
     std::vector<uint32_t> ops;
+    std::vector<HalfResult> halves;   // per half (2x forward, 2x+1 backward of item x)
     int64_t reruns = 0;
+    int64_t predicted = 0, mispredicted = 0;
 };
 
 // Default traceback arena: 32 GiB of the 288 GB of HBM, allocated on first use.
@@ -416,8 +427,12 @@ ChunkPool make_pool(sfe_ctx *c) {
 // separate traceback.  A half that finds the chunk pool dry is re-run with
 // four times fewer waves in flight (persistent schedule); with one wave, the
 // arena grows.
+//
+// cost (optional): predicted log2(1 + cells) of every half.  The halves then
+// start longest-predicted first (for the persistent schedule, the order of its
+// queue); the output does not depend on it.
 void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &items, const ScoreDesc &sc,
-               int cells_per_lane, int schedule, BatchResult &out) {
+               int cells_per_lane, int schedule, BatchResult &out, const std::vector<float> *cost = nullptr) {
     const int64_t n = (int64_t)items.size();
     out.alns.assign(n, sfe_aln{});
     out.ops.clear();
@@ -442,7 +457,16 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     RunArena ra = run_arena(c, std::max<uint64_t>(1 << 12, (uint64_t)c->arena_bytes / 256), 0);
     std::vector<int32_t> todo;
     size_t ai = 0;                      // workgroup-kernel arena
-    bool all = true;
+    bool all = true, first = true;
+    out.reruns = 0;
+    out.predicted = out.mispredicted = 0;
+    if (cost) {
+        if ((int64_t)cost->size() != nh) fail(SFE_EINTERNAL, "cost vector size");
+        todo.resize(nh);
+        for (int64_t h = 0; h < nh; h++) todo[h] = (int32_t)h;
+        std::stable_sort(todo.begin(), todo.end(), [&](int32_t a, int32_t b) { return (*cost)[a] > (*cost)[b]; });
+        all = false;
+    }
     for (;;) {
         std::vector<int32_t> group, rest;
         int sg = 1 << 20, lv = 1 << 20;
@@ -462,8 +486,9 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
             copy_in(c, idd, group.data(), group.size() * 4);
             ids = idd;
             cnt = (int64_t)group.size();
-            out.reruns += cnt;
+            if (!first) out.reruns += cnt;
         }
+        first = false;
         const bool fused = sg <= 1;
         int64_t nwaves = 0;
         uint64_t chunk_bytes = 0;
@@ -579,6 +604,13 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         todo.swap(next);
         if (todo.empty()) break;
     }
+    if (cost) {
+        for (int64_t h = 0; h < nh; h++) {
+            out.predicted++;
+            if (std::fabs((double)(*cost)[h] - std::log2(1.0 + (double)hr[h].cells)) > 2.0) out.mispredicted++;
+        }
+    }
+    out.halves = hr;
     sfe_aln *aln_d = (sfe_aln *)c->aln_d.ensure((size_t)n * sizeof(sfe_aln));
     launch_assemble(items_d, n, c->units_d.as<UnitDesc>(), hres, T, Qp, Qm, sc, aln_d, c->stream);
     copy_out(c, out.alns.data(), aln_d, (size_t)n * sizeof(sfe_aln));
@@ -623,6 +655,50 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         a.ops_len = nops[p];
         out.ops.insert(out.ops.end(), ops_all.begin() + ops_off[p], ops_all.begin() + ops_off[p] + nops[p]);
     }
+}
+
+// Features (n x 16, device) of n device HSPs; the units of L give each
+// (query, strand) its sequence; neighbours are HSPs of the same unit.
+void compute_features(sfe_ctx *c, const sfe_index *ix, const QueryLayout &L, int32_t nq, const sfe_hsp *h, int64_t n,
+                      float *F) {
+    if (n <= 0) return;
+    std::vector<int32_t> unit_of(2 * (size_t)std::max(nq, 1), -1);
+    for (size_t u = 0; u < L.units.size(); u++) unit_of[2 * L.units[u].query_id + L.units[u].strand] = (int32_t)u;
+    int32_t *uo = (int32_t *)c->feat_unit.ensure(unit_of.size() * 4);
+    copy_in(c, uo, unit_of.data(), unit_of.size() * 4);
+    uint64_t *key = (uint64_t *)c->feat_key.ensure((size_t)n * 8);
+    uint64_t *key2 = (uint64_t *)c->feat_key2.ensure((size_t)n * 8);
+    uint32_t *ids = (uint32_t *)c->feat_ids.ensure((size_t)n * 4);
+    uint32_t *order = (uint32_t *)c->feat_ids2.ensure((size_t)n * 4);
+    uint32_t *okey = (uint32_t *)c->feat_okey.ensure((size_t)n * 4);
+    const size_t NU = std::max<size_t>(L.units.size(), 1);
+    int64_t *range = (int64_t *)c->feat_range.ensure(2 * NU * 8);
+    launch_hsp_anchor_keys(h, n, uo, key, ids, c->stream);
+    size_t bytes = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, key, key2, ids, order, (int)n, 0, 64, c->stream));
+    c->cub_temp.ensure(bytes);
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(c->cub_temp.p, bytes, key, key2, ids, order, (int)n, 0, 64, c->stream));
+    HIPCHK(hipMemsetAsync(range, 0, 2 * NU * 8, c->stream));
+    launch_hsp_unit_ranges(h, uo, order, n, okey, range, range + NU, c->stream);
+    launch_hsp_features(h, n, uo, c->units_d.as<UnitDesc>(), ix->target.view(), ix->nt, c->qplus.view(),
+                        c->qminus.view(), order, okey, range, range + NU, F, c->stream);
+    HIPCHK(hipGetLastError());
+}
+
+// Host copies of caller HSPs, checked against the sequences.
+std::vector<sfe_hsp> checked_hsps(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq,
+                                  const sfe_hsp *hsps, int64_t n) {
+    std::vector<sfe_hsp> hh((size_t)n);
+    if (n == 0) return hh;
+    if (!hsps) fail(SFE_EINVAL, "null hsps");
+    HIPCHK(hipMemcpyAsync(hh.data(), hsps, (size_t)n * sizeof(sfe_hsp), hipMemcpyDefault, c->stream));
+    sync(c);
+    for (const sfe_hsp &h : hh) {
+        if (h.query_id >= (uint32_t)nq || h.strand > 1 || h.len == 0) fail(SFE_EINVAL, "bad hsp");
+        if ((int64_t)h.t0 + h.len > ix->nt || (int64_t)h.q0 + h.len > queries[h.query_id].length)
+            fail(SFE_EINVAL, "hsp outside its sequences");
+    }
+    return hh;
 }
 
 // Bounding boxes of committed alignments of one unit, binned by target position.
@@ -916,15 +992,10 @@ sfe_status sfe_gapped_ydrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *quer
         *n_ops = 0;
         if (n == 0) return;
         if (!hsps || !out) fail(SFE_EINVAL, "null hsps or output");
-        std::vector<sfe_hsp> hh((size_t)n);
-        HIPCHK(hipMemcpyAsync(hh.data(), hsps, (size_t)n * sizeof(sfe_hsp), hipMemcpyDefault, c->stream));
-        sync(c);
+        std::vector<sfe_hsp> hh = checked_hsps(c, ix, queries, nq, hsps, n);
         std::vector<ExtItem> items((size_t)n);
         for (int64_t x = 0; x < n; x++) {
             const sfe_hsp &h = hh[x];
-            if (h.query_id >= (uint32_t)nq || h.strand > 1 || h.len == 0) fail(SFE_EINVAL, "bad hsp");
-            if ((int64_t)h.t0 + h.len > ix->nt || (int64_t)h.q0 + h.len > queries[h.query_id].length)
-                fail(SFE_EINVAL, "hsp outside its sequences");
             uint32_t off = (h.len - 1) / 2;
             items[x] = ExtItem{h.t0 + off, h.q0 + off, (int32_t)(2 * h.query_id + h.strand), 0};
         }
@@ -1000,6 +1071,23 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         std::vector<sfe_hsp> hs((size_t)nh);
         copy_out(c, hs.data(), c->hsp_sorted.p, (size_t)nh * sizeof(sfe_hsp));
         sync(c);
+        // --- cost model: predicted size of every HSP's two halves ----------------------
+        std::vector<float> pred;
+        const bool learned = o.model && o.schedule == SFE_SCHED_PERSISTENT && nh > 0;
+        if (o.model && o.model->ctx->device != c->device) fail(SFE_EINVAL, "model lives on another device");
+        if (learned) {
+            const double tp = now_ms();
+            float *F = (float *)c->feat_out.ensure((size_t)nh * SFE_MLP_NFEAT * 4);
+            float *Y = (float *)c->feat_pred.ensure((size_t)nh * SFE_MLP_NOUT * 4);
+            compute_features(c, ix, L, nq, c->hsp_sorted.as<sfe_hsp>(), nh, F);
+            launch_mlp_forward(F, nh, o.model->p16.as<uint16_t>(), Y, c->stream);
+            HIPCHK(hipGetLastError());
+            pred.resize((size_t)nh * SFE_MLP_NOUT);
+            copy_out(c, pred.data(), Y, pred.size() * 4);
+            sync(c);
+            st.ms_predict = now_ms() - tp;
+        }
+        std::vector<float> cost;
         const double t3 = now_ms();
         // --- Alg. 3 rounds ------------------------------------------------------------
         std::vector<int32_t> unit_of(2 * (size_t)std::max(nq, 1), -1);
@@ -1083,7 +1171,17 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             if (items.empty()) break;
             st.rounds++;
             const double tr = now_ms();
-            run_batch(c, ix, items, sc, cpl, o.schedule, br);                 // phase 2: speculative extensions
+            if (learned) {
+                cost.resize(2 * items.size());
+                for (size_t x = 0; x < items.size(); x++) {
+                    const int64_t hx = per_unit[item_ref[x].first][item_ref[x].second];
+                    cost[2 * x] = pred[(size_t)hx * 4 + 0];
+                    cost[2 * x + 1] = pred[(size_t)hx * 4 + 2];
+                }
+            }
+            run_batch(c, ix, items, sc, cpl, o.schedule, br, learned ? &cost : nullptr);   // phase 2
+            st.predicted_halves += br.predicted;
+            st.mispredicted_halves += br.mispredicted;
             if (progress)
                 fprintf(stderr, "[sfe] batch %lld: %zu extensions, %.1f ms, %zu committed so far\n",
                         (long long)st.rounds, items.size(), now_ms() - tr, committed.size());
@@ -1180,6 +1278,185 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         copy_out(c, ops, oo.data(), oo.size() * 4);
         sync(c);
         if (stats) stats->ms_total = now_ms() - t0;
+    });
+}
+
+sfe_status sfe_hsp_features(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, const sfe_hsp *hsps,
+                            int64_t n, float *features) {
+    if (!c || !ix || n < 0) return SFE_EINVAL;
+    return guard(c, [&] {
+        QueryLayout L;
+        upload_queries(c, queries, nq, 3, ix->sd.span, L);
+        if (n == 0) return;
+        if (!features) fail(SFE_EINVAL, "null features");
+        std::vector<sfe_hsp> hh = checked_hsps(c, ix, queries, nq, hsps, n);
+        sfe_hsp *hd = (sfe_hsp *)c->feat_hsp.ensure((size_t)n * sizeof(sfe_hsp));
+        copy_in(c, hd, hh.data(), (size_t)n * sizeof(sfe_hsp));
+        float *F = (float *)c->feat_out.ensure((size_t)n * SFE_MLP_NFEAT * 4);
+        compute_features(c, ix, L, nq, hd, n, F);
+        copy_out(c, features, F, (size_t)n * SFE_MLP_NFEAT * 4);
+        sync(c);
+    });
+}
+
+sfe_status sfe_extension_log(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, const sfe_hsp *hsps,
+                             int64_t n, const sfe_scoring *scp, float *features, float *targets) {
+    if (!c || !ix || n < 0) return SFE_EINVAL;
+    return guard(c, [&] {
+        ScoreDesc sc = check_scoring(scp);
+        QueryLayout L;
+        upload_queries(c, queries, nq, 3, ix->sd.span, L);
+        if (n == 0) return;
+        if (!features || !targets) fail(SFE_EINVAL, "null output");
+        std::vector<sfe_hsp> hh = checked_hsps(c, ix, queries, nq, hsps, n);
+        std::vector<ExtItem> items((size_t)n);
+        for (int64_t x = 0; x < n; x++) {
+            const sfe_hsp &h = hh[x];
+            const uint32_t off = (h.len - 1) / 2;
+            items[x] = ExtItem{h.t0 + off, h.q0 + off, (int32_t)(2 * h.query_id + h.strand), 0};
+        }
+        BatchResult br;
+        run_batch(c, ix, items, sc, 6, SFE_SCHED_PLAIN, br);
+        std::vector<float> tg((size_t)n * SFE_MLP_NOUT);
+        for (int64_t x = 0; x < n; x++)
+            for (int s = 0; s < 2; s++) {
+                const HalfResult &r = br.halves[2 * x + s];
+                tg[x * 4 + 2 * s] = (float)std::log2(1.0 + (double)r.cells);
+                tg[x * 4 + 2 * s + 1] = (float)std::log2(1.0 + (double)r.i_end + (double)r.j_end);
+            }
+        sfe_hsp *hd = (sfe_hsp *)c->feat_hsp.ensure((size_t)n * sizeof(sfe_hsp));
+        copy_in(c, hd, hh.data(), (size_t)n * sizeof(sfe_hsp));
+        float *F = (float *)c->feat_out.ensure((size_t)n * SFE_MLP_NFEAT * 4);
+        compute_features(c, ix, L, nq, hd, n, F);
+        copy_out(c, features, F, (size_t)n * SFE_MLP_NFEAT * 4);
+        copy_out(c, targets, tg.data(), tg.size() * 4);
+        sync(c);
+    });
+}
+
+sfe_status sfe_model_create(sfe_ctx *c, const float *params, sfe_model **out) {
+    if (!c || !params || !out) return SFE_EINVAL;
+    *out = nullptr;
+    sfe_model *m = new (std::nothrow) sfe_model;
+    if (!m) return SFE_ENOMEM;
+    m->ctx = c;
+    sfe_status st = guard(c, [&] {
+        const size_t NP = SFE_MLP_NPARAMS;
+        m->master.ensure(NP * 4);
+        m->m.ensure(NP * 4);
+        m->v.ensure(NP * 4);
+        m->p16.ensure(NP * 2);
+        HIPCHK(hipMemcpyAsync(m->master.p, params, NP * 4, hipMemcpyDefault, c->stream));
+        HIPCHK(hipMemsetAsync(m->m.p, 0, NP * 4, c->stream));
+        HIPCHK(hipMemsetAsync(m->v.p, 0, NP * 4, c->stream));
+        launch_mlp_round(m->master.as<float>(), m->p16.as<uint16_t>(), c->stream);
+        HIPCHK(hipGetLastError());
+        sync(c);
+    });
+    if (st != SFE_OK) {
+        delete m;
+        return st;
+    }
+    *out = m;
+    return SFE_OK;
+}
+
+void sfe_model_destroy(sfe_model *m) {
+    if (!m) return;
+    (void)hipSetDevice(m->ctx->device);
+    (void)hipStreamSynchronize(m->ctx->stream);
+    delete m;
+}
+
+sfe_status sfe_model_params(const sfe_model *m, float *params) {
+    if (!m || !params) return SFE_EINVAL;
+    sfe_ctx *c = m->ctx;
+    return guard(c, [&] {
+        copy_out(c, params, m->master.p, (size_t)SFE_MLP_NPARAMS * 4);
+        sync(c);
+    });
+}
+
+sfe_status sfe_model_predict(sfe_model *m, const float *x, int64_t n, float *y) {
+    if (!m || n < 0) return SFE_EINVAL;
+    sfe_ctx *c = m->ctx;
+    return guard(c, [&] {
+        if (n == 0) return;
+        if (!x || !y) fail(SFE_EINVAL, "null input or output");
+        float *xd = (float *)m->x.ensure((size_t)n * SFE_MLP_NFEAT * 4);
+        float *yd = (float *)m->y.ensure((size_t)n * SFE_MLP_NOUT * 4);
+        copy_in(c, xd, x, (size_t)n * SFE_MLP_NFEAT * 4);
+        launch_mlp_forward(xd, n, m->p16.as<uint16_t>(), yd, c->stream);
+        HIPCHK(hipGetLastError());
+        copy_out(c, y, yd, (size_t)n * SFE_MLP_NOUT * 4);
+        sync(c);
+    });
+}
+
+sfe_status sfe_model_grad(sfe_model *m, const float *x, const float *t, int64_t n, float *grad, float *loss) {
+    if (!m || n < 1 || n > (int64_t)INT32_MAX - 64) return SFE_EINVAL;
+    sfe_ctx *c = m->ctx;
+    return guard(c, [&] {
+        if (!x || !t || !grad) fail(SFE_EINVAL, "null argument");
+        const size_t NP = SFE_MLP_NPARAMS;
+        const int nb = (int)((n + 63) / 64);
+        float *xd = (float *)m->x.ensure((size_t)n * SFE_MLP_NFEAT * 4);
+        float *td = (float *)m->t.ensure((size_t)n * SFE_MLP_NOUT * 4);
+        uint32_t *ids = (uint32_t *)m->ids.ensure((size_t)n * 4);
+        float *part = (float *)m->part.ensure((size_t)nb * NP * 4);
+        float *sse = (float *)m->sse.ensure((size_t)nb * 4);
+        float *gd = (float *)m->grad.ensure(NP * 4);
+        float *ld = (float *)m->loss.ensure(4);
+        copy_in(c, xd, x, (size_t)n * SFE_MLP_NFEAT * 4);
+        copy_in(c, td, t, (size_t)n * SFE_MLP_NOUT * 4);
+        k_iota<<<grid(n, 256), 256, 0, c->stream>>>(ids, n);
+        launch_mlp_grad(xd, td, (const int32_t *)ids, (int32_t)n, m->p16.as<uint16_t>(), part, sse, c->stream);
+        launch_mlp_apply(part, nb, sse, (int32_t)n, gd, nullptr, nullptr, nullptr, nullptr, 0.f, 1.f, 1.f, ld,
+                         c->stream);
+        HIPCHK(hipGetLastError());
+        copy_out(c, grad, gd, NP * 4);
+        if (loss) copy_out(c, loss, ld, 4);
+        sync(c);
+    });
+}
+
+sfe_status sfe_model_train(sfe_model *m, const float *x, const float *t, int64_t n, const int32_t *order,
+                           int64_t n_order, int32_t batch, float lr, float *losses) {
+    if (!m || n < 1 || n_order < 0 || batch < 1 || batch > (1 << 20) || !(lr > 0.0f)) return SFE_EINVAL;
+    sfe_ctx *c = m->ctx;
+    return guard(c, [&] {
+        if (n_order == 0) return;
+        if (!x || !t || !order) fail(SFE_EINVAL, "null argument");
+        std::vector<int32_t> ord((size_t)n_order);
+        HIPCHK(hipMemcpyAsync(ord.data(), order, (size_t)n_order * 4, hipMemcpyDefault, c->stream));
+        sync(c);
+        for (int32_t id : ord)
+            if (id < 0 || id >= n) fail(SFE_EINVAL, "sample id out of range");
+        const size_t NP = SFE_MLP_NPARAMS;
+        const int64_t steps = (n_order + batch - 1) / batch;
+        const int nbmax = (batch + 63) / 64;
+        float *xd = (float *)m->x.ensure((size_t)n * SFE_MLP_NFEAT * 4);
+        float *td = (float *)m->t.ensure((size_t)n * SFE_MLP_NOUT * 4);
+        int32_t *ids = (int32_t *)m->ids.ensure((size_t)n_order * 4);
+        float *part = (float *)m->part.ensure((size_t)nbmax * NP * 4);
+        float *sse = (float *)m->sse.ensure((size_t)nbmax * 4);
+        float *ld = (float *)m->loss.ensure((size_t)steps * 4);
+        copy_in(c, xd, x, (size_t)n * SFE_MLP_NFEAT * 4);
+        copy_in(c, td, t, (size_t)n * SFE_MLP_NOUT * 4);
+        copy_in(c, ids, ord.data(), (size_t)n_order * 4);
+        for (int64_t s = 0; s < steps; s++) {
+            const int32_t B = (int32_t)std::min<int64_t>(batch, n_order - s * batch);
+            const int nb = (B + 63) / 64;
+            launch_mlp_grad(xd, td, ids + s * batch, B, m->p16.as<uint16_t>(), part, sse, c->stream);
+            m->step++;
+            const float c1 = (float)(1.0 - std::pow(0.9, (double)m->step));
+            const float c2 = (float)(1.0 - std::pow(0.999, (double)m->step));
+            launch_mlp_apply(part, nb, sse, B, nullptr, m->master.as<float>(), m->m.as<float>(), m->v.as<float>(),
+                             m->p16.as<uint16_t>(), lr, c1, c2, ld + s, c->stream);
+        }
+        HIPCHK(hipGetLastError());
+        if (losses) copy_out(c, losses, ld, (size_t)steps * 4);
+        sync(c);
     });
 }
 

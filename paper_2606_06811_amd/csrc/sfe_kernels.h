@@ -81,4 +81,19 @@ void launch_ops_assemble(const int32_t *item_ids, int64_t n, const uint64_t *run
                          const uint32_t *nruns, const uint64_t *ops_off, uint32_t *ops, uint32_t *nops,
                          hipStream_t st);
 
+// learned cost model (k_learn.hip)
+void launch_mlp_round(const float *master, uint16_t *p16, hipStream_t st);
+void launch_mlp_forward(const float *X, int64_t n, const uint16_t *p16, float *Y, hipStream_t st);
+void launch_mlp_grad(const float *X, const float *T, const int32_t *ids, int32_t B, const uint16_t *p16,
+                     float *part, float *sse, hipStream_t st);
+void launch_mlp_apply(const float *part, int nb, const float *sse, int32_t B, float *grad, float *master, float *m,
+                      float *v, uint16_t *p16, float lr, float c1, float c2, float *loss, hipStream_t st);
+void launch_hsp_features(const sfe_hsp *h, int64_t n, const int32_t *unit_of, const UnitDesc *units, SeqSetView T,
+                         int64_t nt, SeqSetView Qp, SeqSetView Qm, const uint32_t *order, const uint32_t *okey,
+                         const int64_t *ustart, const int64_t *uend, float *F, hipStream_t st);
+void launch_hsp_anchor_keys(const sfe_hsp *h, int64_t n, const int32_t *unit_of, uint64_t *key, uint32_t *ids,
+                            hipStream_t st);
+void launch_hsp_unit_ranges(const sfe_hsp *h, const int32_t *unit_of, const uint32_t *order, int64_t n,
+                            uint32_t *okey, int64_t *ustart, int64_t *uend, hipStream_t st);
+
 }  // namespace sfe

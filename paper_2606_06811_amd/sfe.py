@@ -55,7 +55,7 @@ class _Scoring(ctypes.Structure):
 class _AlignOpts(ctypes.Structure):
     _fields_ = [("round_k", ctypes.c_int32), ("schedule", ctypes.c_int32), ("strands", ctypes.c_int32),
                 ("max_cells_per_lane", ctypes.c_int32), ("policy", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("arena_bytes", ctypes.c_int64)]
+                ("arena_bytes", ctypes.c_int64), ("model", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):
@@ -63,7 +63,11 @@ class _Stats(ctypes.Structure):
                                                "shadow", "cells", "overflow_reruns", "xdrop_columns",
                                                "ydrop_launches", "ydrop_kernel_cells", "seed_xdrop_launches")] + \
                [(n, ctypes.c_double) for n in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total",
-                                               "ms_ydrop_kernel", "ms_seed_xdrop_kernel")]
+                                               "ms_ydrop_kernel", "ms_seed_xdrop_kernel")] + \
+               [("predicted_halves", ctypes.c_int64), ("mispredicted_halves", ctypes.c_int64),
+                ("ms_predict", ctypes.c_double)]
+
+MLP_NFEAT, MLP_NOUT, MLP_NPARAMS = 16, 4, 9668
 
 
 def lib():
@@ -85,12 +89,21 @@ def lib():
                                        ctypes.POINTER(I64)]
         L.sfe_align.argtypes = [P, P, ctypes.POINTER(_Seq), I32, ctypes.POINTER(_Scoring), ctypes.POINTER(_AlignOpts),
                                 P, I64, ctypes.POINTER(I64), P, I64, ctypes.POINTER(I64), ctypes.POINTER(_Stats)]
+        L.sfe_hsp_features.argtypes = [P, P, ctypes.POINTER(_Seq), I32, P, I64, P]
+        L.sfe_extension_log.argtypes = [P, P, ctypes.POINTER(_Seq), I32, P, I64, ctypes.POINTER(_Scoring), P, P]
+        L.sfe_model_create.argtypes = [P, P, ctypes.POINTER(P)]
+        L.sfe_model_destroy.argtypes = [P]
+        L.sfe_model_params.argtypes = [P, P]
+        L.sfe_model_predict.argtypes = [P, P, I64, P]
+        L.sfe_model_grad.argtypes = [P, P, P, I64, P, P]
+        L.sfe_model_train.argtypes = [P, P, P, I64, P, I64, I32, ctypes.c_float, P]
         L.sfe_status_str.argtypes = [I32]
         L.sfe_status_str.restype = ctypes.c_char_p
         L.sfe_last_error.argtypes = [P]
         L.sfe_last_error.restype = ctypes.c_char_p
         for f in ("sfe_ctx_create", "sfe_build_index", "sfe_seed_hits", "sfe_ungapped_xdrop", "sfe_gapped_ydrop",
-                  "sfe_align"):
+                  "sfe_align", "sfe_hsp_features", "sfe_extension_log", "sfe_model_create", "sfe_model_params",
+                  "sfe_model_predict", "sfe_model_grad", "sfe_model_train"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -247,12 +260,12 @@ def sfe_gapped_ydrop(ctx: Context, idx: Index, queries, hsps: np.ndarray, scorin
 
 def sfe_align(ctx: Context, idx: Index, queries, scoring: dict, round_k: int = 0, schedule: int = SFE_SCHED_PLAIN,
               strands: int = 3, max_cells_per_lane: int = 0, arena_bytes: int = 0, policy: int = SFE_POLICY_DEFER,
-              cap: int = 1 << 12, ops_cap: int = 1 << 18):
+              cap: int = 1 << 12, ops_cap: int = 1 << 18, model=None):
     """Whole pipeline; returns (alignments, ops, stats dict)."""
     seqs, keep = _seq_arrays(queries)
     sc = scoring_struct(scoring)
     opts = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(policy), 0,
-                      int(arena_bytes))
+                      int(arena_bytes), model.ptr if model is not None else None)
     na, no = ctypes.c_int64(), ctypes.c_int64()
     stats = _Stats()
     while True:
@@ -267,3 +280,85 @@ def sfe_align(ctx: Context, idx: Index, queries, scoring: dict, round_k: int = 0
         _check(st, ctx)
         s = {f: getattr(stats, f) for f, _ in _Stats._fields_}
         return out[:na.value], ops[:no.value], s
+
+
+def _f32(a, shape=None):
+    if hasattr(a, "data_ptr"):
+        return a
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def sfe_hsp_features(ctx: Context, idx: Index, queries, hsps: np.ndarray) -> np.ndarray:
+    seqs, keep = _seq_arrays(queries)
+    hsps = np.ascontiguousarray(hsps, HSP_DTYPE)
+    out = np.zeros((hsps.shape[0], MLP_NFEAT), np.float32)
+    _check(lib().sfe_hsp_features(ctx.ptr, idx.ptr, seqs, len(queries), _ptr(hsps), hsps.shape[0], _ptr(out)), ctx)
+    return out
+
+
+def sfe_extension_log(ctx: Context, idx: Index, queries, hsps: np.ndarray, scoring: dict):
+    """(features n x 16, targets n x 4) of the plain pipeline's extensions of `hsps`."""
+    seqs, keep = _seq_arrays(queries)
+    hsps = np.ascontiguousarray(hsps, HSP_DTYPE)
+    sc = scoring_struct(scoring)
+    f = np.zeros((hsps.shape[0], MLP_NFEAT), np.float32)
+    t = np.zeros((hsps.shape[0], MLP_NOUT), np.float32)
+    _check(lib().sfe_extension_log(ctx.ptr, idx.ptr, seqs, len(queries), _ptr(hsps), hsps.shape[0],
+                                   ctypes.byref(sc), _ptr(f), _ptr(t)), ctx)
+    return f, t
+
+
+class Model:
+    """The cost model's parameters on the device of `ctx`."""
+
+    def __init__(self, ctx: Context, params):
+        self.ctx = ctx
+        params = _f32(params)
+        if not hasattr(params, "data_ptr") and params.shape != (MLP_NPARAMS,):
+            raise ValueError(f"need {MLP_NPARAMS} parameters")
+        p = ctypes.c_void_p()
+        _check(lib().sfe_model_create(ctx.ptr, _ptr(params), ctypes.byref(p)), ctx)
+        self.ptr = p
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_NPARAMS, np.float32)
+        _check(lib().sfe_model_params(self.ptr, _ptr(out)), self.ctx)
+        return out
+
+    def predict(self, x) -> np.ndarray:
+        x = _f32(x, (-1, MLP_NFEAT))
+        out = np.zeros((x.shape[0], MLP_NOUT), np.float32)
+        _check(lib().sfe_model_predict(self.ptr, _ptr(x), x.shape[0], _ptr(out)), self.ctx)
+        return out
+
+    def grad(self, x, t):
+        x = _f32(x, (-1, MLP_NFEAT))
+        t = _f32(t, (-1, MLP_NOUT))
+        g = np.zeros(MLP_NPARAMS, np.float32)
+        loss = np.zeros(1, np.float32)
+        _check(lib().sfe_model_grad(self.ptr, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss)), self.ctx)
+        return float(loss[0]), g
+
+    def train(self, x, t, order, batch: int, lr: float) -> np.ndarray:
+        x = _f32(x, (-1, MLP_NFEAT))
+        t = _f32(t, (-1, MLP_NOUT))
+        order = np.ascontiguousarray(order, np.int32)
+        steps = (order.shape[0] + batch - 1) // batch
+        losses = np.zeros(max(steps, 1), np.float32)
+        _check(lib().sfe_model_train(self.ptr, _ptr(x), _ptr(t), x.shape[0], _ptr(order), order.shape[0],
+                                     int(batch), float(lr), _ptr(losses)), self.ctx)
+        return losses[:steps]
+
+    def close(self):
+        if self.ptr:
+            lib().sfe_model_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

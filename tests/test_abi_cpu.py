@@ -47,9 +47,34 @@ def test_struct_layouts():
     assert sfe.HSP_DTYPE.itemsize == 24
     assert sfe.ALN_DTYPE.itemsize == 56
     assert ctypes.sizeof(sfe._Scoring) == 31 * 4
-    assert ctypes.sizeof(sfe._AlignOpts) == 32
+    assert ctypes.sizeof(sfe._AlignOpts) == 40
     src = open(HEADER).read()
     assert "} sfe_aln;                  /* 56 bytes */" in src
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    """Sizes and field offsets of the ctypes mirrors equal what a C compiler
+    makes of include/sfe.h."""
+    import subprocess
+    from paper_2606_06811_amd import sfe
+    pairs = [("sfe_align_opts", sfe._AlignOpts), ("sfe_stats", sfe._Stats), ("sfe_scoring", sfe._Scoring),
+             ("sfe_seq", sfe._Seq), ("sfe_seed_spec", sfe._SeedSpec)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sfe.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    c = tmp_path / "sizes.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = []
+    for cname, py in pairs:
+        want.append(ctypes.sizeof(py))
+        want += [getattr(py, f).offset for f, _ in py._fields_]
+    assert got == want
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
