@@ -7,8 +7,15 @@ filter, the HSP set (dedup + order), and the speculative batched gapped
 Y-drop extension with traceback and serial commit.  Inputs are synthetic
 (seeded), resident in HBM before the timed region.
 
-Prints one JSON line.  `value` is unique HSPs per second of the whole step;
-gapped GCUPS and the other stage rates ride along.
+Two schedules of the gapped stage are timed on the same step: the plain one
+(one wave per anchor-half, halves in batch order) and the learned one
+(persistent waves pulling halves from a queue ordered by the cost model's
+predicted size; the model is trained first, on the GPU, from extension logs
+of the plain pipeline on the 1 Mbp pair).  Their outputs must be identical.
+
+Prints one JSON line.  `value` is unique HSPs per second of the whole step
+with the learned schedule; the plain schedule's figures, gapped GCUPS and the
+other stage rates ride along.
 """
 from __future__ import annotations
 
@@ -61,6 +68,34 @@ def cpu_baseline(T, Q, sc, sample_bp: int):
                        f"in {dt:.1f} s")
 
 
+def train_cost_model(ctx, sfe, synth, log_fn):
+    """The learned part: extension logs of the plain pipeline on the 1 Mbp pair,
+    then GPU training of the cost model (He-uniform start, seeded)."""
+    T, Q = synth.pair_small()
+    idx = sfe.sfe_build_index(ctx, T, synth.SEED_PATTERN, 1, 1)
+    hits = sfe.sfe_seed_hits(ctx, idx, Q)
+    hsps = sfe.sfe_ungapped_xdrop(ctx, idx, Q, hits, dict(synth.SCORING))
+    f, t = sfe.sfe_extension_log(ctx, idx, Q, hsps, dict(synth.SCORING))
+    idx.close()
+    rng = np.random.default_rng(12345)
+    parts = []
+    for o, i in ((64, 16), (64, 64), (64, 64), (4, 64)):
+        lim = np.sqrt(6.0 / i)
+        parts += [rng.uniform(-lim, lim, o * i), np.zeros(o)]
+    p0 = np.concatenate(parts).astype(np.float32)
+    p0[-4:] = t.mean(axis=0)
+    model = sfe.Model(ctx, p0)
+    n = f.shape[0]
+    order = np.concatenate([rng.permutation(n) for _ in range(60)]).astype(np.int32)
+    t0 = time.perf_counter()
+    losses = model.train(f, t, order, batch=256, lr=2e-3)
+    dt = time.perf_counter() - t0
+    log_fn(f"cost model trained on {n} extensions of the 1 Mbp pair: loss {losses[0]:.3f} -> "
+           f"{losses[-1]:.3f} in {len(losses)} steps, {dt:.2f} s")
+    return model, dict(samples=int(n), steps=int(len(losses)), loss_first=float(losses[0]),
+                       loss_last=float(losses[-1]), train_s=round(dt, 3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,7 +103,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mid", choices=["mid", "small"])
     ap.add_argument("--round-k", type=int, default=0)
-    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--schedule", default="both", choices=["plain", "persistent", "learned", "both"],
+                    help="both: time the plain schedule and the learned persistent one (value = learned)")
+    ap.add_argument("--cpl", type=int, default=0, help="rows per lane of the first band window (0: default)")
     ap.add_argument("--cpu-sample-bp", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -91,28 +128,44 @@ def main():
     ctx = sfe.sfe_ctx_create(0, stream.cuda_stream)
     torch.cuda.synchronize()
 
-    def step():
+    model, train_info = None, None
+    if args.schedule in ("learned", "both"):
+        model, train_info = train_cost_model(ctx, sfe, synth, log)
+
+    def step(kind):
         idx = sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
-        out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k, schedule=args.schedule,
-                            cap=1 << 21, ops_cap=1 << 26)
+        sched = sfe.SFE_SCHED_PLAIN if kind == "plain" else sfe.SFE_SCHED_PERSISTENT
+        out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k, schedule=sched, cap=1 << 21, ops_cap=1 << 26,
+                            model=model if kind == "learned" else None, max_cells_per_lane=args.cpl)
         idx.close()
         return out
 
-    for w in range(args.warmup):
-        a, o, s = step()
-        log(f"warmup {w}: {s['hsps']} HSPs, {s['committed']} alignments, {s['rounds']} rounds, "
-            f"{s['ms_total']:.0f} ms")
-    torch.cuda.synchronize()
-    stats = []
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        a, o, s = step()
-        stats.append(s)
-        log(f"step {k}: {s['ms_total']:.0f} ms in align (seed+xdrop {s['ms_seed_xdrop']:.0f}, "
-            f"hsp set {s['ms_hsp_set']:.0f}, extend {s['ms_extend']:.0f})")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ms_step = 1e3 * elapsed / args.steps
+    def run(kind):
+        for w in range(args.warmup):
+            a, o, s = step(kind)
+            log(f"[{kind}] warmup {w}: {s['hsps']} HSPs, {s['committed']} alignments, {s['rounds']} rounds, "
+                f"{s['ms_total']:.0f} ms")
+        torch.cuda.synchronize()
+        stats = []
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            a, o, s = step(kind)
+            stats.append(s)
+            log(f"[{kind}] step {k}: {s['ms_total']:.0f} ms in align (seed+xdrop {s['ms_seed_xdrop']:.0f}, "
+                f"hsp set {s['ms_hsp_set']:.0f}, predict {s['ms_predict']:.0f}, extend {s['ms_extend']:.0f})")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        return dict(ms_step=1e3 * elapsed / args.steps, stats=stats, alns=a, ops=o)
+
+    kinds = ["plain", "learned"] if args.schedule == "both" else [args.schedule]
+    res = {k: run(k) for k in kinds}
+    head = res[kinds[-1]]
+    bit_exact = None
+    if len(kinds) == 2:
+        bit_exact = bool(np.array_equal(res["plain"]["alns"], res["learned"]["alns"])
+                         and np.array_equal(res["plain"]["ops"], res["learned"]["ops"]))
+    stats = head["stats"]
+    ms_step = head["ms_step"]
     s = stats[-1]
     hsps_per_s = s["hsps"] / (ms_step / 1e3)
 
@@ -143,6 +196,17 @@ def main():
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(T, Q, sc, args.cpu_sample_bp)
 
+    def summary(k):
+        r = res[k]
+        x = r["stats"][-1]
+        return dict(ms_per_step=round(r["ms_step"], 2), hsps_per_s=round(x["hsps"] / (r["ms_step"] / 1e3), 2),
+                    alignments_per_s=round(x["committed"] / (r["ms_step"] / 1e3), 2),
+                    ms_extend=round(x["ms_extend"], 2), ms_ydrop_kernel=round(x["ms_ydrop_kernel"], 2),
+                    predicted_halves=x["predicted_halves"], mispredicted_halves=x["mispredicted_halves"],
+                    misprediction_rate=(round(x["mispredicted_halves"] / x["predicted_halves"], 4)
+                                        if x["predicted_halves"] else None),
+                    ms_predict=round(x["ms_predict"], 2))
+
     line = {
         "metric": "HSPs/s + gapped GCUPS, 1 MI355X; learned-binned vs plain batch, bit-exact",
         "value": round(hsps_per_s, 2),
@@ -156,16 +220,21 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": desc, "schedule": "plain" if args.schedule == 0 else "persistent",
-                   "policy": "defer", "round_k": args.round_k or (1 << 20)},
+        "config": {"workload": desc, "schedule": kinds[-1], "policy": "defer",
+                   "round_k": args.round_k or (1 << 20)},
         "gapped_gcups": round(s["cells"] / (s["ms_extend"] / 1e3) / 1e9, 3) if s["ms_extend"] > 0 else None,
         "gapped_gcups_kernel": round(yd_cells / (yd_ms / 1e3) / 1e9, 3) if yd_ms > 0 else None,
         "seed_hits_per_s": round(s["seed_hits"] / (s["ms_seed_xdrop"] / 1e3), 1) if s["ms_seed_xdrop"] > 0 else None,
         "alignments_per_s": round(s["committed"] / (ms_step / 1e3), 2),
+        "schedules": {k: summary(k) for k in kinds},
+        "learned_vs_plain": (round(res["plain"]["ms_step"] / res["learned"]["ms_step"], 4)
+                             if len(kinds) == 2 else None),
+        "bit_exact_learned_vs_plain": bit_exact,
+        "cost_model_training": train_info,
         "counts": {k: s[k] for k in ("seed_hits", "hsps_raw", "hsps", "rounds", "extensions", "committed",
                                      "shadow", "cells", "overflow_reruns", "xdrop_columns")},
         "stage_ms": {k: round(s[k], 2) for k in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total",
-                                                 "ms_ydrop_kernel", "ms_seed_xdrop_kernel")},
+                                                 "ms_ydrop_kernel", "ms_seed_xdrop_kernel", "ms_predict")},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -134,7 +134,9 @@ typedef struct {
     int32_t round_k;        /* per (query, strand) extensions per batch; <= 0 picks a default */
     int32_t schedule;       /* SFE_SCHED_* */
     int32_t strands;        /* bit 0 plus, bit 1 minus; 0 means both */
-    int32_t max_cells_per_lane; /* 0 = automatic (6); 4, 6 or 8 rows per lane in the first band window */
+    int32_t max_cells_per_lane; /* 0 = automatic (6); 2, 3, 4, 6 or 8 rows per lane (64 x that many rows)
+                               in the first band window; wider bands move on to 8, then to the
+                               workgroup kernel */
     int32_t policy;         /* SFE_POLICY_* */
     int32_t pad;
     int64_t arena_bytes;    /* device memory for traceback codes of the halves in flight,

@@ -1023,7 +1023,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         int strands = o.strands ? o.strands : 3;
         if (strands < 1 || strands > 3) fail(SFE_EINVAL, "strands must be 1, 2 or 3");
         const int64_t K = o.round_k > 0 ? o.round_k : (o.policy == SFE_POLICY_DEFER ? (1 << 20) : 256);
-        const int cpl = o.max_cells_per_lane > 0 ? std::min(8, std::max(4, o.max_cells_per_lane)) : 6;
+        const int cpl = o.max_cells_per_lane > 0 ? std::min(8, std::max(2, o.max_cells_per_lane)) : 6;
         if (o.arena_bytes > 0) set_arena(c, std::max<int64_t>(o.arena_bytes, 2 * ARENA_PAGE));
         sfe_stats st{};
         c->ydrop_ms = c->sx_ms = 0;

@@ -127,18 +127,35 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
         const SeqSetView Q = tk.qset ? Qm : Qp;
         const int64_t nA = tk.nA, nB = tk.nB;
         const int64_t kmax = nA + nB;
+        // 32-bit copies: the band never reaches ROW_LIMIT antidiagonals (the half stops there)
+        const int nA32 = (int)min(nA, (int64_t)ROW_LIMIT + 4096);
+        const int nB32 = (int)min(nB, (int64_t)ROW_LIMIT + 4096);
+        const int kmax32 = (int)min(kmax, (int64_t)ROW_LIMIT + 4096);
         __syncthreads();
-        int64_t a_hi = 0, b_hi = 0;
+        int a_hi = 0, b_hi = 0;
         while (a_hi < 64 * C + 64) { ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane); a_hi += RING_CHUNK; }
         while (b_hi < 128) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
-        auto acode = [&](int64_t ia) { return ia < 0 ? 4 : (int)aring[ia & (RING - 1)]; };
-        auto bcode = [&](int64_t jb) {
+        auto acode = [&](int ia) { return ia < 0 ? 4 : (int)aring[ia & (RING - 1)]; };
+        auto bcode = [&](int jb) {
             if (jb < 0) return 4;
             if (jb < b_hi - RING) return codeB(Q, tk, jb);
             return (int)bring[jb & (RING - 1)];
         };
         auto plo_of = [&](int a) { return PERM ? prof[0][a] : a * 8; };
         auto phi_of = [&](int a) { return PERM ? prof[1][a] : 0; };
+        // query codes of positions bw0 + lane (bwa) and bw0 + 64 + lane (bwb): the code
+        // entering the band each antidiagonal is a register read, not an LDS round trip
+        int bw0 = -(1 << 30), bwa = 4, bwb = 4;
+        auto bcode_next = [&](int pos) {
+            if (pos < bw0 || pos >= bw0 + 128) {
+                while (b_hi < pos + 128) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
+                bw0 = pos - 64;
+                bwa = bcode(bw0 + lane);
+                bwb = bcode(bw0 + 64 + lane);
+            }
+            const int d = pos - bw0;
+            return d < 64 ? __builtin_amdgcn_readlane(bwa, d) : __builtin_amdgcn_readlane(bwb, d - 64);
+        };
 
         int H1[C], H2[C], E1[C], F1[C], Plo[C], Phi[C], Bs[C];
         int base = 0;
@@ -173,20 +190,20 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
             }
         }
         int k = 1;
-        for (; status == HALF_OK && (int64_t)k <= kmax; k++) {
+        for (; status == HALF_OK && k <= kmax32; k++) {
             if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
             int lo = 0x7fffffff, hi = -1;
             if (lmin1 <= lmax1) { lo = lmin1; hi = lmax1 + 1; }
             if (lmin2 <= lmax2) { lo = min(lo, lmin2 + 1); hi = max(hi, lmax2 + 1); }
-            const int clo = (int)max((int64_t)0, (int64_t)k - nB);
-            const int chi = (int)min(nA, (int64_t)k);
+            const int clo = max(0, k - nB32);
+            const int chi = min(nA32, k);
             lo = max(lo, clo);
             hi = min(hi, chi);
             const bool nonempty = lo <= hi;
             if (nonempty) {
                 const int s = (lo - 1 - base) / C;
                 if (s >= 1) {
-                    while (a_hi < (int64_t)base + (s + 64) * C + 64) {
+                    while (a_hi < base + (s + 64) * C + 64) {
                         ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane);
                         a_hi += RING_CHUNK;
                     }
@@ -195,7 +212,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                         for (int r = 0; r < C; r++) {
                             const int i_new = base + 64 * C + r;
                             const int a = acode(i_new - 1);
-                            const int fb = S::bsel(bcode((int64_t)k - i_new - 1));
+                            const int fb = S::bsel(bcode(k - i_new - 1));
                             H1[r] = dpp_shl1(NEG, H1[r]);
                             H2[r] = dpp_shl1(NEG, H2[r]);
                             E1[r] = dpp_shl1(NEG, E1[r]);
@@ -222,7 +239,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                             F1[r] = from_next ? NEG : f1;
                             Plo[r] = from_next ? plo_of(a) : pl;
                             Phi[r] = from_next ? phi_of(a) : ph;
-                            Bs[r] = from_next ? S::bsel(bcode((int64_t)k - i_new - 1)) : bs;
+                            Bs[r] = from_next ? S::bsel(bcode(k - i_new - 1)) : bs;
                         }
                     }
                     base += s * C;
@@ -234,9 +251,8 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
             const int upF = dpp_shr1(NEG, F1[C - 1]);
             const int upD = dpp_shr1(NEG, H2[C - 1]);
             int Hn[C], En[C], Fn[C];
-            uint32_t nib = 0;
+            uint32_t nib = 0, lmask = 0;      // traceback codes, live rows of this lane (bit r)
             int lmax = NEG;
-            int fr = 0x7fffffff, lr = -1;
             auto cell_pass = [&](auto edge_tag) {
                 constexpr bool EDGE = decltype(edge_tag)::value;
                 const int i0 = base + lane * C;
@@ -262,22 +278,29 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                         Fn[r] = F;
                     }
                     Hn[r] = live ? H : NEG;
-                    const uint64_t m = __ballot(live);
-                    if (m) {
-                        fr = min(fr, __builtin_ctzll(m) * C + r);
-                        lr = max(lr, (63 - __builtin_clzll(m)) * C + r);
-                    }
+                    lmask |= live ? (1u << r) : 0u;
                     const uint32_t code = (H == G ? 0u : (H == E ? 1u : 2u)) | (hlo >= ele ? 4u : 0u) |
                                           (huo >= fue ? 8u : 0u);
                     nib |= code << (4 * r);
                     lmax = imax(lmax, Hn[r]);
                 }
             };
-            const bool edge = base < clo || (int64_t)base + 64 * C - 1 > nA;
+            const bool edge = base < clo || base + 64 * C - 1 > nA32;
             if (edge) cell_pass(std::true_type());
             else cell_pass(std::false_type());
+            // live rows of the antidiagonal: first and last lane with a live row, then
+            // that lane's first / last live row
             int lmin0 = 1, lmax0 = 0;
-            if (lr >= 0) { lmin0 = base + fr; lmax0 = base + lr; }
+            {
+                const uint64_t m = __ballot(lmask != 0);
+                if (m) {
+                    const int L1 = __builtin_ctzll(m), L2 = 63 - __builtin_clzll(m);
+                    const uint32_t f1 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L1);
+                    const uint32_t f2 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L2);
+                    lmin0 = base + L1 * C + __builtin_ctz(f1);
+                    lmax0 = base + L2 * C + (31 - __builtin_clz(f2));
+                }
+            }
             // record of antidiagonal k: rows of the lanes covering [lo, hi]
             {
                 int l_lo = 0, l_hi = -1;
@@ -304,21 +327,21 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                 uint32_t *rec = (uint32_t *)(cb + fill);
                 if (lane >= l_lo && lane <= l_hi) rec[2 + lane - l_lo] = nib;
                 if (lane == 0) {
-                    rec[0] = nonempty ? (uint32_t)(base + l_lo * C) : 0u;
-                    rec[1] = rec_head_word(ng, C);
+                    *(uint2 *)rec = make_uint2(nonempty ? (uint32_t)(base + l_lo * C) : 0u, rec_head_word(ng, C));
                     *(uint32_t *)(cb + CH - 4u * (uint32_t)(k - k0 + 1)) = fill;
                 }
                 fill += need;
                 if (nonempty) cells += (uint64_t)(hi - lo + 1);
             }
-            const int admax = wave_max_dpp(lmax);
-            if (admax > best) {
-                int row = 0x7fffffff;
+            // best: only when some live cell beats it; then the first row reaching the new maximum
+            if (__ballot(lmax > best)) {
+                const int admax = wave_max_dpp(lmax);
+                uint32_t eq = 0;
 #pragma unroll
-                for (int r = 0; r < C; r++) {
-                    const uint64_t m = __ballot(Hn[r] == admax);
-                    if (m) row = min(row, __builtin_ctzll(m) * C + r);
-                }
+                for (int r = 0; r < C; r++) eq |= (Hn[r] == admax) ? (1u << r) : 0u;
+                const uint64_t m = __ballot(eq != 0);
+                const int L = __builtin_ctzll(m);
+                const int row = L * C + __builtin_ctz((uint32_t)__builtin_amdgcn_readlane((int)eq, L));
                 best = admax;
                 bi = base + row;
                 bj = k - bi;
@@ -331,10 +354,8 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                 E1[r] = En[r];
                 F1[r] = Fn[r];
             }
-            const int64_t bnew = (int64_t)k - base;
-            while (b_hi < bnew + 64) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
             {
-                const int carry = dpp_shr1(S::bsel(bcode(bnew)), Bs[C - 1]);
+                const int carry = dpp_shr1(S::bsel(bcode_next(k - base)), Bs[C - 1]);
 #pragma unroll
                 for (int r = C - 1; r > 0; r--) Bs[r] = Bs[r - 1];
                 Bs[0] = carry;
@@ -518,7 +539,9 @@ void launch_ydrop_fused(int cells_per_lane, bool perm, bool persistent, const Ha
     k_ydrop_fused<CC, PP, QQ><<<(unsigned)grid, 64, 0, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res)
 #define SFE_BY_C(PP, QQ)                                  \
     do {                                                  \
-        if (cells_per_lane <= 4) SFE_LAUNCH(4, PP, QQ);   \
+        if (cells_per_lane <= 2) SFE_LAUNCH(2, PP, QQ);   \
+        else if (cells_per_lane <= 3) SFE_LAUNCH(3, PP, QQ); \
+        else if (cells_per_lane <= 4) SFE_LAUNCH(4, PP, QQ); \
         else if (cells_per_lane <= 6) SFE_LAUNCH(6, PP, QQ); \
         else SFE_LAUNCH(8, PP, QQ);                       \
     } while (0)
@@ -537,7 +560,9 @@ int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool persistent) {
 #define SFE_OCC(CC, PP, QQ) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ydrop_fused<CC, PP, QQ>, 64, 0)
 #define SFE_OCC_C(PP, QQ)                                 \
     do {                                                  \
-        if (cells_per_lane <= 4) SFE_OCC(4, PP, QQ);      \
+        if (cells_per_lane <= 2) SFE_OCC(2, PP, QQ);      \
+        else if (cells_per_lane <= 3) SFE_OCC(3, PP, QQ); \
+        else if (cells_per_lane <= 4) SFE_OCC(4, PP, QQ); \
         else if (cells_per_lane <= 6) SFE_OCC(6, PP, QQ); \
         else SFE_OCC(8, PP, QQ);                          \
     } while (0)
