@@ -722,17 +722,28 @@ struct BoxGrid {
     }
 };
 
-// M runs of computed extensions of one unit, each tagged with the position of
-// its HSP in the walking order.
-struct PathIndex {
-    struct Run { uint32_t tb, te; size_t owner; };
-    std::unordered_map<int64_t, std::vector<Run>> diag;
+// M runs of a set of alignments of one unit, for "does (t, q) lie on an M
+// column of one of them" tests.  Each alignment keeps its runs in path order
+// (so sorted by t and disjoint in t) and is entered in every 16 kbp target
+// bin its box touches; a test reads the alignments of one bin, checks the box
+// and binary-searches the run that could hold t.
+struct PathSet {
+    static const int SH = 14;
+    struct Path { uint32_t t0, t1, q0, q1; size_t owner; size_t first; uint32_t count; };
+    std::vector<Path> paths;
+    std::vector<uint32_t> rt, rl;      // run start (target) and length
+    std::vector<int32_t> rd;           // run diagonal minus the alignment's start diagonal
+    std::unordered_map<uint32_t, std::vector<uint32_t>> bins;
     void add(const sfe_aln &a, const uint32_t *ops, size_t owner) {
+        Path P{a.t_start, a.t_end, a.q_start, a.q_end, owner, rt.size(), 0};
         uint32_t t = a.t_start, q = a.q_start;
+        const int64_t d0 = (int64_t)a.t_start - (int64_t)a.q_start;
         for (uint32_t x = 0; x < a.ops_len; x++) {
-            uint32_t len = ops[x] >> 2, op = ops[x] & 3u;
+            const uint32_t len = ops[x] >> 2, op = ops[x] & 3u;
             if (op == 0) {
-                diag[(int64_t)t - (int64_t)q].push_back(Run{t, t + len, owner});
+                rt.push_back(t);
+                rl.push_back(len);
+                rd.push_back((int32_t)((int64_t)t - (int64_t)q - d0));
                 t += len;
                 q += len;
             } else if (op == 1) {
@@ -741,43 +752,51 @@ struct PathIndex {
                 t += len;
             }
         }
+        P.count = (uint32_t)(rt.size() - P.first);
+        if (P.count == 0 || a.t_end <= a.t_start) return;
+        const uint32_t id = (uint32_t)paths.size();
+        paths.push_back(P);
+        for (uint32_t b = a.t_start >> SH; b <= (a.t_end - 1) >> SH; b++) bins[b].push_back(id);
     }
-    // (t, q) lies on an M column of an extension, still waiting for commit,
-    // whose HSP comes before `pos` (state[owner] == 2)
-    bool contains_before(uint32_t t, uint32_t q, size_t pos, const std::vector<uint8_t> &state) const {
-        auto it = diag.find((int64_t)t - (int64_t)q);
-        if (it == diag.end()) return false;
-        for (const Run &r : it->second)
-            if (r.owner < pos && r.tb <= t && t < r.te && state[r.owner] == 2) return true;
+    template <class Ok>
+    bool contains(uint32_t t, uint32_t q, Ok ok) const {
+        auto it = bins.find(t >> SH);
+        if (it == bins.end()) return false;
+        for (uint32_t id : it->second) {
+            const Path &P = paths[id];
+            if (t < P.t0 || t >= P.t1 || q < P.q0 || q >= P.q1 || !ok(P.owner)) continue;
+            // last run starting at or before t
+            size_t lo = P.first, hi = P.first + P.count;
+            while (hi - lo > 1) {
+                const size_t mid = (lo + hi) / 2;
+                if (rt[mid] <= t) lo = mid;
+                else hi = mid;
+            }
+            if (rt[lo] <= t && t < rt[lo] + rl[lo] &&
+                (int64_t)t - (int64_t)q - ((int64_t)P.t0 - (int64_t)P.q0) == (int64_t)rd[lo])
+                return true;
+        }
         return false;
     }
 };
 
-// Committed M columns of one (query, strand) unit, by diagonal t - q.
+// M runs of computed extensions of one unit, each tagged with the position of
+// its HSP in the walking order.
+struct PathIndex {
+    PathSet set;
+    void add(const sfe_aln &a, const uint32_t *ops, size_t owner) { set.add(a, ops, owner); }
+    // (t, q) lies on an M column of an extension, still waiting for commit,
+    // whose HSP comes before `pos` (state[owner] == 2)
+    bool contains_before(uint32_t t, uint32_t q, size_t pos, const std::vector<uint8_t> &state) const {
+        return set.contains(t, q, [&](size_t o) { return o < pos && state[o] == 2; });
+    }
+};
+
+// Committed M columns of one (query, strand) unit.
 struct SegList {
-    std::unordered_map<int64_t, std::vector<std::pair<uint32_t, uint32_t>>> diag;
-    bool contains(uint32_t t, uint32_t q) const {
-        auto it = diag.find((int64_t)t - (int64_t)q);
-        if (it == diag.end()) return false;
-        for (auto &iv : it->second)
-            if (iv.first <= t && t < iv.second) return true;
-        return false;
-    }
-    void add(const sfe_aln &a, const uint32_t *ops) {
-        uint32_t t = a.t_start, q = a.q_start;
-        for (uint32_t x = 0; x < a.ops_len; x++) {
-            uint32_t len = ops[x] >> 2, op = ops[x] & 3u;
-            if (op == 0) {
-                diag[(int64_t)t - (int64_t)q].push_back({t, t + len});
-                t += len;
-                q += len;
-            } else if (op == 1) {
-                q += len;
-            } else {
-                t += len;
-            }
-        }
-    }
+    PathSet set;
+    bool contains(uint32_t t, uint32_t q) const { return set.contains(t, q, [](size_t) { return true; }); }
+    void add(const sfe_aln &a, const uint32_t *ops) { set.add(a, ops, 0); }
 };
 
 sfe_status guard(sfe_ctx *c, const std::function<void()> &f) {
@@ -1121,7 +1140,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             ta = h.t0 + off;
             qa = h.q0 + off;
         };
-        double host_ms = 0;
+        double host_ms = 0, book_ms = 0, commit_ms = 0;
         for (;;) {
             const double th = now_ms();
             items.clear();
@@ -1201,6 +1220,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 if (defer && (a.flags & SFE_ALN_PASSED)) paths[u].add(pe.first, pe.second.data(), p);
                 state[u][p] = 2;
             }
+            const double th3 = now_ms();
+            book_ms += th3 - th2;
             for (size_t u = 0; u < NU; u++) {                      // phase 3: serial commit, in order
                 auto &lst = per_unit[u];
                 auto &stt = state[u];
@@ -1232,9 +1253,12 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     break;                                          // needs an extension first
                 }
             }
+            commit_ms += now_ms() - th3;
             host_ms += now_ms() - th2;
         }
-        if (progress) fprintf(stderr, "[sfe] host scan/commit time %.1f ms\n", host_ms);
+        if (progress)
+            fprintf(stderr, "[sfe] host scan/commit time %.1f ms (scan %.1f, bookkeeping %.1f, commit %.1f)\n", host_ms,
+                    host_ms - book_ms - commit_ms, book_ms, commit_ms);
         for (size_t u = 0; u < NU; u++)
             if (!pending[u].empty() || cursor[u] != per_unit[u].size()) fail(SFE_EINTERNAL, "commit did not finish");
         st.committed = (int64_t)committed.size();
