@@ -229,6 +229,18 @@ sfe_status sfe_align(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries,
                      sfe_aln *out, int64_t cap, int64_t *n_alns,
                      uint32_t *ops, int64_t ops_cap, int64_t *n_ops, sfe_stats *stats);
 
+/* Schedule knobs of a context (an autotuner's output; none changes results).
+ * wave_group_cap: a half still running after this many antidiagonals on one
+ *   wavefront restarts on a group of 4 wavefronts that share its band (one LDS
+ *   barrier per antidiagonal, Sec. 8's cooperative mapping); halves a cost
+ *   model predicts to be longer start there.  0 = never (default). */
+typedef struct {
+    int32_t wave_group_cap;
+    int32_t reserved[7];
+} sfe_tuning;
+sfe_status sfe_ctx_set_tuning(sfe_ctx *ctx, const sfe_tuning *t);
+sfe_status sfe_ctx_get_tuning(const sfe_ctx *ctx, sfe_tuning *t);
+
 /* ---------------------------------------------------------------------------
  * Learned cost model.  The cost of an anchor-half is unknown until it has run
  * (Sec. 8) and sorting work by expected size up front is the load-balancing

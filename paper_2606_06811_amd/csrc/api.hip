@@ -81,6 +81,7 @@ struct sfe_ctx {
     DBuf feat_unit, feat_key, feat_key2, feat_ids, feat_ids2, feat_okey, feat_range, feat_hsp, feat_out, feat_pred;
     DBuf busy_d;                        // bitmap of the traceback chunk pool
     int cu_count = 0;
+    sfe_tuning tuning{};                // schedule knobs (wave_group_cap 0: one wave per half)
     int32_t pool_avail = 0;             // host copy of the pool's initial free count
     // traceback arenas: arena 0 holds the fused kernel's chunk pool and the
     // workgroup kernel's pages; a workgroup-kernel half that finds its arena
@@ -420,6 +421,11 @@ ChunkPool make_pool(sfe_ctx *c) {
     return ChunkPool{c->arenas[0]->as<uint8_t>(), bits, avail, nwords, shift};
 }
 
+// Stages of a half: one wave with the caller's rows per lane, one wave with 8,
+// a group of 4 waves with 2 and with 4 rows per lane, then the workgroup
+// kernel with a ring of 4096 * 4^(stage - ST_RING) rows.
+enum { ST_WAVE = 0, ST_WAVE8 = 1, ST_COOP2 = 2, ST_COOP4 = 3, ST_RING = 4 };
+
 // Extends the 2n halves of the batch items and traces back every half that
 // ends away from its anchor.  Fused kernel first (rows-per-lane window of
 // cells_per_lane, then 8): a half whose band outgrows the window moves on,
@@ -432,7 +438,8 @@ ChunkPool make_pool(sfe_ctx *c) {
 // start longest-predicted first (for the persistent schedule, the order of its
 // queue); the output does not depend on it.
 void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &items, const ScoreDesc &sc,
-               int cells_per_lane, int schedule, BatchResult &out, const std::vector<float> *cost = nullptr) {
+               int cells_per_lane, int schedule, BatchResult &out, const std::vector<float> *cost = nullptr,
+               const std::vector<float> *extent = nullptr) {
     const int64_t n = (int64_t)items.size();
     out.alns.assign(n, sfe_aln{});
     out.ops.clear();
@@ -450,7 +457,13 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     std::vector<HalfResult> hr(nh);
     std::vector<uint64_t> roff(nh, 0);
     std::vector<uint32_t> nrun(nh, 0);
-    std::vector<int> stage(nh, cells_per_lane < 8 ? 0 : 1), level(nh, 0);
+    std::vector<int> stage(nh, cells_per_lane < 8 ? ST_WAVE : ST_WAVE8), level(nh, 0);
+    // a half still running after long_cap antidiagonals on one wave restarts on a
+    // wave group; predicted longer: straight there
+    const int long_cap = c->tuning.wave_group_cap;
+    if (extent && long_cap > 0)
+        for (int64_t h = 0; h < nh; h++)
+            if ((*extent)[h] > std::log2((double)long_cap)) stage[h] = ST_COOP2;
     c->sched_d.ensure(64);
     if (c->arenas.empty() || !c->arenas[0]->p) ensure_arena(c, kDefaultArena);
     set_run_head(c, 0);
@@ -477,7 +490,7 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
             for (int32_t h : todo) sg = std::min(sg, stage[h]);
             for (int32_t h : todo)
                 if (stage[h] == sg) lv = std::min(lv, level[h]);
-            for (int32_t h : todo) (stage[h] == sg && (sg >= 2 || level[h] == lv) ? group : rest).push_back(h);
+            for (int32_t h : todo) (stage[h] == sg && (sg >= ST_RING || level[h] == lv) ? group : rest).push_back(h);
         }
         const int32_t *ids = nullptr;
         int64_t cnt = nh;
@@ -489,12 +502,12 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
             if (!first) out.reruns += cnt;
         }
         first = false;
-        const bool fused = sg <= 1;
+        const bool fused = sg <= ST_COOP4;         // chunk pool + traceback in the same kernel
         int64_t nwaves = 0;
         uint64_t chunk_bytes = 0;
         Arena ar{};
-        if (fused) {
-            const int C = sg == 0 ? cells_per_lane : 8;
+        if (sg <= ST_WAVE8) {
+            const int C = sg == ST_WAVE ? cells_per_lane : 8;
             bool persistent = schedule == SFE_SCHED_PERSISTENT || lv > 0;
             // level L > 0 (the pool ran dry at level L - 1): 4^L times fewer
             // waves than the device holds, pulling from the queue
@@ -508,10 +521,22 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
             WorkQueue wq{ids, cnt, qhead};
             HIPCHK(hipEventRecord(c->ev0, c->stream));
             launch_ydrop_fused(C, perm, persistent, tasks, wq, persistent ? count : cnt, T, Qp, Qm, sc, pool, ra,
-                               hres, c->stream);
+                               hres, long_cap, c->stream);
+        } else if (sg <= ST_COOP4) {
+            // wave groups; level L > 0: at most 256 / 4^(L-1) halves in flight
+            const int C = sg == ST_COOP2 ? 2 : 4;
+            const int64_t slice = lv == 0 ? cnt : std::max<int64_t>(1, 256 >> std::min(62, 2 * (lv - 1)));
+            nwaves = slice == 1 ? 1 : 0;
+            HIPCHK(hipEventRecord(c->ev0, c->stream));
+            for (int64_t o = 0; o < cnt; o += slice) {
+                ChunkPool pool = make_pool(c);
+                chunk_bytes = (uint64_t)1 << pool.shift;
+                launch_ydrop_coop(C, perm, tasks, ids + o, std::min(slice, cnt - o), T, Qp, Qm, sc, pool, ra, hres,
+                                  c->stream);
+            }
         } else {
-            const int32_t cap = 4096 << (2 * (sg - 2));
-            if (sg - 2 > 10) fail(SFE_EINTERNAL, "band width beyond 2^24 rows");
+            const int32_t cap = 4096 << (2 * (sg - ST_RING));
+            if (sg - ST_RING > 10) fail(SFE_EINTERNAL, "band width beyond 2^24 rows");
             ar = arena_at(c, ai);
             HIPCHK(hipMemsetAsync(ar.head, 0, 8, c->stream));
             int32_t *ring = (int32_t *)c->ring_d.ensure((size_t)cnt * 7 * cap * 4);
@@ -539,7 +564,13 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
                     traced.push_back(h);
                 }
                 break;
-            case HALF_WIDTH_OVERFLOW: stage[h]++; level[h] = 0; next.push_back(h); break;
+            case HALF_WIDTH_OVERFLOW:
+                // 384 -> 512 rows (one wave), 512 -> 1024 (wave group), then the workgroup kernel
+                stage[h] = stage[h] == ST_WAVE ? ST_WAVE8 : stage[h] <= ST_COOP2 ? ST_COOP4 : stage[h] + 1;
+                level[h] = 0;
+                next.push_back(h);
+                break;
+            case HALF_LONG: stage[h] = std::max(stage[h], (int)ST_COOP2); level[h] = 0; next.push_back(h); break;
             case HALF_ARENA_OVERFLOW:
                 if (fused) {
                     if (nwaves == 1) pool_full = true;    // one wave already: grow the arena
@@ -593,8 +624,9 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         if (pool_full) ensure_arena(c, c->arena_bytes * 4);
         if (getenv("SFE_PROGRESS")) {
             if (fused)
-                fprintf(stderr, "[sfe]   launch: fused C=%d level %d, %lld halves, %lld waves, %llu KiB chunks, next %zu\n",
-                        sg == 0 ? cells_per_lane : 8, lv, (long long)cnt, (long long)nwaves,
+                fprintf(stderr, "[sfe]   launch: %s C=%d level %d, %lld halves, %lld waves, %llu KiB chunks, next %zu\n",
+                        sg <= ST_WAVE8 ? "wave" : "wave group", sg == ST_WAVE ? cells_per_lane : sg == ST_WAVE8 ? 8
+                        : sg == ST_COOP2 ? 2 : 4, lv, (long long)cnt, (long long)nwaves,
                         (unsigned long long)(chunk_bytes >> 10), next.size());
             else
                 fprintf(stderr, "[sfe]   launch: workgroup stage %d, %lld halves, arena %zu%s, next %zu\n", sg,
@@ -1106,7 +1138,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             sync(c);
             st.ms_predict = now_ms() - tp;
         }
-        std::vector<float> cost;
+        std::vector<float> cost, extent;
         const double t3 = now_ms();
         // --- Alg. 3 rounds ------------------------------------------------------------
         std::vector<int32_t> unit_of(2 * (size_t)std::max(nq, 1), -1);
@@ -1192,13 +1224,17 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             const double tr = now_ms();
             if (learned) {
                 cost.resize(2 * items.size());
+                extent.resize(2 * items.size());
                 for (size_t x = 0; x < items.size(); x++) {
                     const int64_t hx = per_unit[item_ref[x].first][item_ref[x].second];
                     cost[2 * x] = pred[(size_t)hx * 4 + 0];
+                    extent[2 * x] = pred[(size_t)hx * 4 + 1];
                     cost[2 * x + 1] = pred[(size_t)hx * 4 + 2];
+                    extent[2 * x + 1] = pred[(size_t)hx * 4 + 3];
                 }
             }
-            run_batch(c, ix, items, sc, cpl, o.schedule, br, learned ? &cost : nullptr);   // phase 2
+            run_batch(c, ix, items, sc, cpl, o.schedule, br, learned ? &cost : nullptr,
+                      learned ? &extent : nullptr);                                   // phase 2
             st.predicted_halves += br.predicted;
             st.mispredicted_halves += br.mispredicted;
             if (progress)
@@ -1303,6 +1339,18 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         sync(c);
         if (stats) stats->ms_total = now_ms() - t0;
     });
+}
+
+sfe_status sfe_ctx_set_tuning(sfe_ctx *c, const sfe_tuning *t) {
+    if (!c || !t || t->wave_group_cap < 0) return SFE_EINVAL;
+    c->tuning = *t;
+    return SFE_OK;
+}
+
+sfe_status sfe_ctx_get_tuning(const sfe_ctx *c, sfe_tuning *t) {
+    if (!c || !t) return SFE_EINVAL;
+    *t = c->tuning;
+    return SFE_OK;
 }
 
 sfe_status sfe_hsp_features(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, const sfe_hsp *hsps,

@@ -78,11 +78,189 @@ __device__ __forceinline__ void pool_free(const ChunkPool &p, int c, int lane) {
     }
 }
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ uint8_t *chunk_ptr(const ChunkPool &p, int c) {
+    return p.base + ((uint64_t)(uint32_t)c << p.shift);
+}
+__device__ __forceinline__ uint32_t chunk_hdr(const ChunkPool &p, int c, int w) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)((const uint32_t *)chunk_ptr(p, c))[w]);
+}
+// Returns a backward-linked chain of chunks to the pool.
+__device__ __forceinline__ void free_chain(const ChunkPool &p, int c, int lane) {
+    for (int guard = 0; c >= 0 && guard < (1 << 24); guard++) {
+        const int prev = (int)chunk_hdr(p, c, 0);
+        pool_free(p, c, lane);
+        c = prev;
+    }
+}
+
+// Traceback of one half by one wave: walks the codes back from the end cell
+// (bi, bj) of the chain ending at chunk `cur` (its fill recorded in the
+// header), staging index entries and records through LDS, returns each chunk
+// to the pool once the walk has left it, and copies the edit runs (end cell
+// first) to the run arena.  maxg bounds the code words of one record.  Frees
+// every chunk it was given; returns the half's status.
+__device__ int trace_half(const ChunkPool &pool, int &hint, int lane, int cur, int bi, int bj, const RunArena &ra,
+                          uint32_t *tb_idx, uint32_t *tb_rec, int maxg, uint64_t &run_off, uint32_t &nruns) {
+    const uint32_t CH = 1u << pool.shift;
+    int status = HALF_OK;
+    uint8_t *cb = nullptr;
+    int k0 = 0;
+    uint32_t fill = 0;
+    const uint32_t RC = (CH - 16) / 4;       // runs per chunk of the run chain
+    wave_sync();
+    const int64_t kk0 = (int64_t)bi + bj;
+    bool bad = false, oom = false;
+    // chunks holding only antidiagonals past the end cell go back at once
+    while (cur >= 0 && (int64_t)chunk_hdr(pool, cur, 1) > kk0) {
+        const int pc = (int)chunk_hdr(pool, cur, 0);
+        pool_free(pool, cur, lane);
+        cur = pc;
+    }
+    if (cur < 0) bad = true;
+    else { cb = chunk_ptr(pool, cur); k0 = (int)chunk_hdr(pool, cur, 1); fill = chunk_hdr(pool, cur, 2); }
+    int rcur = -1;
+    uint32_t rfill = RC, cnt = 0;
+    auto emit = [&](uint32_t w) {
+        if (rfill == RC) {
+            const int nc = pool_alloc(pool, hint, lane);
+            if (nc < 0) return false;
+            if (lane == 0) ((uint32_t *)chunk_ptr(pool, nc))[0] = (uint32_t)rcur;
+            rcur = nc;
+            rfill = 0;
+        }
+        if (lane == 0) ((uint32_t *)(chunk_ptr(pool, rcur) + 16))[rfill] = w;
+        rfill++;
+        cnt++;
+        return true;
+    };
+    int64_t ic = -1;                 // antidiagonal of tb_idx[0] (-1: nothing staged)
+    int64_t rc = -1;                 // chunk offset of tb_rec[0]
+    int ti = bi, tj = bj, state = 0;
+    uint32_t cur_op = 0xffffffffu, cur_len = 0;
+    int64_t guard = 2 * kk0 + 4;
+    while (!bad && !(ti == 0 && tj == 0 && state == 0)) {
+        if (--guard < 0 || ti < 0 || tj < 0) { bad = true; break; }
+        const int64_t kk = (int64_t)ti + tj;
+        if (kk < 1) { bad = true; break; }
+        while (kk < k0) {            // the walk left this chunk
+            const int pc = (int)chunk_hdr(pool, cur, 0);
+            pool_free(pool, cur, lane);
+            cur = pc;
+            if (cur < 0) break;
+            cb = chunk_ptr(pool, cur);
+            k0 = (int)chunk_hdr(pool, cur, 1);
+            fill = chunk_hdr(pool, cur, 2);
+            ic = -1;
+            rc = -1;
+        }
+        if (cur < 0) { bad = true; break; }
+        if (ic < 0 || kk < ic) {
+            ic = max((int64_t)k0, kk - TB_IDX + 1);
+            wave_sync();
+            for (int q = lane; q < TB_IDX; q += 64) {
+                const int64_t kq = ic + q;
+                tb_idx[q] = kq <= kk ? *(const uint32_t *)(cb + CH - 4u * (uint32_t)(kq - k0 + 1)) : 0u;
+            }
+            wave_sync();
+        }
+        const uint32_t rec = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_idx[kk - ic]);
+        if (rec < 16 || rec + 8 > fill) { bad = true; break; }
+        const int64_t wend = min(rc + 4 * TB_REC, (int64_t)fill);   // end of the staged bytes
+        if (rc < 0 || (int64_t)rec < rc || ((int64_t)rec + 8 + 4 * maxg > wend && wend < (int64_t)fill)) {
+            // stage the record bytes that end just past a full record at `rec`
+            const int64_t top = min((int64_t)rec + 8 + 4 * maxg, (int64_t)fill);
+            rc = max((int64_t)0, top - 4 * TB_REC);
+            wave_sync();
+            for (int q = lane; q < TB_REC; q += 64) {
+                const int64_t bo = rc + 4 * q;
+                tb_rec[q] = bo + 4 <= (int64_t)fill ? *(const uint32_t *)(cb + bo) : 0u;
+            }
+            wave_sync();
+        }
+        const uint32_t w0 = (uint32_t)(rec - rc) >> 2;
+        const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0]);
+        const uint32_t hw = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0 + 1]);
+        const uint32_t ng = hw & 0xffffffu, G = hw >> 24;
+        const uint32_t idx = (uint32_t)(ti - (int)r0);
+        if ((uint32_t)ti < r0 || G == 0 || G > 8 || idx / G >= ng || w0 + 2 + idx / G >= TB_REC) {
+            bad = true;
+            break;
+        }
+        const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0 + 2 + idx / G]);
+        const uint32_t code = (word >> (4 * (idx % G))) & 15u;
+        uint32_t op;
+        if (state == 0) {
+            const uint32_t src = code & 3u;
+            if (src == 1) { state = 1; continue; }
+            if (src == 2) { state = 2; continue; }
+            op = 0; ti--; tj--;
+        } else if (state == 1) {
+            op = 1;
+            if (code & 4u) state = 0;
+            tj--;
+        } else {
+            op = 2;
+            if (code & 8u) state = 0;
+            ti--;
+        }
+        if (op == cur_op) {
+            cur_len++;
+        } else {
+            if (cur_len) {
+                if (cnt >= (uint32_t)kk0) { bad = true; break; }     // runs <= operations <= bi + bj
+                if (!emit((cur_len << 2) | cur_op)) { oom = true; break; }
+            }
+            cur_op = op;
+            cur_len = 1;
+        }
+    }
+    if (!bad && !oom && cur_len) {
+        if (cnt >= (uint32_t)kk0) bad = true;
+        else if (!emit((cur_len << 2) | cur_op)) oom = true;
+    }
+    if (bad) status = HALF_TRACE_ERROR;
+    else if (oom) status = HALF_ARENA_OVERFLOW;
+    if (status == HALF_OK) {
+        unsigned long long off = 0;
+        if (lane == 0) off = atomicAdd(ra.head, (unsigned long long)cnt);
+        const uint32_t olo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off);
+        const uint32_t ohi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(off >> 32));
+        off = ((unsigned long long)ohi << 32) | olo;
+        if (off + cnt > ra.cap) {
+            status = HALF_RUNS_OVERFLOW;
+        } else {
+            // the run chain holds runs [j * RC, ...) in its j-th chunk, last chunk first
+            wave_sync();
+            int64_t j = ((int64_t)cnt + RC - 1) / RC - 1;
+            for (int c = rcur; c >= 0 && j >= 0; j--) {
+                const uint64_t lo = (uint64_t)j * RC;
+                const uint32_t m = (uint32_t)min((uint64_t)RC, (uint64_t)cnt - lo);
+                const uint32_t *src = (const uint32_t *)(chunk_ptr(pool, c) + 16);
+                for (uint32_t q = lane; q < m; q += 64) ra.base[off + lo + q] = src[q];
+                const int pc = (int)chunk_hdr(pool, c, 0);
+                pool_free(pool, c, lane);
+                c = pc;
+            }
+            rcur = -1;
+            run_off = off;
+            nruns = cnt;
+        }
+    }
+    free_chain(pool, rcur, lane);
+    free_chain(pool, cur, lane);
+    return status;
+}
+
 template <int C, bool PERM, bool PERSIST>
 __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__ tasks, WorkQueue wq, SeqSetView T,
                                                     SeqSetView Qp, SeqSetView Qm, ScoreDesc sc, ChunkPool pool,
-                                                    RunArena ra, HalfResult *__restrict__ res) {
+                                                    RunArena ra, HalfResult *__restrict__ res, int kcap) {
     static_assert(C <= 8, "one 32-bit record word per lane");
+    static_assert(64 * C + 64 + RING_CHUNK <= RING, "target ring too small for the window");
     typedef Scorer<PERM> S;
     __shared__ int sub[40];
     __shared__ int prof[2][8];
@@ -101,17 +279,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
 
     int hint = (int)((blockIdx.x * 37u) % (unsigned)pool.nwords);
     const uint32_t CH = 1u << pool.shift;
-    auto chunk = [&](int c) { return pool.base + ((uint64_t)(uint32_t)c << pool.shift); };
-    auto hdr = [&](int c, int w) {
-        return (uint32_t)__builtin_amdgcn_readfirstlane((int)((const uint32_t *)chunk(c))[w]);
-    };
-    auto free_chain = [&](int c) {
-        for (int guard = 0; c >= 0 && guard < (1 << 24); guard++) {
-            const int prev = (int)hdr(c, 0);
-            pool_free(pool, c, lane);
-            c = prev;
-        }
-    };
+    auto chunk = [&](int c) { return chunk_ptr(pool, c); };
 
     int64_t item = PERSIST ? -1 : (int64_t)blockIdx.x;
     for (;;) {
@@ -190,8 +358,10 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
             }
         }
         int k = 1;
+        const int klong = kcap > 0 ? kcap : 0x7fffffff;
         for (; status == HALF_OK && k <= kmax32; k++) {
             if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
+            if (k > klong) { status = HALF_LONG; break; }
             int lo = 0x7fffffff, hi = -1;
             if (lmin1 <= lmax1) { lo = lmin1; hi = lmax1 + 1; }
             if (lmin2 <= lmax2) { lo = min(lo, lmin2 + 1); hi = max(hi, lmax2 + 1); }
@@ -368,153 +538,12 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
 
         if (cur >= 0 && lane == 0) ((uint32_t *)cb)[2] = fill;
 
-        // ---- traceback from the end cell, codes read through LDS ----
         uint64_t run_off = 0;
         uint32_t nruns = 0;
-        if (status == HALF_OK && (bi != 0 || bj != 0)) {
-            const uint32_t RC = (CH - 16) / 4;       // runs per chunk of the run chain
-            __syncthreads();
-            const int64_t kk0 = (int64_t)bi + bj;
-            bool bad = false, oom = false;
-            // chunks holding only antidiagonals past the end cell go back at once
-            while (cur >= 0 && (int64_t)hdr(cur, 1) > kk0) {
-                const int pc = (int)hdr(cur, 0);
-                pool_free(pool, cur, lane);
-                cur = pc;
-            }
-            if (cur < 0) bad = true;
-            else { cb = chunk(cur); k0 = (int)hdr(cur, 1); fill = hdr(cur, 2); }
-            int rcur = -1;
-            uint32_t rfill = RC, cnt = 0;
-            auto emit = [&](uint32_t w) {
-                if (rfill == RC) {
-                    const int nc = pool_alloc(pool, hint, lane);
-                    if (nc < 0) return false;
-                    if (lane == 0) ((uint32_t *)chunk(nc))[0] = (uint32_t)rcur;
-                    rcur = nc;
-                    rfill = 0;
-                }
-                if (lane == 0) ((uint32_t *)(chunk(rcur) + 16))[rfill] = w;
-                rfill++;
-                cnt++;
-                return true;
-            };
-            int64_t ic = -1;                 // antidiagonal of tb_idx[0] (-1: nothing staged)
-            int64_t rc = -1;                 // chunk offset of tb_rec[0]
-            int ti = bi, tj = bj, state = 0;
-            uint32_t cur_op = 0xffffffffu, cur_len = 0;
-            int64_t guard = 2 * kk0 + 4;
-            while (!bad && !(ti == 0 && tj == 0 && state == 0)) {
-                if (--guard < 0 || ti < 0 || tj < 0) { bad = true; break; }
-                const int64_t kk = (int64_t)ti + tj;
-                if (kk < 1) { bad = true; break; }
-                while (kk < k0) {            // the walk left this chunk
-                    const int pc = (int)hdr(cur, 0);
-                    pool_free(pool, cur, lane);
-                    cur = pc;
-                    if (cur < 0) break;
-                    cb = chunk(cur);
-                    k0 = (int)hdr(cur, 1);
-                    fill = hdr(cur, 2);
-                    ic = -1;
-                    rc = -1;
-                }
-                if (cur < 0) { bad = true; break; }
-                if (ic < 0 || kk < ic) {
-                    ic = max((int64_t)k0, kk - TB_IDX + 1);
-                    __syncthreads();
-                    for (int q = lane; q < TB_IDX; q += 64) {
-                        const int64_t kq = ic + q;
-                        tb_idx[q] = kq <= kk ? *(const uint32_t *)(cb + CH - 4u * (uint32_t)(kq - k0 + 1)) : 0u;
-                    }
-                    __syncthreads();
-                }
-                const uint32_t rec = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_idx[kk - ic]);
-                if (rec < 16 || rec + 8 > fill) { bad = true; break; }
-                const int64_t wend = min(rc + 4 * TB_REC, (int64_t)fill);   // end of the staged bytes
-                if (rc < 0 || (int64_t)rec < rc || ((int64_t)rec + 8 + 4 * 64 > wend && wend < (int64_t)fill)) {
-                    // stage the record bytes that end just past a full record at `rec`
-                    const int64_t top = min((int64_t)rec + 8 + 4 * 64, (int64_t)fill);
-                    rc = max((int64_t)0, top - 4 * TB_REC);
-                    __syncthreads();
-                    for (int q = lane; q < TB_REC; q += 64) {
-                        const int64_t bo = rc + 4 * q;
-                        tb_rec[q] = bo + 4 <= (int64_t)fill ? *(const uint32_t *)(cb + bo) : 0u;
-                    }
-                    __syncthreads();
-                }
-                const uint32_t w0 = (uint32_t)(rec - rc) >> 2;
-                const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0]);
-                const uint32_t hw = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0 + 1]);
-                const uint32_t ng = hw & 0xffffffu, G = hw >> 24;
-                const uint32_t idx = (uint32_t)(ti - (int)r0);
-                if ((uint32_t)ti < r0 || G == 0 || G > 8 || idx / G >= ng || w0 + 2 + idx / G >= TB_REC) {
-                    bad = true;
-                    break;
-                }
-                const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0 + 2 + idx / G]);
-                const uint32_t code = (word >> (4 * (idx % G))) & 15u;
-                uint32_t op;
-                if (state == 0) {
-                    const uint32_t src = code & 3u;
-                    if (src == 1) { state = 1; continue; }
-                    if (src == 2) { state = 2; continue; }
-                    op = 0; ti--; tj--;
-                } else if (state == 1) {
-                    op = 1;
-                    if (code & 4u) state = 0;
-                    tj--;
-                } else {
-                    op = 2;
-                    if (code & 8u) state = 0;
-                    ti--;
-                }
-                if (op == cur_op) {
-                    cur_len++;
-                } else {
-                    if (cur_len) {
-                        if (cnt >= (uint32_t)kk0) { bad = true; break; }     // runs <= operations <= bi + bj
-                        if (!emit((cur_len << 2) | cur_op)) { oom = true; break; }
-                    }
-                    cur_op = op;
-                    cur_len = 1;
-                }
-            }
-            if (!bad && !oom && cur_len) {
-                if (cnt >= (uint32_t)kk0) bad = true;
-                else if (!emit((cur_len << 2) | cur_op)) oom = true;
-            }
-            if (bad) status = HALF_TRACE_ERROR;
-            else if (oom) status = HALF_ARENA_OVERFLOW;
-            if (status == HALF_OK) {
-                unsigned long long off = 0;
-                if (lane == 0) off = atomicAdd(ra.head, (unsigned long long)cnt);
-                const uint32_t olo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off);
-                const uint32_t ohi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(off >> 32));
-                off = ((unsigned long long)ohi << 32) | olo;
-                if (off + cnt > ra.cap) {
-                    status = HALF_RUNS_OVERFLOW;
-                } else {
-                    // the run chain holds runs [j * RC, ...) in its j-th chunk, last chunk first
-                    __syncthreads();
-                    int64_t j = ((int64_t)cnt + RC - 1) / RC - 1;
-                    for (int c = rcur; c >= 0 && j >= 0; j--) {
-                        const uint64_t lo = (uint64_t)j * RC;
-                        const uint32_t m = (uint32_t)min((uint64_t)RC, (uint64_t)cnt - lo);
-                        const uint32_t *src = (const uint32_t *)(chunk(c) + 16);
-                        for (uint32_t q = lane; q < m; q += 64) ra.base[off + lo + q] = src[q];
-                        const int pc = (int)hdr(c, 0);
-                        pool_free(pool, c, lane);
-                        c = pc;
-                    }
-                    rcur = -1;
-                    run_off = off;
-                    nruns = cnt;
-                }
-            }
-            free_chain(rcur);
-        }
-        free_chain(cur);
+        if (status == HALF_OK && (bi != 0 || bj != 0))
+            status = trace_half(pool, hint, lane, cur, bi, bj, ra, tb_idx, tb_rec, 64, run_off, nruns);
+        else
+            free_chain(pool, cur, lane);
         if (lane == 0) {
             HalfResult o;
             o.best = best;
@@ -531,12 +560,449 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wave-group extension of one long half (Sec. 8: a long anchor-half spread over
+// several warps instead of one).  W waves own consecutive slabs of the window
+// (wave w: lanes w*64 .. w*64+63 of the group, C rows each).  Per antidiagonal
+// each wave computes its slab; the row above its first row, the query code that
+// crosses into it, its lane 0 (needed when the window slides by one lane) and
+// its share of the reductions (live rows, best) go through LDS, and one
+// barrier per antidiagonal makes them visible.  Every wave then derives the
+// same uniform state (range, slide, best, chunk), so control flow never
+// diverges across the barrier.  The records have the single-wave format with
+// W*64 lane groups; wave 0 traces the half back afterwards.
+template <int C, int W>
+struct CoopXch {
+    int bnd[4];           // lane 63, row C-1 after the update: H, F, H of k-1, query code before the shift
+    int l0[7 * C];        // lane 0 after the update: H1, H2, E1, F1, Plo, Phi, Bs (Bs[0] placeholder)
+    int lmin, lmax;       // live rows of the wave (lmin > lmax: none)
+    int vmax, vrow;       // wave maximum of live H and its first row (when above the best)
+    int newchunk, pad;    // wave 0: chunk for the next antidiagonal (-1 none, -2 pool dry)
+};
+
+template <int C, int W, bool PERM>
+__global__ void __launch_bounds__(64 * W) k_ydrop_coop(const HalfTask *__restrict__ tasks,
+                                                       const int32_t *__restrict__ ids, SeqSetView T, SeqSetView Qp,
+                                                       SeqSetView Qm, ScoreDesc sc, ChunkPool pool, RunArena ra,
+                                                       HalfResult *__restrict__ res) {
+    static_assert(C <= 8, "one 32-bit record word per lane");
+    typedef Scorer<PERM> S;
+    constexpr int NT = 64 * W;            // lanes of the group
+    constexpr int NR = NT * C;            // rows of the window
+    constexpr int NV = 7 * C;             // registers of one lane
+    // target codes of the whole window plus margin and a refill chunk
+    constexpr int ARING = NR + 64 + RING_CHUNK <= RING ? RING : (NR + 64 + RING_CHUNK <= 2048 ? 2048 : 4096);
+    static_assert(NR + 64 + RING_CHUNK <= ARING, "target ring too small for the window");
+    __shared__ int sub[40];
+    __shared__ int prof[2][8];
+    __shared__ uint8_t aring[ARING], bring[RING];
+    __shared__ uint32_t tb_idx[TB_IDX], tb_rec[TB_REC];
+    __shared__ CoopXch<C, W> xch[2][W];
+    __shared__ int dump[NT * NV];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    if (tid < 40) sub[tid] = (tid & 7) < 5 ? sc.sub[tid >> 3][tid & 7] : 0;
+    if (tid < 5) {
+        uint32_t lo = 0;
+        for (int b = 0; b < 4; b++) lo |= ((uint32_t)sc.sub[tid][b] & 0xffu) << (8 * b);
+        prof[0][tid] = (int)lo;
+        prof[1][tid] = (int)((uint32_t)sc.sub[tid][4] & 0xffu);
+    }
+    __syncthreads();
+    const int e = sc.gap_extend, oe = sc.gap_open + sc.gap_extend, Y = sc.ydrop;
+    int hint = (int)((blockIdx.x * 37u) % (unsigned)pool.nwords);
+    const uint32_t CH = 1u << pool.shift;
+    const int64_t hid = ids ? ids[blockIdx.x] : (int64_t)blockIdx.x;
+    const HalfTask tk = tasks[hid];
+    const SeqSetView Q = tk.qset ? Qm : Qp;
+    const int64_t nA = tk.nA, nB = tk.nB;
+    const int64_t kmax = nA + nB;
+    const int nA32 = (int)min(nA, (int64_t)ROW_LIMIT + 4096);
+    const int nB32 = (int)min(nB, (int64_t)ROW_LIMIT + 4096);
+    const int kmax32 = (int)min(kmax, (int64_t)ROW_LIMIT + 4096);
+    int a_hi = 0, b_hi = 0;
+    while (a_hi < NR + 64) { ring_fill<NT, ARING>(aring, T, tk.a0, tk.adir, nA, a_hi, tid); a_hi += RING_CHUNK; }
+    while (b_hi < 128) { ring_fill<NT>(bring, Q, tk.b0, tk.bdir, nB, b_hi, tid); b_hi += RING_CHUNK; }
+    auto acode = [&](int ia) { return ia < 0 ? 4 : (int)aring[ia & (ARING - 1)]; };
+    auto bcode = [&](int jb) {
+        if (jb < 0) return 4;
+        if (jb < b_hi - RING) return codeB(Q, tk, jb);
+        return (int)bring[jb & (RING - 1)];
+    };
+    auto plo_of = [&](int a) { return PERM ? prof[0][a] : a * 8; };
+    auto phi_of = [&](int a) { return PERM ? prof[1][a] : 0; };
+    int bw0 = -(1 << 30), bwa = 4, bwb = 4;
+    auto bcode_next = [&](int pos) {          // uniform position; every wave calls it
+        if (pos < bw0 || pos >= bw0 + 128) {
+            while (b_hi < pos + 128) { ring_fill<NT>(bring, Q, tk.b0, tk.bdir, nB, b_hi, tid); b_hi += RING_CHUNK; }
+            bw0 = pos - 64;
+            bwa = bcode(bw0 + lane);
+            bwb = bcode(bw0 + 64 + lane);
+        }
+        const int d = pos - bw0;
+        return d < 64 ? __builtin_amdgcn_readlane(bwa, d) : __builtin_amdgcn_readlane(bwb, d - 64);
+    };
+
+    int H1[C], H2[C], E1[C], F1[C], Plo[C], Phi[C], Bs[C];
+    int base = 0;
+#pragma unroll
+    for (int r = 0; r < C; r++) {
+        const int i = tid * C + r;
+        H1[r] = (i == 0) ? 0 : NEG;
+        H2[r] = NEG;
+        E1[r] = NEG;
+        F1[r] = NEG;
+        const int a = acode(i - 1);
+        Plo[r] = plo_of(a);
+        Phi[r] = phi_of(a);
+        Bs[r] = S::bsel(i == 0 ? bcode(0) : 4);
+    }
+    int best = 0, bi = 0, bj = 0;
+    uint64_t cells = 1;
+    int lmin1 = 0, lmax1 = 0, lmin2 = 1, lmax2 = 0;
+    int status = HALF_OK;
+    // chunk of the code chain (uniform): wave 0 takes it, everyone learns it through LDS
+    if (w == 0) {
+        const int c0 = pool_alloc(pool, hint, lane);
+        if (lane == 0) {
+            xch[1][0].newchunk = c0 >= 0 ? c0 : -2;
+            if (c0 >= 0) {
+                ((uint32_t *)chunk_ptr(pool, c0))[0] = 0xffffffffu;
+                ((uint32_t *)chunk_ptr(pool, c0))[1] = 1u;
+            }
+        }
+    }
+    __syncthreads();
+    int cur = xch[1][0].newchunk;
+    if (cur < 0) { status = HALF_ARENA_OVERFLOW; cur = -1; }
+    uint8_t *cb = cur >= 0 ? chunk_ptr(pool, cur) : nullptr;
+    int k0 = 1;
+    uint32_t fill = 16;
+    constexpr uint32_t MAXNEED = 8 + 4 * NT;
+    int k = 1;
+    for (; status == HALF_OK && k <= kmax32; k++) {
+        if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
+        const int par = k & 1, prv = par ^ 1;
+        // the query code that crossed from wave w-1 into this wave's lane 0
+        if (k >= 2 && w > 0 && lane == 0) Bs[0] = xch[prv][w - 1].bnd[3];
+        int lo = 0x7fffffff, hi = -1;
+        if (lmin1 <= lmax1) { lo = lmin1; hi = lmax1 + 1; }
+        if (lmin2 <= lmax2) { lo = min(lo, lmin2 + 1); hi = max(hi, lmax2 + 1); }
+        const int clo = max(0, k - nB32);
+        const int chi = min(nA32, k);
+        lo = max(lo, clo);
+        hi = min(hi, chi);
+        const bool nonempty = lo <= hi;
+        // the row above this wave's first row (wave 0: none)
+        int bH = NEG, bF = NEG, bD = NEG;
+        if (w > 0 && k >= 2) {
+            bH = xch[prv][w - 1].bnd[0];
+            bF = xch[prv][w - 1].bnd[1];
+            bD = xch[prv][w - 1].bnd[2];
+        }
+        if (nonempty) {
+            const int s = (lo - 1 - base) / C;
+            if (s >= 1) {
+                while (a_hi < base + s * C + NR + 64) {
+                    ring_fill<NT, ARING>(aring, T, tk.a0, tk.adir, nA, a_hi, tid);
+                    a_hi += RING_CHUNK;
+                }
+                if (s == 1 && k >= 2) {
+                    // lane 63 takes the next wave's lane 0 (the last wave: new rows)
+#pragma unroll
+                    for (int r = 0; r < C; r++) {
+                        int iH1, iH2, iE1, iF1, iPlo, iPhi, iBs;
+                        if (w < W - 1) {
+                            const int *l0 = xch[prv][w + 1].l0;
+                            iH1 = l0[r];
+                            iH2 = l0[C + r];
+                            iE1 = l0[2 * C + r];
+                            iF1 = l0[3 * C + r];
+                            iPlo = l0[4 * C + r];
+                            iPhi = l0[5 * C + r];
+                            iBs = r ? l0[6 * C + r] : xch[prv][w].bnd[3];
+                        } else {
+                            const int i_new = base + NR + r;
+                            const int a = acode(i_new - 1);
+                            iH1 = iH2 = iE1 = iF1 = NEG;
+                            iPlo = plo_of(a);
+                            iPhi = phi_of(a);
+                            iBs = S::bsel(bcode(k - i_new - 1));
+                        }
+                        H1[r] = dpp_shl1(iH1, H1[r]);
+                        H2[r] = dpp_shl1(iH2, H2[r]);
+                        E1[r] = dpp_shl1(iE1, E1[r]);
+                        F1[r] = dpp_shl1(iF1, F1[r]);
+                        Plo[r] = dpp_shl1(iPlo, Plo[r]);
+                        Phi[r] = dpp_shl1(iPhi, Phi[r]);
+                        Bs[r] = dpp_shl1(iBs, Bs[r]);
+                    }
+                    // the row above wave w's new first row was wave w's old lane 0, row C-1
+                    if (w > 0) {
+                        const int *l0 = xch[prv][w].l0;
+                        bH = l0[C - 1];
+                        bF = l0[3 * C + C - 1];
+                        bD = l0[C + C - 1];
+                    }
+                } else {
+                    // any shift: through the whole window in LDS
+#pragma unroll
+                    for (int r = 0; r < C; r++) {
+                        int *d = dump + tid * NV;
+                        d[r] = H1[r];
+                        d[C + r] = H2[r];
+                        d[2 * C + r] = E1[r];
+                        d[3 * C + r] = F1[r];
+                        d[4 * C + r] = Plo[r];
+                        d[5 * C + r] = Phi[r];
+                        d[6 * C + r] = Bs[r];
+                    }
+                    __syncthreads();
+                    const int src = tid + s;
+#pragma unroll
+                    for (int r = 0; r < C; r++) {
+                        if (src < NT) {
+                            const int *d = dump + src * NV;
+                            H1[r] = d[r];
+                            H2[r] = d[C + r];
+                            E1[r] = d[2 * C + r];
+                            F1[r] = d[3 * C + r];
+                            Plo[r] = d[4 * C + r];
+                            Phi[r] = d[5 * C + r];
+                            Bs[r] = d[6 * C + r];
+                        } else {
+                            const int i_new = base + s * C + tid * C + r;
+                            const int a = acode(i_new - 1);
+                            H1[r] = H2[r] = E1[r] = F1[r] = NEG;
+                            Plo[r] = plo_of(a);
+                            Phi[r] = phi_of(a);
+                            Bs[r] = S::bsel(bcode(k - i_new - 1));
+                        }
+                    }
+                    bH = bF = bD = NEG;
+                    const int up = w * 64 - 1 + s;          // old lane of the row above wave w's first row
+                    if (w > 0 && up < NT) {
+                        const int *d = dump + up * NV;
+                        bH = d[C - 1];
+                        bF = d[3 * C + C - 1];
+                        bD = d[C + C - 1];
+                    }
+                    __syncthreads();
+                }
+                base += s * C;
+            }
+            if (hi > base + NR - 1) { status = HALF_WIDTH_OVERFLOW; break; }
+        }
+        const int thr = best - Y;
+        const int upH = dpp_shr1(bH, H1[C - 1]);
+        const int upF = dpp_shr1(bF, F1[C - 1]);
+        const int upD = dpp_shr1(bD, H2[C - 1]);
+        int Hn[C], En[C], Fn[C];
+        uint32_t nib = 0, lmask = 0;
+        int lmax = NEG;
+        auto cell_pass = [&](auto edge_tag) {
+            constexpr bool EDGE = decltype(edge_tag)::value;
+            const int i0 = base + tid * C;
+#pragma unroll
+            for (int r = 0; r < C; r++) {
+                const int Hu = r ? H1[r - 1] : upH;
+                const int Fu = r ? F1[r - 1] : upF;
+                const int Hd = r ? H2[r - 1] : upD;
+                const int hlo = H1[r] - oe, ele = E1[r] - e;
+                const int huo = Hu - oe, fue = Fu - e;
+                const int E = imax3(hlo, ele, NEG);
+                const int F = imax3(huo, fue, NEG);
+                const int G = Hd + S::score(Plo[r], Phi[r], Bs[r], sub);
+                const int H = imax3(G, E, F);
+                bool live = H >= thr;
+                if (EDGE) {
+                    const bool v = (unsigned)(i0 + r - clo) <= (unsigned)(chi - clo);
+                    live = live && v;
+                    En[r] = v ? E : NEG;
+                    Fn[r] = v ? F : NEG;
+                } else {
+                    En[r] = E;
+                    Fn[r] = F;
+                }
+                Hn[r] = live ? H : NEG;
+                lmask |= live ? (1u << r) : 0u;
+                const uint32_t code = (H == G ? 0u : (H == E ? 1u : 2u)) | (hlo >= ele ? 4u : 0u) |
+                                      (huo >= fue ? 8u : 0u);
+                nib |= code << (4 * r);
+                lmax = imax(lmax, Hn[r]);
+            }
+        };
+        const bool edge = base < clo || base + NR - 1 > nA32;
+        if (edge) cell_pass(std::true_type());
+        else cell_pass(std::false_type());
+        // this wave's share of the reductions
+        int wmin = 1, wmax = 0;
+        {
+            const uint64_t m = __ballot(lmask != 0);
+            if (m) {
+                const int L1 = __builtin_ctzll(m), L2 = 63 - __builtin_clzll(m);
+                const uint32_t f1 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L1);
+                const uint32_t f2 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L2);
+                wmin = base + (w * 64 + L1) * C + __builtin_ctz(f1);
+                wmax = base + (w * 64 + L2) * C + (31 - __builtin_clz(f2));
+            }
+        }
+        int vmax = NEG, vrow = 0x7fffffff;
+        if (__ballot(lmax > best)) {
+            vmax = wave_max_dpp(lmax);
+            uint32_t eq = 0;
+#pragma unroll
+            for (int r = 0; r < C; r++) eq |= (Hn[r] == vmax) ? (1u << r) : 0u;
+            const uint64_t m = __ballot(eq != 0);
+            const int L = __builtin_ctzll(m);
+            vrow = base + (w * 64 + L) * C + __builtin_ctz((uint32_t)__builtin_amdgcn_readlane((int)eq, L));
+        }
+        // record of antidiagonal k: the lane groups covering [lo, hi]
+        int g_lo = 0, g_hi = -1;
+        if (nonempty) {
+            g_lo = (lo - base) / C;
+            g_hi = (hi - base) / C;
+        }
+        const uint32_t ng = (uint32_t)(g_hi - g_lo + 1);
+        const uint32_t need = 8 + 4 * ng;
+        {
+            uint32_t *rec = (uint32_t *)(cb + fill);
+            if (tid >= g_lo && tid <= g_hi) rec[2 + tid - g_lo] = nib;
+            if (tid == 0) {
+                *(uint2 *)rec = make_uint2(nonempty ? (uint32_t)(base + g_lo * C) : 0u, rec_head_word(ng, C));
+                *(uint32_t *)(cb + CH - 4u * (uint32_t)(k - k0 + 1)) = fill;
+            }
+        }
+        fill += need;
+        if (nonempty) cells += (uint64_t)(hi - lo + 1);
+        // state update and the query-code shift (the code entering wave 0)
+        const int bs_out = Bs[C - 1];
+        const int code_in = S::bsel(bcode_next(k - base));
+        {
+            const int carry = dpp_shr1(w == 0 ? code_in : S::bsel(4), Bs[C - 1]);
+#pragma unroll
+            for (int r = C - 1; r > 0; r--) Bs[r] = Bs[r - 1];
+            Bs[0] = carry;
+        }
+        CoopXch<C, W> &X = xch[par][w];
+        if (lane == 63) {
+            X.bnd[0] = Hn[C - 1];
+            X.bnd[1] = Fn[C - 1];
+            X.bnd[2] = H1[C - 1];
+            X.bnd[3] = bs_out;
+        }
+#pragma unroll
+        for (int r = 0; r < C; r++) {
+            H2[r] = H1[r];
+            H1[r] = Hn[r];
+            E1[r] = En[r];
+            F1[r] = Fn[r];
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < C; r++) {
+                X.l0[r] = H1[r];
+                X.l0[C + r] = H2[r];
+                X.l0[2 * C + r] = E1[r];
+                X.l0[3 * C + r] = F1[r];
+                X.l0[4 * C + r] = Plo[r];
+                X.l0[5 * C + r] = Phi[r];
+                X.l0[6 * C + r] = Bs[r];
+            }
+            X.lmin = wmin;
+            X.lmax = wmax;
+            X.vmax = vmax;
+            X.vrow = vrow;
+        }
+        // room for the next antidiagonal's record: wave 0 takes a new chunk now
+        if (w == 0) {
+            int nc = -1;
+            if (fill + MAXNEED + 4u * (uint32_t)(k + 1 - k0 + 1) > CH) {
+                nc = pool_alloc(pool, hint, lane);
+                if (nc >= 0 && lane == 0) {
+                    ((uint32_t *)cb)[2] = fill;
+                    uint32_t *nh = (uint32_t *)chunk_ptr(pool, nc);
+                    nh[0] = (uint32_t)cur;
+                    nh[1] = (uint32_t)(k + 1);
+                }
+                if (nc < 0) nc = -2;
+            }
+            if (lane == 0) X.newchunk = nc;
+        }
+        __syncthreads();
+        // uniform state from every wave's share
+        int lmin0 = 1, lmax0 = 0, gmax = NEG, grow = 0x7fffffff;
+#pragma unroll
+        for (int v = 0; v < W; v++) {
+            const CoopXch<C, W> &Z = xch[par][v];
+            if (Z.lmin <= Z.lmax) {
+                if (lmin0 > lmax0) { lmin0 = Z.lmin; lmax0 = Z.lmax; }
+                else { lmin0 = min(lmin0, Z.lmin); lmax0 = max(lmax0, Z.lmax); }
+            }
+            if (Z.vmax > gmax) { gmax = Z.vmax; grow = Z.vrow; }
+        }
+        if (gmax > best) {
+            best = gmax;
+            bi = grow;
+            bj = k - bi;
+            if (best >= SFE_SCORE_LIMIT) { status = HALF_SCORE_RANGE; break; }
+        }
+        const int nc = xch[par][0].newchunk;
+        if (nc == -2) { status = HALF_ARENA_OVERFLOW; break; }
+        if (nc >= 0) {
+            cur = nc;
+            cb = chunk_ptr(pool, nc);
+            k0 = k + 1;
+            fill = 16;
+        }
+        const bool stop = (lmin0 > lmax0) && (lmin1 > lmax1);
+        lmin2 = lmin1; lmax2 = lmax1;
+        lmin1 = lmin0; lmax1 = lmax0;
+        if (stop) break;
+    }
+    __syncthreads();
+    if (cur >= 0 && tid == 0) ((uint32_t *)cb)[2] = fill;
+    __syncthreads();
+    if (w == 0) {
+        uint64_t run_off = 0;
+        uint32_t nruns = 0;
+        if (status == HALF_OK && (bi != 0 || bj != 0))
+            status = trace_half(pool, hint, lane, cur, bi, bj, ra, tb_idx, tb_rec, NT, run_off, nruns);
+        else
+            free_chain(pool, cur, lane);
+        if (lane == 0) {
+            HalfResult o;
+            o.best = best;
+            o.i_end = bi;
+            o.j_end = bj;
+            o.status = status;
+            o.cells = cells;
+            o.tb_page = run_off;
+            o.tb_end = nruns;
+            o.k_last = (int32_t)min((int64_t)k, kmax);
+            res[hid] = o;
+        }
+    }
+}
+
+void launch_ydrop_coop(int cells_per_lane, bool perm, const HalfTask *tasks, const int32_t *ids, int64_t n,
+                       SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, ChunkPool pool, RunArena ra,
+                       HalfResult *res, hipStream_t st) {
+    if (n <= 0) return;
+    if (cells_per_lane <= 2) {
+        if (perm) k_ydrop_coop<2, 4, true><<<(unsigned)n, 256, 0, st>>>(tasks, ids, T, Qp, Qm, sc, pool, ra, res);
+        else k_ydrop_coop<2, 4, false><<<(unsigned)n, 256, 0, st>>>(tasks, ids, T, Qp, Qm, sc, pool, ra, res);
+    } else {
+        if (perm) k_ydrop_coop<4, 4, true><<<(unsigned)n, 256, 0, st>>>(tasks, ids, T, Qp, Qm, sc, pool, ra, res);
+        else k_ydrop_coop<4, 4, false><<<(unsigned)n, 256, 0, st>>>(tasks, ids, T, Qp, Qm, sc, pool, ra, res);
+    }
+}
+
 void launch_ydrop_fused(int cells_per_lane, bool perm, bool persistent, const HalfTask *tasks, WorkQueue wq,
                         int64_t grid, SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, ChunkPool pool,
-                        RunArena ra, HalfResult *res, hipStream_t st) {
+                        RunArena ra, HalfResult *res, int kcap, hipStream_t st) {
     if (grid <= 0) return;
 #define SFE_LAUNCH(CC, PP, QQ) \
-    k_ydrop_fused<CC, PP, QQ><<<(unsigned)grid, 64, 0, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res)
+    k_ydrop_fused<CC, PP, QQ><<<(unsigned)grid, 64, 0, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res, kcap)
 #define SFE_BY_C(PP, QQ)                                  \
     do {                                                  \
         if (cells_per_lane <= 2) SFE_LAUNCH(2, PP, QQ);   \

@@ -89,6 +89,7 @@ struct HalfTask {
 #define HALF_SCORE_RANGE 3      // a score reached 2^29 (or the band 2^30 antidiagonals)
 #define HALF_RUNS_OVERFLOW 4    // the run arena is full
 #define HALF_TRACE_ERROR 5      // traceback codes inconsistent (internal error)
+#define HALF_LONG 7             // reached the antidiagonal cap of its launch (re-run by a wave group)
 
 struct HalfResult {
     int32_t best, i_end, j_end, status;

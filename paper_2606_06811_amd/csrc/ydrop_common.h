@@ -60,15 +60,20 @@ template <> struct Scorer<false> {
 };
 
 // Loads codes of positions [from, from + RING_CHUNK) of one side of a half into
-// its LDS ring (index & (RING - 1)); positions outside [0, n) read as N.
+// its LDS ring of RS codes (index & (RS - 1)); positions outside [0, n) read as
+// N.  All NT threads of the block take part (tid = thread index).  A ring must
+// hold every position the band window can read: the window, its slide margin
+// and one refill chunk.
+template <int NT = 64, int RS = RING>
 __device__ __forceinline__ void ring_fill(uint8_t *ring, const SeqSetView &S, int64_t p0, int64_t dir, int64_t n,
-                                          int64_t from, int lane) {
+                                          int64_t from, int tid) {
+    static_assert((RS & (RS - 1)) == 0 && RS >= RING_CHUNK, "ring size");
 #pragma unroll 4
-    for (int x = lane; x < RING_CHUNK; x += 64) {
+    for (int x = tid; x < RING_CHUNK; x += NT) {
         const int64_t j = from + x;
         int c = 4;
         if (j >= 0 && j < n) c = base_code(S, p0 + dir * j);
-        ring[j & (RING - 1)] = (uint8_t)c;
+        ring[j & (RS - 1)] = (uint8_t)c;
     }
     __syncthreads();
 }

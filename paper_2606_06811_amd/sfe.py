@@ -58,6 +58,10 @@ class _AlignOpts(ctypes.Structure):
                 ("arena_bytes", ctypes.c_int64), ("model", ctypes.c_void_p)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("wave_group_cap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("seed_hits", "hsps_raw", "hsps", "rounds", "extensions", "committed",
                                                "shadow", "cells", "overflow_reruns", "xdrop_columns",
@@ -89,6 +93,8 @@ def lib():
                                        ctypes.POINTER(I64)]
         L.sfe_align.argtypes = [P, P, ctypes.POINTER(_Seq), I32, ctypes.POINTER(_Scoring), ctypes.POINTER(_AlignOpts),
                                 P, I64, ctypes.POINTER(I64), P, I64, ctypes.POINTER(I64), ctypes.POINTER(_Stats)]
+        L.sfe_ctx_set_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
+        L.sfe_ctx_get_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
         L.sfe_hsp_features.argtypes = [P, P, ctypes.POINTER(_Seq), I32, P, I64, P]
         L.sfe_extension_log.argtypes = [P, P, ctypes.POINTER(_Seq), I32, P, I64, ctypes.POINTER(_Scoring), P, P]
         L.sfe_model_create.argtypes = [P, P, ctypes.POINTER(P)]
@@ -102,7 +108,7 @@ def lib():
         L.sfe_last_error.argtypes = [P]
         L.sfe_last_error.restype = ctypes.c_char_p
         for f in ("sfe_ctx_create", "sfe_build_index", "sfe_seed_hits", "sfe_ungapped_xdrop", "sfe_gapped_ydrop",
-                  "sfe_align", "sfe_hsp_features", "sfe_extension_log", "sfe_model_create", "sfe_model_params",
+                  "sfe_align", "sfe_ctx_set_tuning", "sfe_ctx_get_tuning", "sfe_hsp_features", "sfe_extension_log", "sfe_model_create", "sfe_model_params",
                   "sfe_model_predict", "sfe_model_grad", "sfe_model_train"):
             getattr(L, f).restype = I32
         _lib = L
@@ -188,6 +194,18 @@ class Index:
 
 def sfe_ctx_create(device: int = 0, stream=None) -> Context:
     return Context(device, stream)
+
+
+def sfe_ctx_set_tuning(ctx: Context, wave_group_cap: int = 0):
+    t = _Tuning()
+    t.wave_group_cap = int(wave_group_cap)
+    _check(lib().sfe_ctx_set_tuning(ctx.ptr, ctypes.byref(t)), ctx)
+
+
+def sfe_ctx_get_tuning(ctx: Context) -> dict:
+    t = _Tuning()
+    _check(lib().sfe_ctx_get_tuning(ctx.ptr, ctypes.byref(t)), ctx)
+    return {"wave_group_cap": t.wave_group_cap}
 
 
 def sfe_build_index(ctx: Context, target, pattern: str = "1110100110010101111", transitions: int = 1,

@@ -260,6 +260,21 @@ def test_align_parity(ctx, align_case, K, cpl, policy, schedule):
     assert st["extensions"] >= ref["n_extensions"]
 
 
+@pytest.mark.parametrize("policy", [0, 1])
+def test_align_parity_wave_groups(ctx, align_case, policy):
+    """Long halves restarted on wave groups inside the whole pipeline."""
+    log(f"align with wave groups, policy={policy}")
+    T, Q, ref = align_case
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=1024)
+    try:
+        alns, ops, st = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), policy=policy)
+    finally:
+        sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
+    compare_alignments(alns, ops, ref)
+    assert st["overflow_reruns"] > 0
+
+
 @pytest.mark.parametrize("arena,schedule", [(1 << 20, PLAIN), (1 << 20, PERSIST), (3 << 18, PLAIN)])
 def test_align_tiny_arena_reruns(align_case, arena, schedule):
     """A small traceback arena (fresh context, so the run arena starts small
@@ -277,3 +292,33 @@ def test_align_tiny_arena_reruns(align_case, arena, schedule):
         idx.close()
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("n,div,indel", [(30_000, 0.10, 0.02), (20_000, 0.30, 0.05), (12_000, 0.0, 0.0)])
+@pytest.mark.parametrize("cap", [0, 2048])
+def test_long_halves_on_wave_groups(ctx, n, div, indel, cap):
+    """Halves longer than the one-wave antidiagonal cap restart on a group of
+    waves; results must equal the oracle's (score, ends, cells, ops)."""
+    log(f"long halves n={n} div={div} wave-group cap {cap}")
+    sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=cap)
+    rng = synth.rng_for(500 + n)
+    t = synth.iid_codes(rng, n)
+    q, _ = synth.mutate(rng, t, np.zeros(n, bool), div, indel=indel)
+    T, Q = synth.to_ascii(t), [synth.to_ascii(q)]
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    h = np.zeros(3, sfe.HSP_DTYPE)
+    m = min(len(T), len(Q[0]))
+    for x, (a, L) in enumerate([(200, 1), (m // 2, 1), (m - 300, 1)]):
+        h[x] = (a, a, L, 0, 0, 0, (0, 0, 0))
+    alns, ops = sfe.sfe_gapped_ydrop(ctx, idx, Q, h, dict(synth.SCORING))
+    tc, _ = oracle.encode(T)
+    qc, _ = oracle.encode(Q[0])
+    off = 0
+    for x in range(h.shape[0]):
+        a, o = oracle.extend(tc, qc, int(h["t0"][x]), int(h["q0"][x]), dict(synth.SCORING))
+        for f in ("t_start", "t_end", "q_start", "q_end", "score", "cells"):
+            assert int(alns[f][x]) == int(a[f]), (x, f, int(alns[f][x]), int(a[f]))
+        if alns["flags"][x] & sfe.SFE_ALN_PASSED:
+            g = ops[int(alns["ops_offset"][x]):int(alns["ops_offset"][x]) + int(alns["ops_len"][x])]
+            assert np.array_equal(g, o), x
+    sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
