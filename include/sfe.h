@@ -236,10 +236,32 @@ sfe_status sfe_align(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries,
  *   model predicts to be longer start there.  0 = never (default). */
 typedef struct {
     int32_t wave_group_cap;
-    int32_t reserved[7];
+    int32_t use_graphs;     /* 1: sfe_model_train records its whole step sequence in one hipGraph
+                               and launches it once (same kernels, same order, same results) */
+    int32_t reserved[6];
 } sfe_tuning;
 sfe_status sfe_ctx_set_tuning(sfe_ctx *ctx, const sfe_tuning *t);
 sfe_status sfe_ctx_get_tuning(const sfe_ctx *ctx, sfe_tuning *t);
+
+/* Autotuner.  Times sfe_align on a sample of the workload (the first
+ * sample_bases of every query, all against idx) under each candidate schedule
+ * -- rows per lane 4 / 6 / 8 in the first band window, plain or persistent
+ * launch (persistent with opts->model when one is given), wave groups for
+ * long halves off or after 8192 antidiagonals -- and keeps the fastest: the
+ * context's wave_group_cap is set and opts->max_cells_per_lane / schedule are
+ * written.  Other fields of *opts are used as given.  report (may be NULL)
+ * receives every candidate's extension time.  No choice changes results. */
+typedef struct {
+    int32_t cells_per_lane, schedule, wave_group_cap, pad;
+    double ms_extend;
+} sfe_tune_entry;
+typedef struct {
+    int32_t n, best;
+    sfe_tune_entry entries[16];
+} sfe_tune_report;
+sfe_status sfe_autotune(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries, int32_t nq,
+                        const sfe_scoring *sc, int64_t sample_bases, sfe_align_opts *opts,
+                        sfe_tune_report *report);
 
 /* ---------------------------------------------------------------------------
  * Learned cost model.  The cost of an anchor-half is unknown until it has run
@@ -280,7 +302,9 @@ sfe_status sfe_hsp_features(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *q
 sfe_status sfe_extension_log(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries, int32_t nq,
                              const sfe_hsp *hsps, int64_t n, const sfe_scoring *sc,
                              float *features, float *targets);
-/* A model on ctx's device with the given initial parameters (host or device). */
+/* A model on ctx's device with the given initial parameters (host or device).
+ * It runs on ctx's stream: destroy it before ctx (destroying it after ctx is
+ * allowed; using it is not). */
 sfe_status sfe_model_create(sfe_ctx *ctx, const float *params, sfe_model **out);
 void sfe_model_destroy(sfe_model *m);
 sfe_status sfe_model_params(const sfe_model *m, float *params);

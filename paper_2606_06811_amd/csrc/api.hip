@@ -99,6 +99,7 @@ struct sfe_ctx {
 
 struct sfe_index {
     sfe_ctx *ctx = nullptr;
+    int device = 0;
     SeqSet target;
     int64_t nt = 0;
     SeedDesc sd{};
@@ -109,7 +110,8 @@ struct sfe_index {
 };
 
 struct sfe_model {
-    sfe_ctx *ctx = nullptr;
+    sfe_ctx *ctx = nullptr;             // must outlive the model (its stream runs the kernels)
+    int device = 0;
     DBuf master, m, v, p16;             // FP32 master weights, Adam moments, BF16 copy
     DBuf part, sse, loss, x, t, ids, y, grad;
     int64_t step = 0;                   // Adam steps taken
@@ -833,6 +835,7 @@ struct SegList {
 
 sfe_status guard(sfe_ctx *c, const std::function<void()> &f) {
     try {
+        (void)hipGetLastError();        // an error left by an unrelated earlier call is not this call's
         if (c) HIPCHK(hipSetDevice(c->device));
         f();
         return SFE_OK;
@@ -899,6 +902,7 @@ sfe_status sfe_build_index(sfe_ctx *c, const sfe_seq *target, const sfe_seed_spe
     if (!ix) return SFE_ENOMEM;
     sfe_status st = guard(c, [&] {
         ix->ctx = c;
+        ix->device = c->device;
         ix->sd = parse_seed(seed);
         std::vector<int64_t> starts;
         pack_set(c, target, 1, 0, ix->target, starts);
@@ -932,8 +936,9 @@ sfe_status sfe_build_index(sfe_ctx *c, const sfe_seq *target, const sfe_seed_spe
 
 void sfe_index_destroy(sfe_index *ix) {
     if (!ix) return;
-    if (ix->ctx) (void)hipSetDevice(ix->ctx->device);
+    (void)hipSetDevice(ix->device);
     delete ix;
+    (void)hipGetLastError();
 }
 
 sfe_status sfe_seed_hits(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, int32_t strands,
@@ -1342,8 +1347,71 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
 }
 
 sfe_status sfe_ctx_set_tuning(sfe_ctx *c, const sfe_tuning *t) {
-    if (!c || !t || t->wave_group_cap < 0) return SFE_EINVAL;
+    if (!c || !t || t->wave_group_cap < 0 || t->use_graphs < 0 || t->use_graphs > 1) return SFE_EINVAL;
     c->tuning = *t;
+    return SFE_OK;
+}
+
+sfe_status sfe_autotune(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, const sfe_scoring *scp,
+                        int64_t sample_bases, sfe_align_opts *opts, sfe_tune_report *report) {
+    if (!c || !ix || !opts || nq < 1 || !queries || sample_bases < 1) return SFE_EINVAL;
+    std::vector<sfe_seq> sample((size_t)nq);
+    for (int32_t i = 0; i < nq; i++) {
+        sample[i] = queries[i];
+        sample[i].length = std::min<int64_t>(queries[i].length, sample_bases);
+    }
+    const sfe_tuning saved = c->tuning;
+    sfe_tune_report rep{};
+    double best_ms = 1e300;
+    sfe_align_opts best = *opts;
+    int32_t best_cap = saved.wave_group_cap;
+    std::vector<sfe_aln> out(1 << 16);
+    std::vector<uint32_t> ops(1 << 22);
+    const int cpls[3] = {4, 6, 8};
+    const int caps[2] = {0, 8192};
+    bool first = true;
+    for (int cap : caps)
+        for (int sched = 0; sched < 2; sched++)
+            for (int cpl : cpls) {
+                sfe_align_opts o = *opts;
+                o.max_cells_per_lane = cpl;
+                o.schedule = sched;
+                if (sched == SFE_SCHED_PLAIN) o.model = nullptr;
+                c->tuning.wave_group_cap = cap;
+                sfe_stats st{};
+                int64_t na = 0, no = 0;
+                sfe_status r = SFE_OK;
+                for (int rep_i = first ? 2 : 1; rep_i > 0; rep_i--) {      // the first run also warms up
+                    for (;;) {
+                        r = sfe_align(c, ix, sample.data(), nq, scp, &o, out.data(), (int64_t)out.size(), &na,
+                                      ops.data(), (int64_t)ops.size(), &no, &st);
+                        if (r == SFE_ECAPACITY && (na > (int64_t)out.size() || no > (int64_t)ops.size())) {
+                            out.resize(std::max<size_t>(out.size(), (size_t)na));
+                            ops.resize(std::max<size_t>(ops.size(), (size_t)no));
+                            continue;
+                        }
+                        break;
+                    }
+                    if (r != SFE_OK) break;
+                }
+                first = false;
+                if (r != SFE_OK) {
+                    c->tuning = saved;
+                    return r;
+                }
+                if (rep.n < 16) rep.entries[rep.n++] = sfe_tune_entry{cpl, sched, cap, 0, st.ms_extend};
+                if (st.ms_extend < best_ms) {
+                    best_ms = st.ms_extend;
+                    best = o;
+                    best_cap = cap;
+                    rep.best = rep.n - 1;
+                }
+            }
+    c->tuning = saved;
+    c->tuning.wave_group_cap = best_cap;
+    opts->max_cells_per_lane = best.max_cells_per_lane;
+    opts->schedule = best.schedule;
+    if (report) *report = rep;
     return SFE_OK;
 }
 
@@ -1412,6 +1480,7 @@ sfe_status sfe_model_create(sfe_ctx *c, const float *params, sfe_model **out) {
     sfe_model *m = new (std::nothrow) sfe_model;
     if (!m) return SFE_ENOMEM;
     m->ctx = c;
+    m->device = c->device;
     sfe_status st = guard(c, [&] {
         const size_t NP = SFE_MLP_NPARAMS;
         m->master.ensure(NP * 4);
@@ -1435,9 +1504,9 @@ sfe_status sfe_model_create(sfe_ctx *c, const float *params, sfe_model **out) {
 
 void sfe_model_destroy(sfe_model *m) {
     if (!m) return;
-    (void)hipSetDevice(m->ctx->device);
-    (void)hipStreamSynchronize(m->ctx->stream);
-    delete m;
+    (void)hipSetDevice(m->device);
+    delete m;                           // hipFree waits for work that still uses the buffers
+    (void)hipGetLastError();
 }
 
 sfe_status sfe_model_params(const sfe_model *m, float *params) {
@@ -1516,6 +1585,9 @@ sfe_status sfe_model_train(sfe_model *m, const float *x, const float *t, int64_t
         copy_in(c, xd, x, (size_t)n * SFE_MLP_NFEAT * 4);
         copy_in(c, td, t, (size_t)n * SFE_MLP_NOUT * 4);
         copy_in(c, ids, ord.data(), (size_t)n_order * 4);
+        const bool graph = c->tuning.use_graphs == 1;
+        hipGraph_t g = nullptr;
+        if (graph) HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         for (int64_t s = 0; s < steps; s++) {
             const int32_t B = (int32_t)std::min<int64_t>(batch, n_order - s * batch);
             const int nb = (B + 63) / 64;
@@ -1527,6 +1599,17 @@ sfe_status sfe_model_train(sfe_model *m, const float *x, const float *t, int64_t
                              m->p16.as<uint16_t>(), lr, c1, c2, ld + s, c->stream);
         }
         HIPCHK(hipGetLastError());
+        if (graph) {
+            // the whole step sequence as one graph, launched once
+            HIPCHK(hipStreamEndCapture(c->stream, &g));
+            hipGraphExec_t ge = nullptr;
+            hipError_t e1 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            hipError_t e2 = e1 == hipSuccess ? hipGraphLaunch(ge, c->stream) : e1;
+            hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(c->stream) : e2;
+            if (ge) (void)hipGraphExecDestroy(ge);
+            (void)hipGraphDestroy(g);
+            HIPCHK(e3);
+        }
         if (losses) copy_out(c, losses, ld, (size_t)steps * 4);
         sync(c);
     });

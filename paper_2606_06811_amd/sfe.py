@@ -59,7 +59,16 @@ class _AlignOpts(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("wave_group_cap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("wave_group_cap", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [("cells_per_lane", ctypes.c_int32), ("schedule", ctypes.c_int32), ("wave_group_cap", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("ms_extend", ctypes.c_double)]
+
+
+class _TuneReport(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("best", ctypes.c_int32), ("entries", _TuneEntry * 16)]
 
 
 class _Stats(ctypes.Structure):
@@ -95,6 +104,8 @@ def lib():
                                 P, I64, ctypes.POINTER(I64), P, I64, ctypes.POINTER(I64), ctypes.POINTER(_Stats)]
         L.sfe_ctx_set_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
         L.sfe_ctx_get_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
+        L.sfe_autotune.argtypes = [P, P, ctypes.POINTER(_Seq), I32, ctypes.POINTER(_Scoring), I64,
+                                   ctypes.POINTER(_AlignOpts), ctypes.POINTER(_TuneReport)]
         L.sfe_hsp_features.argtypes = [P, P, ctypes.POINTER(_Seq), I32, P, I64, P]
         L.sfe_extension_log.argtypes = [P, P, ctypes.POINTER(_Seq), I32, P, I64, ctypes.POINTER(_Scoring), P, P]
         L.sfe_model_create.argtypes = [P, P, ctypes.POINTER(P)]
@@ -108,7 +119,7 @@ def lib():
         L.sfe_last_error.argtypes = [P]
         L.sfe_last_error.restype = ctypes.c_char_p
         for f in ("sfe_ctx_create", "sfe_build_index", "sfe_seed_hits", "sfe_ungapped_xdrop", "sfe_gapped_ydrop",
-                  "sfe_align", "sfe_ctx_set_tuning", "sfe_ctx_get_tuning", "sfe_hsp_features", "sfe_extension_log", "sfe_model_create", "sfe_model_params",
+                  "sfe_align", "sfe_ctx_set_tuning", "sfe_ctx_get_tuning", "sfe_autotune", "sfe_hsp_features", "sfe_extension_log", "sfe_model_create", "sfe_model_params",
                   "sfe_model_predict", "sfe_model_grad", "sfe_model_train"):
             getattr(L, f).restype = I32
         _lib = L
@@ -160,12 +171,16 @@ def scoring_struct(d: dict) -> _Scoring:
 
 class Context:
     def __init__(self, device: int = 0, stream=None):
+        import weakref
         p = ctypes.c_void_p()
         _check(lib().sfe_ctx_create(int(device), stream, ctypes.byref(p)))
         self.ptr = p
+        self._children = weakref.WeakSet()      # models and indexes: closed before the context
 
     def close(self):
         if self.ptr:
+            for ch in list(self._children):
+                ch.close()
             lib().sfe_ctx_destroy(self.ptr)
             self.ptr = None
 
@@ -179,6 +194,7 @@ class Context:
 class Index:
     def __init__(self, ctx: Context, ptr, nt: int):
         self.ctx, self.ptr, self.nt = ctx, ptr, nt
+        ctx._children.add(self)
 
     def close(self):
         if self.ptr:
@@ -196,16 +212,34 @@ def sfe_ctx_create(device: int = 0, stream=None) -> Context:
     return Context(device, stream)
 
 
-def sfe_ctx_set_tuning(ctx: Context, wave_group_cap: int = 0):
+def sfe_ctx_set_tuning(ctx: Context, wave_group_cap: int = 0, use_graphs: int = 0):
     t = _Tuning()
     t.wave_group_cap = int(wave_group_cap)
+    t.use_graphs = int(use_graphs)
     _check(lib().sfe_ctx_set_tuning(ctx.ptr, ctypes.byref(t)), ctx)
 
 
 def sfe_ctx_get_tuning(ctx: Context) -> dict:
     t = _Tuning()
     _check(lib().sfe_ctx_get_tuning(ctx.ptr, ctypes.byref(t)), ctx)
-    return {"wave_group_cap": t.wave_group_cap}
+    return {"wave_group_cap": t.wave_group_cap, "use_graphs": t.use_graphs}
+
+
+def sfe_autotune(ctx: Context, idx: Index, queries, scoring: dict, sample_bases: int, model=None,
+                 round_k: int = 0, policy: int = SFE_POLICY_DEFER):
+    """Returns (chosen {max_cells_per_lane, schedule, wave_group_cap}, list of candidate timings)."""
+    seqs, keep = _seq_arrays(queries)
+    sc = scoring_struct(scoring)
+    opts = _AlignOpts(int(round_k), SFE_SCHED_PLAIN, 3, 0, int(policy), 0, 0,
+                      model.ptr if model is not None else None)
+    rep = _TuneReport()
+    _check(lib().sfe_autotune(ctx.ptr, idx.ptr, seqs, len(queries), ctypes.byref(sc), int(sample_bases),
+                              ctypes.byref(opts), ctypes.byref(rep)), ctx)
+    entries = [dict(cells_per_lane=e.cells_per_lane, schedule=e.schedule, wave_group_cap=e.wave_group_cap,
+                    ms_extend=e.ms_extend) for e in rep.entries[:rep.n]]
+    chosen = dict(max_cells_per_lane=opts.max_cells_per_lane, schedule=opts.schedule,
+                  wave_group_cap=sfe_ctx_get_tuning(ctx)["wave_group_cap"])
+    return chosen, entries
 
 
 def sfe_build_index(ctx: Context, target, pattern: str = "1110100110010101111", transitions: int = 1,
@@ -340,6 +374,7 @@ class Model:
         p = ctypes.c_void_p()
         _check(lib().sfe_model_create(ctx.ptr, _ptr(params), ctypes.byref(p)), ctx)
         self.ptr = p
+        ctx._children.add(self)
 
     def params(self) -> np.ndarray:
         out = np.zeros(MLP_NPARAMS, np.float32)

@@ -58,7 +58,7 @@ def test_binding_structs_match_the_c_header(tmp_path):
     import subprocess
     from paper_2606_06811_amd import sfe
     pairs = [("sfe_align_opts", sfe._AlignOpts), ("sfe_stats", sfe._Stats), ("sfe_scoring", sfe._Scoring),
-             ("sfe_tuning", sfe._Tuning),
+             ("sfe_tuning", sfe._Tuning), ("sfe_tune_entry", sfe._TuneEntry), ("sfe_tune_report", sfe._TuneReport),
              ("sfe_seq", sfe._Seq), ("sfe_seed_spec", sfe._SeedSpec)]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sfe.h"', "int main(void) {"]
     for cname, py in pairs:

@@ -213,3 +213,44 @@ def test_trained_model_beats_constant_predictor(ctx):
     base = float(np.mean((t[tr].mean(axis=0) - t[te]) ** 2))
     log(f"held-out MSE {mse:.4g} vs constant {base:.4g}")
     assert mse < 0.8 * base
+
+
+def test_train_in_one_graph_equals_eager(ctx):
+    """The whole training step sequence recorded in one hipGraph gives the
+    same parameters and losses, bit for bit, as eager launches."""
+    p0 = init_params(11)
+    rng = np.random.default_rng(12)
+    X = rng.uniform(0, 1, (500, 16)).astype(np.float32)
+    T = rng.uniform(0, 16, (500, 4)).astype(np.float32)
+    order = np.concatenate([rng.permutation(500) for _ in range(4)]).astype(np.int32)
+    m0 = sfe.Model(ctx, p0)
+    l0 = m0.train(X, T, order, batch=100, lr=1e-3)
+    sfe.sfe_ctx_set_tuning(ctx, use_graphs=1)
+    try:
+        m1 = sfe.Model(ctx, p0)
+        l1 = m1.train(X, T, order, batch=100, lr=1e-3)
+        m2 = sfe.Model(ctx, p0)
+        l2 = m2.train(X, T, order, batch=100, lr=1e-3)      # a second capture and launch
+    finally:
+        sfe.sfe_ctx_set_tuning(ctx, use_graphs=0)
+    assert np.array_equal(l0, l1) and np.array_equal(l0, l2)
+    assert np.array_equal(m0.params(), m1.params()) and np.array_equal(m0.params(), m2.params())
+
+
+def test_autotune_picks_a_schedule_and_keeps_results(ctx, case):
+    T, Q, idx, hsps = case
+    m = sfe.Model(ctx, init_params(13))
+    chosen, entries = sfe.sfe_autotune(ctx, idx, Q, dict(synth.SCORING), sample_bases=20_000, model=m)
+    log(f"autotune: chosen {chosen}; {len(entries)} candidates")
+    assert len(entries) == 12
+    assert chosen["max_cells_per_lane"] in (4, 6, 8) and chosen["schedule"] in (0, 1)
+    best = min(entries, key=lambda e: e["ms_extend"])
+    assert (best["cells_per_lane"], best["schedule"], best["wave_group_cap"]) == (
+        chosen["max_cells_per_lane"], chosen["schedule"], chosen["wave_group_cap"])
+    try:
+        a1, o1, _ = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), schedule=chosen["schedule"],
+                                  max_cells_per_lane=chosen["max_cells_per_lane"], model=m)
+    finally:
+        sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
+    a0, o0, _ = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING))
+    assert np.array_equal(a0, a1) and np.array_equal(o0, o1)
