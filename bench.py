@@ -8,10 +8,13 @@ Y-drop extension with traceback and serial commit.  Inputs are synthetic
 (seeded), resident in HBM before the timed region.
 
 Two schedules of the gapped stage are timed on the same step: the plain one
-(one wave per anchor-half, halves in batch order) and the learned one
-(persistent waves pulling halves from a queue ordered by the cost model's
-predicted size; the model is trained first, on the GPU, from extension logs
-of the plain pipeline on the 1 Mbp pair).  Their outputs must be identical.
+(one wave per anchor-half, halves in batch order) and the learned one: the
+cost model is trained first, on the GPU, from extension logs of the plain
+pipeline on the 1 Mbp pair; the autotuner then times candidate schedules
+(rows per lane, plain or persistent launch with the model's longest-first
+queue, wave groups for long halves) on a 1 Mbp sample of the query and the
+fastest is used.  Both run untimed before the timed steps.  Their outputs must
+be identical.
 
 Prints one JSON line.  `value` is unique HSPs per second of the whole step
 with the learned schedule; the plain schedule's figures, gapped GCUPS and the
@@ -106,6 +109,8 @@ def main():
     ap.add_argument("--schedule", default="both", choices=["plain", "persistent", "learned", "both"],
                     help="both: time the plain schedule and the learned persistent one (value = learned)")
     ap.add_argument("--cpl", type=int, default=0, help="rows per lane of the first band window (0: default)")
+    ap.add_argument("--tune-bp", type=int, default=1_000_000,
+                    help="query bases the autotuner samples for the learned schedule (0: no tuning)")
     ap.add_argument("--cpu-sample-bp", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -128,15 +133,33 @@ def main():
     ctx = sfe.sfe_ctx_create(0, stream.cuda_stream)
     torch.cuda.synchronize()
 
-    model, train_info = None, None
+    model, train_info, tune_info = None, None, None
+    tuned = dict(max_cells_per_lane=args.cpl, schedule=sfe.SFE_SCHED_PERSISTENT, wave_group_cap=0)
     if args.schedule in ("learned", "both"):
         model, train_info = train_cost_model(ctx, sfe, synth, log)
+        if args.tune_bp > 0:
+            # autotuner: candidate schedules timed on the first tune_bp query bases (untimed setup)
+            t0 = time.perf_counter()
+            idx = sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
+            tuned, entries = sfe.sfe_autotune(ctx, idx, Qd, sc, sample_bases=args.tune_bp, model=model,
+                                              round_k=args.round_k)
+            idx.close()
+            tune_info = dict(sample_bases=args.tune_bp, chosen=tuned, seconds=round(time.perf_counter() - t0, 2),
+                             candidates=entries)
+            log(f"autotune on {args.tune_bp} query bases: {tuned} in {tune_info['seconds']} s")
 
     def step(kind):
         idx = sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
-        sched = sfe.SFE_SCHED_PLAIN if kind == "plain" else sfe.SFE_SCHED_PERSISTENT
-        out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k, schedule=sched, cap=1 << 21, ops_cap=1 << 26,
-                            model=model if kind == "learned" else None, max_cells_per_lane=args.cpl)
+        if kind == "plain":
+            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
+            out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k, schedule=sfe.SFE_SCHED_PLAIN, cap=1 << 21,
+                                ops_cap=1 << 26, max_cells_per_lane=args.cpl)
+        else:
+            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=tuned["wave_group_cap"] if kind == "learned" else 0)
+            out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k,
+                                schedule=tuned["schedule"] if kind == "learned" else sfe.SFE_SCHED_PERSISTENT,
+                                cap=1 << 21, ops_cap=1 << 26, model=model if kind == "learned" else None,
+                                max_cells_per_lane=tuned["max_cells_per_lane"] if kind == "learned" else args.cpl)
         idx.close()
         return out
 
@@ -231,6 +254,7 @@ def main():
                              if len(kinds) == 2 else None),
         "bit_exact_learned_vs_plain": bit_exact,
         "cost_model_training": train_info,
+        "autotune": tune_info,
         "counts": {k: s[k] for k in ("seed_hits", "hsps_raw", "hsps", "rounds", "extensions", "committed",
                                      "shadow", "cells", "overflow_reruns", "xdrop_columns")},
         "stage_ms": {k: round(s[k], 2) for k in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total",
