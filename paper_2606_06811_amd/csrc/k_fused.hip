@@ -2,13 +2,13 @@
 // traceback, one 64-lane wave per half (Sec. 8 of the paper).
 //
 // The DP is the one described at the top of k_extend.hip.  The traceback
-// codes of a half (one record per antidiagonal: u32 first row, u32
-// (groups | G << 24), one u32 of 4-bit codes per lane-group of G rows) go to
-// a chain of fixed-size chunks taken from a pool shared by all waves.  When
-// the half stops, the same wave walks the codes back from the end cell
-// (staging index entries and records through LDS), returning each chunk to
-// the pool once the walk has left it; the run-length edit operations go to a
-// second chain and are finally copied, contiguous, to the run arena.  The
+// codes of a half (one record per antidiagonal: one u32 of 4-bit codes per
+// lane group of G rows, located through an index entry holding the record's
+// offset and first row) go to a chain of fixed-size chunks taken from a pool
+// shared by all waves.  When the half stops, the same wave walks the codes
+// back from the end cell a run at a time, returning each chunk to the pool
+// once the walk has left it; the run-length edit operations go to a second
+// chain and are finally copied, contiguous, to the run arena.  The
 // device thus holds codes only for the halves in flight, and a half never
 // has to be re-run because its traceback is long -- only when the whole pool
 // is exhausted.
@@ -22,7 +22,6 @@
 namespace sfe {
 
 #define TB_IDX 512            // index entries staged in LDS during traceback
-#define TB_REC 1024           // record words staged in LDS during traceback
 
 // Takes a free chunk (wave-uniform; -1 if none came free in time).  A wave
 // first reserves one of the `avail` free chunks -- when none is left it
@@ -97,20 +96,24 @@ __device__ __forceinline__ void free_chain(const ChunkPool &p, int c, int lane) 
     }
 }
 
-// Traceback of one half by one wave: walks the codes back from the end cell
-// (bi, bj) of the chain ending at chunk `cur` (its fill recorded in the
-// header), staging index entries and records through LDS, returns each chunk
-// to the pool once the walk has left it, and copies the edit runs (end cell
-// first) to the run arena.  maxg bounds the code words of one record.  Frees
-// every chunk it was given; returns the half's status.
-__device__ int trace_half(const ChunkPool &pool, int &hint, int lane, int cur, int bi, int bj, const RunArena &ra,
-                          uint32_t *tb_idx, uint32_t *tb_rec, int maxg, uint64_t &run_off, uint32_t &nruns) {
+// Traceback of one half by one wave, a run at a time: from the current cell,
+// lane l fetches the code of the l-th cell along the current direction
+// (diagonal in state H, left in E, up in F) and one ballot finds where the
+// run ends (an H cell not reached diagonally, a gap opened from H), so a run
+// of up to 64 operations costs one index lookup in LDS and one code load per
+// lane.  Index entries of the chunk being walked are staged in LDS 512
+// antidiagonals at a time; a chunk goes back to the pool once the walk has
+// left it.  The edit runs (end cell first) go to a chain of pool chunks, then
+// to an exact-size slice of the run arena.  G = rows per code word of the
+// records.  Frees every chunk it was given; returns the half's status.
+__device__ int trace_half(const ChunkPool &pool, int &hint, int lane, int cur, int bi, int bj, int G,
+                          const RunArena &ra, uint2 *tb_idx, uint64_t &run_off, uint32_t &nruns) {
     const uint32_t CH = 1u << pool.shift;
+    const uint32_t RC = (CH - 16) / 4;           // runs per chunk of the run chain
     int status = HALF_OK;
     uint8_t *cb = nullptr;
     int k0 = 0;
     uint32_t fill = 0;
-    const uint32_t RC = (CH - 16) / 4;       // runs per chunk of the run chain
     wave_sync();
     const int64_t kk0 = (int64_t)bi + bj;
     bool bad = false, oom = false;
@@ -137,16 +140,25 @@ __device__ int trace_half(const ChunkPool &pool, int &hint, int lane, int cur, i
         cnt++;
         return true;
     };
-    int64_t ic = -1;                 // antidiagonal of tb_idx[0] (-1: nothing staged)
-    int64_t rc = -1;                 // chunk offset of tb_rec[0]
-    int ti = bi, tj = bj, state = 0;
     uint32_t cur_op = 0xffffffffu, cur_len = 0;
-    int64_t guard = 2 * kk0 + 4;
-    while (!bad && !(ti == 0 && tj == 0 && state == 0)) {
-        if (--guard < 0 || ti < 0 || tj < 0) { bad = true; break; }
+    // appends len operations op, closing the previous run when op changes
+    auto push = [&](uint32_t op, uint32_t len) {
+        if (len == 0) return;
+        if (op == cur_op) { cur_len += len; return; }
+        if (cur_len) {
+            if (cnt >= (uint32_t)kk0) { bad = true; return; }    // runs <= operations <= bi + bj
+            if (!emit((cur_len << 2) | cur_op)) { oom = true; return; }
+        }
+        cur_op = op;
+        cur_len = len;
+    };
+    int64_t ic = -1;                  // antidiagonal of tb_idx[0] (-1: nothing staged)
+    int ti = bi, tj = bj, st = 0;     // st: 0 H, 1 E (op I), 2 F (op D)
+    int64_t guard = 2 * kk0 + 64;
+    while (!bad && !oom && !(ti == 0 && tj == 0 && st == 0)) {
+        if (--guard < 0 || (st == 1 && tj == 0) || (st == 2 && ti == 0)) { bad = true; break; }
         const int64_t kk = (int64_t)ti + tj;
-        if (kk < 1) { bad = true; break; }
-        while (kk < k0) {            // the walk left this chunk
+        while (kk < k0) {             // the walk left this chunk
             const int pc = (int)chunk_hdr(pool, cur, 0);
             pool_free(pool, cur, lane);
             cur = pc;
@@ -155,67 +167,77 @@ __device__ int trace_half(const ChunkPool &pool, int &hint, int lane, int cur, i
             k0 = (int)chunk_hdr(pool, cur, 1);
             fill = chunk_hdr(pool, cur, 2);
             ic = -1;
-            rc = -1;
         }
         if (cur < 0) { bad = true; break; }
-        if (ic < 0 || kk < ic) {
+        const int64_t lowest = kk - (st == 0 ? 126 : 63);     // deepest antidiagonal of this round
+        if (ic < 0 || (lowest < ic && ic > k0)) {
             ic = max((int64_t)k0, kk - TB_IDX + 1);
             wave_sync();
             for (int q = lane; q < TB_IDX; q += 64) {
                 const int64_t kq = ic + q;
-                tb_idx[q] = kq <= kk ? *(const uint32_t *)(cb + CH - 4u * (uint32_t)(kq - k0 + 1)) : 0u;
+                tb_idx[q] = kq <= kk ? *(const uint2 *)(cb + CH - 8u * (uint32_t)(kq - k0 + 1)) : make_uint2(0u, 0u);
             }
             wave_sync();
         }
-        const uint32_t rec = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_idx[kk - ic]);
-        if (rec < 16 || rec + 8 > fill) { bad = true; break; }
-        const int64_t wend = min(rc + 4 * TB_REC, (int64_t)fill);   // end of the staged bytes
-        if (rc < 0 || (int64_t)rec < rc || ((int64_t)rec + 8 + 4 * maxg > wend && wend < (int64_t)fill)) {
-            // stage the record bytes that end just past a full record at `rec`
-            const int64_t top = min((int64_t)rec + 8 + 4 * maxg, (int64_t)fill);
-            rc = max((int64_t)0, top - 4 * TB_REC);
-            wave_sync();
-            for (int q = lane; q < TB_REC; q += 64) {
-                const int64_t bo = rc + 4 * q;
-                tb_rec[q] = bo + 4 <= (int64_t)fill ? *(const uint32_t *)(cb + bo) : 0u;
+        // this lane's cell
+        const int ci = st == 1 ? ti : ti - lane;
+        const int cj = st == 2 ? tj : tj - lane;
+        const int64_t ka = (int64_t)ci + cj;
+        // (a gap state never reaches row or column 0: its run stops before)
+        bool inside = ci >= (st == 2 ? 1 : 0) && cj >= (st == 1 ? 1 : 0) && ka >= 1 && ka >= ic && ka <= kk;
+        // its code, when the cell lies in the computed range of its antidiagonal
+        // (lanes past the end of the run may fall outside: that only stops the run)
+        uint32_t code = 0;
+        bool valid = false;
+        if (inside) {
+            const uint2 ent = tb_idx[ka - ic];
+            if ((uint32_t)ci >= ent.y) {
+                const uint32_t idx = (uint32_t)ci - ent.y;
+                const uint64_t wofs = (uint64_t)ent.x + 4ull * (idx / (uint32_t)G);
+                if (wofs + 4 <= (uint64_t)fill) {
+                    valid = true;
+                    code = (*(const uint32_t *)(cb + wofs) >> (4u * (idx % (uint32_t)G))) & 15u;
+                }
             }
-            wave_sync();
         }
-        const uint32_t w0 = (uint32_t)(rec - rc) >> 2;
-        const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0]);
-        const uint32_t hw = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0 + 1]);
-        const uint32_t ng = hw & 0xffffffu, G = hw >> 24;
-        const uint32_t idx = (uint32_t)(ti - (int)r0);
-        if ((uint32_t)ti < r0 || G == 0 || G > 8 || idx / G >= ng || w0 + 2 + idx / G >= TB_REC) {
-            bad = true;
-            break;
-        }
-        const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb_rec[w0 + 2 + idx / G]);
-        const uint32_t code = (word >> (4 * (idx % G))) & 15u;
-        uint32_t op;
-        if (state == 0) {
-            const uint32_t src = code & 3u;
-            if (src == 1) { state = 1; continue; }
-            if (src == 2) { state = 2; continue; }
-            op = 0; ti--; tj--;
-        } else if (state == 1) {
-            op = 1;
-            if (code & 4u) state = 0;
-            tj--;
+        if (st == 0) {
+            // diagonal run: lanes 0 .. f-1 are M columns; lane f stops it
+            const uint64_t stop = __ballot(!valid || (code & 3u) != 0);
+            const int f = stop ? __builtin_ctzll(stop) : 64;
+            push(0u, (uint32_t)f);
+            ti -= f;
+            tj -= f;
+            if (f < 64 && !(ti == 0 && tj == 0)) {
+                const uint32_t cf = (uint32_t)__builtin_amdgcn_readlane((int)code, f);
+                const int fin = __builtin_amdgcn_readlane((int)inside, f);
+                const int fva = __builtin_amdgcn_readlane((int)valid, f);
+                if (fin && !fva) { bad = true; break; }      // the path needs a cell never computed
+                if (fva) {
+                    const uint32_t src = cf & 3u;
+                    if (src == 3u) { bad = true; break; }
+                    st = (int)src;
+                }
+            }
         } else {
-            op = 2;
-            if (code & 8u) state = 0;
-            ti--;
-        }
-        if (op == cur_op) {
-            cur_len++;
-        } else {
-            if (cur_len) {
-                if (cnt >= (uint32_t)kk0) { bad = true; break; }     // runs <= operations <= bi + bj
-                if (!emit((cur_len << 2) | cur_op)) { oom = true; break; }
+            // gap run: every cell emits one gap column; the first cell whose gap
+            // was opened from H ends it (and the walk returns to H)
+            const uint32_t obit = st == 1 ? 4u : 8u;
+            const uint64_t open = __ballot(valid && (code & obit) != 0);
+            const uint64_t out = __ballot(!valid);
+            const int fo = open ? __builtin_ctzll(open) : 64;
+            const int fx = out ? __builtin_ctzll(out) : 64;
+            const uint32_t op = st == 1 ? 1u : 2u;
+            int len;
+            if (fo < fx) {
+                len = fo + 1;
+                st = 0;
+            } else {
+                len = fx;
+                if (fx < 64 && __builtin_amdgcn_readlane((int)inside, fx)) { bad = true; break; }
             }
-            cur_op = op;
-            cur_len = 1;
+            push(op, (uint32_t)len);
+            if (op == 1u) tj -= len;
+            else ti -= len;
         }
     }
     if (!bad && !oom && cur_len) {
@@ -265,7 +287,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
     __shared__ int sub[40];
     __shared__ int prof[2][8];
     __shared__ uint8_t aring[RING], bring[RING];
-    __shared__ uint32_t tb_idx[TB_IDX], tb_rec[TB_REC];
+    __shared__ uint2 tb_idx[TB_IDX];
     const int lane = threadIdx.x;
     if (lane < 40) sub[lane] = (lane & 7) < 5 ? sc.sub[lane >> 3][lane & 7] : 0;
     if (lane < 5) {
@@ -479,8 +501,8 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                     l_hi = (hi - base) / C;
                 }
                 const uint32_t ng = (uint32_t)(l_hi - l_lo + 1);
-                const uint32_t need = 8 + 4 * ng;
-                if (fill + need + 4u * (uint32_t)(k - k0 + 1) > CH) {
+                const uint32_t need = 4 * ng;
+                if (fill + need + 8u * (uint32_t)(k - k0 + 1) > CH) {
                     const int nc = pool_alloc(pool, hint, lane);
                     if (nc < 0) { status = HALF_ARENA_OVERFLOW; break; }
                     if (lane == 0) {
@@ -495,11 +517,10 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                     fill = 16;
                 }
                 uint32_t *rec = (uint32_t *)(cb + fill);
-                if (lane >= l_lo && lane <= l_hi) rec[2 + lane - l_lo] = nib;
-                if (lane == 0) {
-                    *(uint2 *)rec = make_uint2(nonempty ? (uint32_t)(base + l_lo * C) : 0u, rec_head_word(ng, C));
-                    *(uint32_t *)(cb + CH - 4u * (uint32_t)(k - k0 + 1)) = fill;
-                }
+                if (lane >= l_lo && lane <= l_hi) rec[lane - l_lo] = nib;
+                if (lane == 0)
+                    *(uint2 *)(cb + CH - 8u * (uint32_t)(k - k0 + 1)) =
+                        make_uint2(fill, nonempty ? (uint32_t)(base + l_lo * C) : 0u);
                 fill += need;
                 if (nonempty) cells += (uint64_t)(hi - lo + 1);
             }
@@ -541,7 +562,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
         uint64_t run_off = 0;
         uint32_t nruns = 0;
         if (status == HALF_OK && (bi != 0 || bj != 0))
-            status = trace_half(pool, hint, lane, cur, bi, bj, ra, tb_idx, tb_rec, 64, run_off, nruns);
+            status = trace_half(pool, hint, lane, cur, bi, bj, C, ra, tb_idx, run_off, nruns);
         else
             free_chain(pool, cur, lane);
         if (lane == 0) {
@@ -596,7 +617,7 @@ __global__ void __launch_bounds__(64 * W) k_ydrop_coop(const HalfTask *__restric
     __shared__ int sub[40];
     __shared__ int prof[2][8];
     __shared__ uint8_t aring[ARING], bring[RING];
-    __shared__ uint32_t tb_idx[TB_IDX], tb_rec[TB_REC];
+    __shared__ uint2 tb_idx[TB_IDX];
     __shared__ CoopXch<C, W> xch[2][W];
     __shared__ int dump[NT * NV];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -677,7 +698,7 @@ __global__ void __launch_bounds__(64 * W) k_ydrop_coop(const HalfTask *__restric
     uint8_t *cb = cur >= 0 ? chunk_ptr(pool, cur) : nullptr;
     int k0 = 1;
     uint32_t fill = 16;
-    constexpr uint32_t MAXNEED = 8 + 4 * NT;
+    constexpr uint32_t MAXNEED = 4 * NT;
     int k = 1;
     for (; status == HALF_OK && k <= kmax32; k++) {
         if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
@@ -863,14 +884,13 @@ __global__ void __launch_bounds__(64 * W) k_ydrop_coop(const HalfTask *__restric
             g_hi = (hi - base) / C;
         }
         const uint32_t ng = (uint32_t)(g_hi - g_lo + 1);
-        const uint32_t need = 8 + 4 * ng;
+        const uint32_t need = 4 * ng;
         {
             uint32_t *rec = (uint32_t *)(cb + fill);
-            if (tid >= g_lo && tid <= g_hi) rec[2 + tid - g_lo] = nib;
-            if (tid == 0) {
-                *(uint2 *)rec = make_uint2(nonempty ? (uint32_t)(base + g_lo * C) : 0u, rec_head_word(ng, C));
-                *(uint32_t *)(cb + CH - 4u * (uint32_t)(k - k0 + 1)) = fill;
-            }
+            if (tid >= g_lo && tid <= g_hi) rec[tid - g_lo] = nib;
+            if (tid == 0)
+                *(uint2 *)(cb + CH - 8u * (uint32_t)(k - k0 + 1)) =
+                    make_uint2(fill, nonempty ? (uint32_t)(base + g_lo * C) : 0u);
         }
         fill += need;
         if (nonempty) cells += (uint64_t)(hi - lo + 1);
@@ -916,7 +936,7 @@ __global__ void __launch_bounds__(64 * W) k_ydrop_coop(const HalfTask *__restric
         // room for the next antidiagonal's record: wave 0 takes a new chunk now
         if (w == 0) {
             int nc = -1;
-            if (fill + MAXNEED + 4u * (uint32_t)(k + 1 - k0 + 1) > CH) {
+            if (fill + MAXNEED + 8u * (uint32_t)(k + 1 - k0 + 1) > CH) {
                 nc = pool_alloc(pool, hint, lane);
                 if (nc >= 0 && lane == 0) {
                     ((uint32_t *)cb)[2] = fill;
@@ -966,7 +986,7 @@ __global__ void __launch_bounds__(64 * W) k_ydrop_coop(const HalfTask *__restric
         uint64_t run_off = 0;
         uint32_t nruns = 0;
         if (status == HALF_OK && (bi != 0 || bj != 0))
-            status = trace_half(pool, hint, lane, cur, bi, bj, ra, tb_idx, tb_rec, NT, run_off, nruns);
+            status = trace_half(pool, hint, lane, cur, bi, bj, C, ra, tb_idx, run_off, nruns);
         else
             free_chain(pool, cur, lane);
         if (lane == 0) {
