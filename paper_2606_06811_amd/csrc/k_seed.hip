@@ -150,40 +150,101 @@ __global__ void __launch_bounds__(64) k_seed_emit(const UnitDesc *__restrict__ u
 // ---------------------------------------------------------------------------
 struct XResult { int64_t t0, q0, len; int32_t score; int32_t work; bool range; };
 
+// Codes of 16 consecutive bases starting at absolute position p of a set:
+// bits 2u..2u+1 of c2 = base p + u (N stored as 0), bit u of n = base p + u
+// is N.  Reads at most 46 bases past p + 15 (inside every sequence's padding).
+struct Codes16 {
+    uint32_t c2, n;
+};
+__device__ __forceinline__ Codes16 codes16(const SeqSetView &S, int64_t p) {
+    const int64_t w = p >> 4;
+    const int sh = (int)(p & 15) * 2;
+    uint32_t c2 = S.bases[w];
+    if (sh) c2 = (uint32_t)((((uint64_t)S.bases[w + 1] << 32) | c2) >> sh);
+    const int64_t nw = p >> 5;
+    const int nsh = (int)(p & 31);
+    uint32_t n = S.nbits[nw] >> nsh;
+    if (nsh > 16) n |= S.nbits[nw + 1] << (32 - nsh);
+    return Codes16{c2, n};
+}
+__device__ __forceinline__ int code_at(const Codes16 &c, int u) {
+    return ((c.n >> u) & 1u) ? 4 : (int)((c.c2 >> (2 * u)) & 3u);
+}
+
 // t, q relative to their sequences (which start at tb / qb in their sets and
-// have lengths nt / nq).  sub: 5x8 table in LDS.
+// have lengths nt / nq).  sub: 5x8 table in LDS.  Columns are read 16 at a
+// time (two words per side), their scores looked up together, then scanned
+// in order; the scan stops exactly where the column-by-column rule does.
 __device__ __forceinline__ XResult xdrop_one(const SeqSetView &T, int64_t tb, int64_t nt, const SeqSetView &Q,
                                              int64_t qb, int64_t nq, int64_t t, int64_t q, int span,
                                              const int *sub, int32_t X) {
     int32_t s0 = 0;
-    for (int u = 0; u < span; u++) s0 += sub[base_code(T, tb + t + u) * 8 + base_code(Q, qb + q + u)];
-    int32_t s = 0, bR = 0;
-    int64_t R = 0, r = 1;
-    int64_t lim = nt - t - span;
-    if (nq - q - span < lim) lim = nq - q - span;
-    bool range = false;
-    for (; r <= lim; r++) {
-        s += sub[base_code(T, tb + t + span - 1 + r) * 8 + base_code(Q, qb + q + span - 1 + r)];
-        if (s > bR) {
-            bR = s; R = r;
-            if (bR >= SFE_SCORE_LIMIT) { range = true; r++; break; }
-        }
-        else if (bR - s > X) { r++; break; }
+    {
+        const Codes16 a0 = codes16(T, tb + t), b0 = codes16(Q, qb + q);
+        const Codes16 a1 = codes16(T, tb + t + 16), b1 = codes16(Q, qb + q + 16);
+        for (int u = 0; u < span; u++)
+            s0 += u < 16 ? sub[code_at(a0, u) * 8 + code_at(b0, u)] : sub[code_at(a1, u - 16) * 8 + code_at(b1, u - 16)];
     }
-    int32_t work = span + (int32_t)(r - 1);
+    bool range = false;
+    // right of the seed: columns r = 1 .. lim at t + span - 1 + r
+    int32_t s = 0, bR = 0;
+    int64_t R = 0;
+    int32_t work = span;
+    {
+        int64_t lim = nt - t - span;
+        if (nq - q - span < lim) lim = nq - q - span;
+        bool stop = false;
+        for (int64_t r0 = 1; r0 <= lim && !stop; r0 += 16) {
+            const int m = (int)min((int64_t)16, lim - r0 + 1);
+            const Codes16 a = codes16(T, tb + t + span - 1 + r0), b = codes16(Q, qb + q + span - 1 + r0);
+            int sv[16];
+#pragma unroll
+            for (int i = 0; i < 16; i++) sv[i] = sub[code_at(a, i) * 8 + code_at(b, i)];
+            for (int i = 0; i < m; i++) {
+                s += sv[i];
+                work++;
+                if (s > bR) {
+                    bR = s;
+                    R = r0 + i;
+                    if (bR >= SFE_SCORE_LIMIT) { range = true; stop = true; break; }
+                } else if (bR - s > X) {
+                    stop = true;
+                    break;
+                }
+            }
+        }
+    }
+    // left of the seed: columns r = 1 .. lim at t - r
     int32_t bL = 0;
     int64_t L = 0;
-    s = 0;
-    lim = t < q ? t : q;
-    for (r = 1; r <= lim && !range; r++) {
-        s += sub[base_code(T, tb + t - r) * 8 + base_code(Q, qb + q - r)];
-        if (s > bL) {
-            bL = s; L = r;
-            if (bL >= SFE_SCORE_LIMIT) { range = true; r++; break; }
+    if (!range) {
+        const int64_t lim = t < q ? t : q;
+        s = 0;
+        bool stop = false;
+        for (int64_t r0 = 1; r0 <= lim && !stop; r0 += 16) {
+            const int m = (int)min((int64_t)16, lim - r0 + 1);
+            // bases t - r0 - m + 1 .. t - r0: column r0 + i is bit m - 1 - i
+            const Codes16 a = codes16(T, tb + t - r0 - m + 1), b = codes16(Q, qb + q - r0 - m + 1);
+            int sv[16];
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                const int u = (m - 1 - i) & 15;
+                sv[i] = sub[code_at(a, u) * 8 + code_at(b, u)];
+            }
+            for (int i = 0; i < m; i++) {
+                s += sv[i];
+                work++;
+                if (s > bL) {
+                    bL = s;
+                    L = r0 + i;
+                    if (bL >= SFE_SCORE_LIMIT) { range = true; stop = true; break; }
+                } else if (bL - s > X) {
+                    stop = true;
+                    break;
+                }
+            }
         }
-        else if (bL - s > X) { r++; break; }
     }
-    work += (int32_t)(r - 1);
     XResult res;
     res.t0 = t - L;
     res.q0 = q - L;
