@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--schedule", default="both", choices=["plain", "persistent", "learned", "both"],
                     help="both: time the plain schedule and the learned persistent one (value = learned)")
     ap.add_argument("--cpl", type=int, default=0, help="rows per lane of the first band window (0: default)")
+    ap.add_argument("--near-band", type=int, default=0, help="deferral nearness band (0: default, <0: off)")
     ap.add_argument("--tune-bp", type=int, default=1_000_000,
                     help="query bases the autotuner samples for the learned schedule (0: no tuning)")
     ap.add_argument("--cpu-sample-bp", type=int, default=30_000)
@@ -153,7 +154,7 @@ def main():
         if kind == "plain":
             sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
             out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k, schedule=sfe.SFE_SCHED_PLAIN, cap=1 << 21,
-                                ops_cap=1 << 26, max_cells_per_lane=args.cpl)
+                                ops_cap=1 << 26, max_cells_per_lane=args.cpl, near_band=args.near_band)
         else:
             sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=tuned["wave_group_cap"] if kind == "learned" else 0)
             out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k,

@@ -124,7 +124,7 @@ typedef struct {
  *   anchors are not contained in a committed alignment (Alg. 3 as printed).
  * DEFER:  the scan also passes over (defers) an HSP whose anchor lies on an M
  *   column of an earlier extension still waiting for commit, or whose diagonal
- *   is within 128 of an earlier HSP already in the batch; deferred HSPs are
+ *   is within near_band (64 by default) of an earlier HSP already in the batch; deferred HSPs are
  *   decided in later batches.  Commit still walks the HSPs in order and stops
  *   at the first one without an extension. */
 #define SFE_POLICY_DEFER 0
@@ -138,7 +138,8 @@ typedef struct {
                                in the first band window; wider bands move on to 8, then to the
                                workgroup kernel */
     int32_t policy;         /* SFE_POLICY_* */
-    int32_t pad;
+    int32_t near_band;      /* SFE_POLICY_DEFER's nearness rule: diagonals within which a later HSP
+                               of the batch waits for an earlier one; 0 = 64, < 0 = rule off */
     int64_t arena_bytes;    /* device memory for traceback codes of the halves in flight,
                                allocated once per context; 0 = 32 GiB.  A batch whose halves
                                need more at once runs with fewer in flight; a single half

@@ -1171,7 +1171,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         BatchResult br;
         const bool defer = o.policy == SFE_POLICY_DEFER;
         const bool progress = getenv("SFE_PROGRESS") != nullptr;
-        const int64_t DB = 128;                                   // diagonal band of the nearness rule
+        const int64_t DB = o.near_band == 0 ? 64 : o.near_band;      // diagonal band of the nearness rule
         auto anchor_of = [&](const sfe_hsp &h, uint32_t &ta, uint32_t &qa) {
             uint32_t off = (h.len - 1) / 2;
             ta = h.t0 + off;
@@ -1201,18 +1201,20 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                         if (paths[u].contains_before(ta, qa, p, stt)) { still.push_back(p); continue; }
                         // inside a committed alignment but off its path: such HSPs are extended
                         // side by side (each may start a separate alignment of the region)
-                        const bool known_region = boxes[u].inside(ta, qa);
-                        const int64_t d = (int64_t)ta - (int64_t)qa;
-                        const int64_t b = d >= 0 ? d / DB : -((-d + DB - 1) / DB);
-                        bool close = false;
-                        for (int64_t bb = b - 1; bb <= b + 1 && !close; bb++) {
-                            auto it = near.find(bb);
-                            if (it == near.end()) continue;
-                            for (int64_t dd : it->second)
-                                if (std::llabs(dd - d) <= DB) { close = true; break; }
+                        if (DB > 0) {
+                            const bool known_region = boxes[u].inside(ta, qa);
+                            const int64_t d = (int64_t)ta - (int64_t)qa;
+                            const int64_t b = d >= 0 ? d / DB : -((-d + DB - 1) / DB);
+                            bool close = false;
+                            for (int64_t bb = b - 1; bb <= b + 1 && !close; bb++) {
+                                auto it = near.find(bb);
+                                if (it == near.end()) continue;
+                                for (int64_t dd : it->second)
+                                    if (std::llabs(dd - d) <= DB) { close = true; break; }
+                            }
+                            if (close && !known_region) { still.push_back(p); continue; }   // likely the same region
+                            near[b].push_back(d);
                         }
-                        if (close && !known_region) { still.push_back(p); continue; }   // likely the same region
-                        near[b].push_back(d);
                     }
                     items.push_back(ExtItem{ta, qa, (int32_t)u, 0});
                     item_ref.push_back({(int32_t)u, p});

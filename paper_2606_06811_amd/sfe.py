@@ -54,7 +54,7 @@ class _Scoring(ctypes.Structure):
 
 class _AlignOpts(ctypes.Structure):
     _fields_ = [("round_k", ctypes.c_int32), ("schedule", ctypes.c_int32), ("strands", ctypes.c_int32),
-                ("max_cells_per_lane", ctypes.c_int32), ("policy", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("max_cells_per_lane", ctypes.c_int32), ("policy", ctypes.c_int32), ("near_band", ctypes.c_int32),
                 ("arena_bytes", ctypes.c_int64), ("model", ctypes.c_void_p)]
 
 
@@ -312,12 +312,12 @@ def sfe_gapped_ydrop(ctx: Context, idx: Index, queries, hsps: np.ndarray, scorin
 
 def sfe_align(ctx: Context, idx: Index, queries, scoring: dict, round_k: int = 0, schedule: int = SFE_SCHED_PLAIN,
               strands: int = 3, max_cells_per_lane: int = 0, arena_bytes: int = 0, policy: int = SFE_POLICY_DEFER,
-              cap: int = 1 << 12, ops_cap: int = 1 << 18, model=None):
+              cap: int = 1 << 12, ops_cap: int = 1 << 18, model=None, near_band: int = 0):
     """Whole pipeline; returns (alignments, ops, stats dict)."""
     seqs, keep = _seq_arrays(queries)
     sc = scoring_struct(scoring)
-    opts = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(policy), 0,
-                      int(arena_bytes), model.ptr if model is not None else None)
+    opts = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(policy),
+                      int(near_band), int(arena_bytes), model.ptr if model is not None else None)
     na, no = ctypes.c_int64(), ctypes.c_int64()
     stats = _Stats()
     while True:
