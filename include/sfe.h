@@ -123,10 +123,14 @@ typedef struct {
  * PREFIX: each batch is the next round_k HSPs of a (query, strand) whose
  *   anchors are not contained in a committed alignment (Alg. 3 as printed).
  * DEFER:  the scan also passes over (defers) an HSP whose anchor lies on an M
- *   column of an earlier extension still waiting for commit, or whose diagonal
- *   is within near_band (64 by default) of an earlier HSP already in the batch; deferred HSPs are
- *   decided in later batches.  Commit still walks the HSPs in order and stops
- *   at the first one without an extension. */
+ *   column of an earlier extension still waiting for commit, or whose
+ *   diagonal is within near_band (64 by default) of an earlier HSP already in
+ *   the batch; deferred HSPs are decided in later batches.  A waiting
+ *   extension holds nothing back when it is expected to be skipped at commit:
+ *   its anchor already lies in a committed alignment, or on an M column of an
+ *   earlier waiting extension that is not itself expected to be skipped.
+ *   Commit still walks the HSPs in order and stops at the first one without
+ *   an extension. */
 #define SFE_POLICY_DEFER 0
 #define SFE_POLICY_PREFIX 1
 

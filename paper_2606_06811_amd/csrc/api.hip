@@ -819,10 +819,11 @@ struct PathSet {
 struct PathIndex {
     PathSet set;
     void add(const sfe_aln &a, const uint32_t *ops, size_t owner) { set.add(a, ops, owner); }
-    // (t, q) lies on an M column of an extension, still waiting for commit,
-    // whose HSP comes before `pos` (state[owner] == 2)
-    bool contains_before(uint32_t t, uint32_t q, size_t pos, const std::vector<uint8_t> &state) const {
-        return set.contains(t, q, [&](size_t o) { return o < pos && state[o] == 2; });
+    // (t, q) lies on an M column of an extension, still waiting for commit
+    // (state[owner] == 2) and not marked in `doomed`, whose HSP comes before `pos`
+    bool contains_before(uint32_t t, uint32_t q, size_t pos, const std::vector<uint8_t> &state,
+                         const std::vector<uint8_t> &doomed) const {
+        return set.contains(t, q, [&](size_t o) { return o < pos && state[o] == 2 && !doomed[o]; });
     }
 };
 
@@ -1172,12 +1173,15 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         const bool defer = o.policy == SFE_POLICY_DEFER;
         const bool progress = getenv("SFE_PROGRESS") != nullptr;
         const int64_t DB = o.near_band == 0 ? 64 : o.near_band;      // diagonal band of the nearness rule
+        std::vector<std::vector<uint8_t>> doomed(NU);              // pending extensions expected to be skipped
         auto anchor_of = [&](const sfe_hsp &h, uint32_t &ta, uint32_t &qa) {
             uint32_t off = (h.len - 1) / 2;
             ta = h.t0 + off;
             qa = h.q0 + off;
         };
         double host_ms = 0, book_ms = 0, commit_ms = 0;
+        std::vector<std::vector<uint16_t>> why(progress ? NU : 0);   // deferrals by path (lo byte) and nearness (hi)
+        for (size_t u = 0; u < why.size(); u++) why[u].assign(per_unit[u].size(), 0);
         for (;;) {
             const double th = now_ms();
             items.clear();
@@ -1185,6 +1189,23 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             for (size_t u = 0; u < NU; u++) {                      // phase 1: serial scan per unit
                 auto &lst = per_unit[u];
                 auto &stt = state[u];
+                if (defer) {
+                    // a pending extension whose anchor already lies in a committed alignment, or on
+                    // the path of an earlier pending one that is not itself doomed, will most likely
+                    // be skipped at commit: its path does not hold back later HSPs
+                    auto &dm = doomed[u];
+                    dm.assign(lst.size(), 0);
+                    std::vector<size_t> pend;
+                    pend.reserve(pending[u].size());
+                    for (const auto &kv : pending[u]) pend.push_back(kv.first);
+                    std::sort(pend.begin(), pend.end());
+                    for (size_t p : pend) {
+                        const sfe_aln &a = pending[u][p].first;
+                        if (seg[u].contains(a.anchor_t, a.anchor_q) ||
+                            paths[u].contains_before(a.anchor_t, a.anchor_q, p, stt, dm))
+                            dm[p] = 1;
+                    }
+                }
                 int64_t taken = 0;
                 std::unordered_map<int64_t, std::vector<int64_t>> near;   // diagonal bucket -> selected diagonals
                 std::vector<size_t> still;
@@ -1198,7 +1219,11 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     if (seg[u].contains(ta, qa)) { stt[p] = 1; continue; }
                     if (defer) {
                         // on the path of an earlier extension that may still commit: wait for it
-                        if (paths[u].contains_before(ta, qa, p, stt)) { still.push_back(p); continue; }
+                        if (paths[u].contains_before(ta, qa, p, stt, doomed[u])) {
+                            if (progress) why[u][p] += 1;
+                            still.push_back(p);
+                            continue;
+                        }
                         // inside a committed alignment but off its path: such HSPs are extended
                         // side by side (each may start a separate alignment of the region)
                         if (DB > 0) {
@@ -1212,7 +1237,11 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                                 for (int64_t dd : it->second)
                                     if (std::llabs(dd - d) <= DB) { close = true; break; }
                             }
-                            if (close && !known_region) { still.push_back(p); continue; }   // likely the same region
+                            if (close && !known_region) {                                  // likely the same region
+                                if (progress) why[u][p] += 256;
+                                still.push_back(p);
+                                continue;
+                            }
                             near[b].push_back(d);
                         }
                     }
@@ -1244,9 +1273,27 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                       learned ? &extent : nullptr);                                   // phase 2
             st.predicted_halves += br.predicted;
             st.mispredicted_halves += br.mispredicted;
-            if (progress)
+            if (progress) {
                 fprintf(stderr, "[sfe] batch %lld: %zu extensions, %.1f ms, %zu committed so far\n",
                         (long long)st.rounds, items.size(), now_ms() - tr, committed.size());
+                size_t xl = 0;
+                int64_t kl = -1, nlong = 0;
+                for (size_t x = 0; x < items.size(); x++)
+                    for (int s2 = 0; s2 < 2; s2++) {
+                        const int64_t kk = br.halves[2 * x + s2].k_last;
+                        if (kk > 100000) nlong++;
+                        if (kk > kl) { kl = kk; xl = x; }
+                    }
+                if (kl >= 0) {
+                    const int32_t u = item_ref[xl].first;
+                    const size_t p = item_ref[xl].second;
+                    const sfe_hsp &h = hs[per_unit[u][p]];
+                    fprintf(stderr, "[sfe]   longest half %lld antidiagonals (item unit %d pos %zu of %zu, score %d, "
+                                    "diag %lld, deferred %d by path, %d by nearness); %lld halves > 100k\n",
+                            (long long)kl, u, p, per_unit[u].size(), (int)h.score, (long long)h.t0 - (long long)h.q0,
+                            why[u][p] & 255, why[u][p] >> 8, (long long)nlong);
+                }
+            }
             const double th2 = now_ms();
             st.overflow_reruns += br.reruns;
             st.extensions += (int64_t)items.size();
