@@ -243,7 +243,11 @@ typedef struct {
     int32_t wave_group_cap;
     int32_t use_graphs;     /* 1: sfe_model_train records its whole step sequence in one hipGraph
                                and launches it once (same kernels, same order, same results) */
-    int32_t reserved[6];
+    int32_t wide_scores;    /* 1: gapped extension always in 32-bit arithmetic; 0 (default): in
+                               packed 16-bit arithmetic, values relative to the Y-drop threshold,
+                               when every score fits in int8 and ydrop + gap_open + gap_extend +
+                               2 * max |score| + 512 <= 32767 (same results either way) */
+    int32_t reserved[5];
 } sfe_tuning;
 sfe_status sfe_ctx_set_tuning(sfe_ctx *ctx, const sfe_tuning *t);
 sfe_status sfe_ctx_get_tuning(const sfe_ctx *ctx, sfe_tuning *t);

@@ -396,13 +396,13 @@ void set_run_head(sfe_ctx *c, uint64_t h) {
 }
 
 // Blocks of the fused kernel the device holds at once.
-int64_t fused_resident(sfe_ctx *c, int cells_per_lane, bool perm, bool persistent) {
+int64_t fused_resident(sfe_ctx *c, int cells_per_lane, bool perm, bool narrow, bool persistent) {
     if (c->cu_count <= 0) {
         int n = 0;
         HIPCHK(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, c->device));
         c->cu_count = n;
     }
-    const int per_cu = ydrop_fused_blocks_per_cu(cells_per_lane, perm, persistent);
+    const int per_cu = ydrop_fused_blocks_per_cu(cells_per_lane, perm, narrow, persistent);
     if (per_cu <= 0) fail(SFE_EDEVICE, "occupancy query of the extension kernel failed");
     return (int64_t)per_cu * c->cu_count;
 }
@@ -453,8 +453,15 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     launch_make_tasks(items_d, n, c->units_d.as<UnitDesc>(), idx->nt, tasks, c->stream);
     SeqSetView T = idx->target.view(), Qp = c->qplus.view(), Qm = c->qminus.view();
     bool perm = true;                   // every score fits in int8: scores come from packed row profiles
+    int smax = 0;
     for (int a = 0; a < 5; a++)
-        for (int b = 0; b < 5; b++) perm = perm && sc.sub[a][b] >= -128 && sc.sub[a][b] <= 127;
+        for (int b = 0; b < 5; b++) {
+            perm = perm && sc.sub[a][b] >= -128 && sc.sub[a][b] <= 127;
+            smax = std::max(smax, std::abs(sc.sub[a][b]));
+        }
+    // packed 16-bit DP: live values relative to the Y-drop threshold stay below 2^15
+    const bool narrow = perm && c->tuning.wide_scores == 0 &&
+                        (int64_t)sc.ydrop + sc.gap_open + sc.gap_extend + 2 * (int64_t)smax + 512 <= 32767;
     const int64_t nh = 2 * n;
     std::vector<HalfResult> hr(nh);
     std::vector<uint64_t> roff(nh, 0);
@@ -513,7 +520,7 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
             bool persistent = schedule == SFE_SCHED_PERSISTENT || lv > 0;
             // level L > 0 (the pool ran dry at level L - 1): 4^L times fewer
             // waves than the device holds, pulling from the queue
-            int64_t count = fused_resident(c, C, perm, persistent);
+            int64_t count = fused_resident(c, C, perm, narrow, persistent);
             if (lv > 0) count = std::max<int64_t>(1, count >> std::min(62, 2 * lv));
             ChunkPool pool = make_pool(c);
             nwaves = persistent ? count : 0;
@@ -522,8 +529,8 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
             HIPCHK(hipMemsetAsync(qhead, 0, 4, c->stream));
             WorkQueue wq{ids, cnt, qhead};
             HIPCHK(hipEventRecord(c->ev0, c->stream));
-            launch_ydrop_fused(C, perm, persistent, tasks, wq, persistent ? count : cnt, T, Qp, Qm, sc, pool, ra,
-                               hres, long_cap, c->stream);
+            launch_ydrop_fused(C, perm, narrow, persistent, tasks, wq, persistent ? count : cnt, T, Qp, Qm, sc, pool,
+                               ra, hres, long_cap, c->stream);
         } else if (sg <= ST_COOP4) {
             // wave groups; level L > 0: at most 256 / 4^(L-1) halves in flight
             const int C = sg == ST_COOP2 ? 2 : 4;
@@ -1174,6 +1181,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         const bool progress = getenv("SFE_PROGRESS") != nullptr;
         const int64_t DB = o.near_band == 0 ? 64 : o.near_band;      // diagonal band of the nearness rule
         std::vector<std::vector<uint8_t>> doomed(NU);              // pending extensions expected to be skipped
+        std::vector<std::vector<size_t>> pend_list(NU);            // positions with an extension waiting for commit
         auto anchor_of = [&](const sfe_hsp &h, uint32_t &ta, uint32_t &qa) {
             uint32_t off = (h.len - 1) / 2;
             ta = h.t0 + off;
@@ -1193,17 +1201,19 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     // a pending extension whose anchor already lies in a committed alignment, or on
                     // the path of an earlier pending one that is not itself doomed, will most likely
                     // be skipped at commit: its path does not hold back later HSPs
+                    // (2: anchor in a committed alignment, which stays so; 1: on a waiting path)
                     auto &dm = doomed[u];
-                    dm.assign(lst.size(), 0);
-                    std::vector<size_t> pend;
-                    pend.reserve(pending[u].size());
-                    for (const auto &kv : pending[u]) pend.push_back(kv.first);
+                    if (dm.size() != lst.size()) dm.assign(lst.size(), 0);
+                    auto &pend = pend_list[u];
+                    pend.erase(std::remove_if(pend.begin(), pend.end(), [&](size_t p) { return stt[p] != 2; }),
+                               pend.end());
                     std::sort(pend.begin(), pend.end());
                     for (size_t p : pend) {
+                        if (dm[p] == 2) continue;
                         const sfe_aln &a = pending[u][p].first;
-                        if (seg[u].contains(a.anchor_t, a.anchor_q) ||
-                            paths[u].contains_before(a.anchor_t, a.anchor_q, p, stt, dm))
-                            dm[p] = 1;
+                        dm[p] = seg[u].contains(a.anchor_t, a.anchor_q)                              ? 2
+                                : paths[u].contains_before(a.anchor_t, a.anchor_q, p, stt, dm) ? 1
+                                                                                               : 0;
                     }
                 }
                 int64_t taken = 0;
@@ -1308,6 +1318,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                                  br.ops.begin() + (a.flags & SFE_ALN_PASSED ? a.ops_offset + a.ops_len : 0));
                 pe.first.ops_offset = 0;
                 if (defer && (a.flags & SFE_ALN_PASSED)) paths[u].add(pe.first, pe.second.data(), p);
+                if (defer) pend_list[u].push_back(p);
                 state[u][p] = 2;
             }
             const double th3 = now_ms();
@@ -1396,7 +1407,9 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
 }
 
 sfe_status sfe_ctx_set_tuning(sfe_ctx *c, const sfe_tuning *t) {
-    if (!c || !t || t->wave_group_cap < 0 || t->use_graphs < 0 || t->use_graphs > 1) return SFE_EINVAL;
+    if (!c || !t || t->wave_group_cap < 0 || t->use_graphs < 0 || t->use_graphs > 1 || t->wide_scores < 0 ||
+        t->wide_scores > 1)
+        return SFE_EINVAL;
     c->tuning = *t;
     return SFE_OK;
 }

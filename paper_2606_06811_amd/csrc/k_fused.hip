@@ -96,6 +96,16 @@ __device__ __forceinline__ void free_chain(const ChunkPool &p, int c, int lane) 
     }
 }
 
+// Code of row r of a 16-bit record word (rows in pairs (p, p + P), pair p's
+// nibbles at bits 12 - 4p (row p) and 28 - 4p (row p + P); nibble bits, high
+// to low: from a gap, from F rather than E, E extended, F extended), in the
+// layout of the 32-bit kernel (bits 0-1: 0 diagonal, 1 E, 2 F; bit 2: E
+// opened from H; bit 3: F opened from H).
+__device__ __forceinline__ uint32_t narrow_code(uint32_t w, uint32_t r, uint32_t P) {
+    const uint32_t n = (w >> (r < P ? 12u - 4u * r : 28u - 4u * (r - P))) & 15u;
+    return ((n & 8u) ? ((n & 4u) ? 2u : 1u) : 0u) | ((n & 2u) ? 0u : 4u) | ((n & 1u) ? 0u : 8u);
+}
+
 // Traceback of one half by one wave, a run at a time: from the current cell,
 // lane l fetches the code of the l-th cell along the current direction
 // (diagonal in state H, left in E, up in F) and one ballot finds where the
@@ -105,7 +115,9 @@ __device__ __forceinline__ void free_chain(const ChunkPool &p, int c, int lane) 
 // antidiagonals at a time; a chunk goes back to the pool once the walk has
 // left it.  The edit runs (end cell first) go to a chain of pool chunks, then
 // to an exact-size slice of the run arena.  G = rows per code word of the
-// records.  Frees every chunk it was given; returns the half's status.
+// records; NARROW selects the code layout of the 16-bit kernel (see
+// narrow_code).  Frees every chunk it was given; returns the half's status.
+template <bool NARROW>
 __device__ int trace_half(const ChunkPool &pool, int &hint, int lane, int cur, int bi, int bj, int G,
                           const RunArena &ra, uint2 *tb_idx, uint64_t &run_off, uint32_t &nruns) {
     const uint32_t CH = 1u << pool.shift;
@@ -196,7 +208,9 @@ __device__ int trace_half(const ChunkPool &pool, int &hint, int lane, int cur, i
                 const uint64_t wofs = (uint64_t)ent.x + 4ull * (idx / (uint32_t)G);
                 if (wofs + 4 <= (uint64_t)fill) {
                     valid = true;
-                    code = (*(const uint32_t *)(cb + wofs) >> (4u * (idx % (uint32_t)G))) & 15u;
+                    const uint32_t w = *(const uint32_t *)(cb + wofs);
+                    code = NARROW ? narrow_code(w, idx % (uint32_t)G, (uint32_t)G / 2)
+                                  : (w >> (4u * (idx % (uint32_t)G))) & 15u;
                 }
             }
         }
@@ -562,7 +576,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
         uint64_t run_off = 0;
         uint32_t nruns = 0;
         if (status == HALF_OK && (bi != 0 || bj != 0))
-            status = trace_half(pool, hint, lane, cur, bi, bj, C, ra, tb_idx, run_off, nruns);
+            status = trace_half<false>(pool, hint, lane, cur, bi, bj, C, ra, tb_idx, run_off, nruns);
         else
             free_chain(pool, cur, lane);
         if (lane == 0) {
@@ -580,6 +594,385 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
         if (!PERSIST) break;
     }
 }
+
+// ---------------------------------------------------------------------------
+// The same extension in packed 16-bit arithmetic, two rows per register.
+//
+// Every value of antidiagonal k is held relative to that antidiagonal's
+// Y-drop threshold t_k = (best over earlier antidiagonals) - Y, so a cell is
+// live exactly when its value is >= 0; dead values saturate towards -32768
+// (the 16-bit NEG).  When the best improves by d on antidiagonal k,
+// t_{k+1} = t_k + d, and the operands read from antidiagonals k and k - 1 are
+// lowered by the matching sums of improvements (folded into the gap
+// penalties and the score bias).  Live values stay in [0, Y + max score], so
+// the kernel is exact whenever Y + gap open + gap extend + twice the largest
+// score magnitude stays well below 2^15 (checked by the host).  Ties and the
+// traceback decisions are those of the 32-bit kernel: each decision compares
+// two values of which the winner is live, and saturating subtraction keeps
+// the sign of every difference.
+//
+// A lane's C rows form P = C / 2 pairs (p, p + P), row p in the low half of
+// register p, so the row above pair p is pair p - 1 (pair 0: the lane above's
+// last row and the lane's own row P - 1).  Substitution scores come from
+// per-row profiles of biased bytes (score + 128) through v_perm, straight into
+// the right half; two perms and one 32-bit add3 give both rows' diagonal
+// candidates (a low half of at most 0x8000 + 255 never carries).
+typedef short pk_i16 __attribute__((ext_vector_type(2)));
+typedef unsigned short pk_u16 __attribute__((ext_vector_type(2)));
+#define NEG2 ((int)0x80008000)
+
+__device__ __forceinline__ int pk_subs(int a, int b) {
+    return __builtin_bit_cast(int, __builtin_elementwise_sub_sat(__builtin_bit_cast(pk_i16, a), __builtin_bit_cast(pk_i16, b)));
+}
+__device__ __forceinline__ int pk_max(int a, int b) {
+    return __builtin_bit_cast(int, __builtin_elementwise_max(__builtin_bit_cast(pk_i16, a), __builtin_bit_cast(pk_i16, b)));
+}
+// live (>= 0) values unchanged, negative values to -32768
+__device__ __forceinline__ int pk_kill(int a) {
+    return __builtin_bit_cast(int, __builtin_elementwise_min(__builtin_bit_cast(pk_u16, a), (pk_u16){0x8000, 0x8000}));
+}
+__device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & b); }
+__device__ __forceinline__ int pk2(int v) { return (int)(((uint32_t)v & 0xffffu) * 0x10001u); }
+__device__ __forceinline__ int lo16(int v) { return (int)(short)(v & 0xffff); }
+__device__ __forceinline__ int hi16(int v) { return v >> 16; }
+// query-code selectors: the score byte lands in byte 0 (rows p) or byte 2 (rows p + P)
+__device__ __forceinline__ int sel_lo(int code) { return 0x0c0c0c00 | code; }
+__device__ __forceinline__ int sel_hi(int code) { return 0x0c000c0c | (code << 16); }
+__device__ __forceinline__ int lo_of_hi(int x) { return (int)__builtin_amdgcn_perm((uint32_t)x, 0x0c0c0c0cu, 0x00000006u); }
+__device__ __forceinline__ int hi_of_lo(int x) { return (int)__builtin_amdgcn_perm((uint32_t)x, 0x0c0c0c0cu, 0x00040000u); }
+
+template <int C, bool PERSIST>
+__global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict__ tasks, WorkQueue wq, SeqSetView T,
+                                                      SeqSetView Qp, SeqSetView Qm, ScoreDesc sc, ChunkPool pool,
+                                                      RunArena ra, HalfResult *__restrict__ res, int kcap) {
+    static_assert(C % 2 == 0 && C <= 8, "rows in pairs, one 32-bit record word per lane");
+    static_assert(64 * C + 64 + RING_CHUNK <= RING, "target ring too small for the window");
+    constexpr int P = C / 2;
+    __shared__ int prof[2][8];
+    __shared__ uint8_t aring[RING], bring[RING];
+    __shared__ uint2 tb_idx[TB_IDX];
+    const int lane = threadIdx.x;
+    if (lane < 5) {
+        uint32_t lo = 0;
+        for (int b = 0; b < 4; b++) lo |= ((uint32_t)(sc.sub[lane][b] + 128) & 0xffu) << (8 * b);
+        prof[0][lane] = (int)lo;
+        prof[1][lane] = (int)((uint32_t)(sc.sub[lane][4] + 128) & 0xffu);
+    }
+    __syncthreads();
+    const int e = sc.gap_extend, oe = sc.gap_open + sc.gap_extend, Y = sc.ydrop;
+
+    int hint = (int)((blockIdx.x * 37u) % (unsigned)pool.nwords);
+    const uint32_t CH = 1u << pool.shift;
+    auto chunk = [&](int c) { return chunk_ptr(pool, c); };
+
+    int64_t item = PERSIST ? -1 : (int64_t)blockIdx.x;
+    for (;;) {
+        if (PERSIST) {
+            unsigned int q = 0;
+            if (lane == 0) q = atomicAdd(wq.head, 1u);
+            q = (unsigned int)__builtin_amdgcn_readfirstlane((int)q);
+            if ((int64_t)q >= wq.n) break;
+            item = q;
+        }
+        const int64_t tid = wq.ids ? wq.ids[item] : item;
+        const HalfTask tk = tasks[tid];
+        const SeqSetView Q = tk.qset ? Qm : Qp;
+        const int64_t nA = tk.nA, nB = tk.nB;
+        const int64_t kmax = nA + nB;
+        const int nA32 = (int)min(nA, (int64_t)ROW_LIMIT + 4096);
+        const int nB32 = (int)min(nB, (int64_t)ROW_LIMIT + 4096);
+        const int kmax32 = (int)min(kmax, (int64_t)ROW_LIMIT + 4096);
+        __syncthreads();
+        int a_hi = 0, b_hi = 0;
+        while (a_hi < 64 * C + 64) { ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane); a_hi += RING_CHUNK; }
+        while (b_hi < 128) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
+        auto acode = [&](int ia) { return ia < 0 ? 4 : (int)aring[ia & (RING - 1)]; };
+        auto bcode = [&](int jb) {
+            if (jb < 0) return 4;
+            if (jb < b_hi - RING) return codeB(Q, tk, jb);
+            return (int)bring[jb & (RING - 1)];
+        };
+        int bw0 = -(1 << 30), bwa = 4, bwb = 4;
+        auto bcode_next = [&](int pos) {
+            if (pos < bw0 || pos >= bw0 + 128) {
+                while (b_hi < pos + 128) { ring_fill(bring, Q, tk.b0, tk.bdir, nB, b_hi, lane); b_hi += RING_CHUNK; }
+                bw0 = pos - 64;
+                bwa = bcode(bw0 + lane);
+                bwb = bcode(bw0 + 64 + lane);
+            }
+            const int d = pos - bw0;
+            return d < 64 ? __builtin_amdgcn_readlane(bwa, d) : __builtin_amdgcn_readlane(bwb, d - 64);
+        };
+        auto sel_row = [&](int r, int code) { return r < P ? sel_lo(code) : sel_hi(code); };
+
+        // pairs: H1/E1/F1 antidiagonal k - 1 (relative to t_{k-1}), H2 antidiagonal k - 2 (t_{k-2})
+        int H1[P], H2[P], E1[P], F1[P];
+        int Plo[C], Phi[C], Bs[C];
+        int base = 0;
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+            H1[p] = (lane == 0 && p == 0) ? (int)(0x80000000u | (uint32_t)Y) : NEG2;   // cell (0, 0): 0 - t_0 = Y
+            H2[p] = NEG2;
+            E1[p] = NEG2;
+            F1[p] = NEG2;
+        }
+#pragma unroll
+        for (int r = 0; r < C; r++) {
+            const int i = lane * C + r;
+            const int a = acode(i - 1);
+            Plo[r] = prof[0][a];
+            Phi[r] = prof[1][a];
+            Bs[r] = sel_row(r, i == 0 ? bcode(0) : 4);
+        }
+        int best = 0, bi = 0, bj = 0;
+        int d1 = 0, d2 = 0;               // t_k - t_{k-1}, t_{k-1} - t_{k-2}
+        uint64_t cells = 1;
+        int lmin1 = 0, lmax1 = 0, lmin2 = 1, lmax2 = 0;
+        int cur = pool_alloc(pool, hint, lane);
+        uint8_t *cb = nullptr;
+        int k0 = 1;
+        uint32_t fill = 16;
+        int status = HALF_OK;
+        if (cur < 0) {
+            status = HALF_ARENA_OVERFLOW;
+        } else {
+            cb = chunk(cur);
+            if (lane == 0) {
+                ((uint32_t *)cb)[0] = 0xffffffffu;
+                ((uint32_t *)cb)[1] = 1u;
+            }
+        }
+        int k = 1;
+        const int klong = kcap > 0 ? kcap : 0x7fffffff;
+        for (; status == HALF_OK && k <= kmax32; k++) {
+            if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
+            if (k > klong) { status = HALF_LONG; break; }
+            int lo = 0x7fffffff, hi = -1;
+            if (lmin1 <= lmax1) { lo = lmin1; hi = lmax1 + 1; }
+            if (lmin2 <= lmax2) { lo = min(lo, lmin2 + 1); hi = max(hi, lmax2 + 1); }
+            const int clo = max(0, k - nB32);
+            const int chi = min(nA32, k);
+            lo = max(lo, clo);
+            hi = min(hi, chi);
+            const bool nonempty = lo <= hi;
+            if (nonempty) {
+                const int s = (lo - 1 - base) / C;
+                if (s >= 1) {
+                    while (a_hi < base + (s + 64) * C + 64) {
+                        ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane);
+                        a_hi += RING_CHUNK;
+                    }
+                    if (s == 1) {
+#pragma unroll
+                        for (int p = 0; p < P; p++) {
+                            H1[p] = dpp_shl1(NEG2, H1[p]);
+                            H2[p] = dpp_shl1(NEG2, H2[p]);
+                            E1[p] = dpp_shl1(NEG2, E1[p]);
+                            F1[p] = dpp_shl1(NEG2, F1[p]);
+                        }
+#pragma unroll
+                        for (int r = 0; r < C; r++) {
+                            const int i_new = base + 64 * C + r;
+                            const int a = acode(i_new - 1);
+                            Plo[r] = dpp_shl1(prof[0][a], Plo[r]);
+                            Phi[r] = dpp_shl1(prof[1][a], Phi[r]);
+                            Bs[r] = dpp_shl1(sel_row(r, bcode(k - i_new - 1)), Bs[r]);
+                        }
+                    } else {
+                        const int sl_ = min(s, 64);
+                        const int src = (lane + sl_) & 63;
+                        const bool from_next = lane + sl_ >= 64;
+#pragma unroll
+                        for (int p = 0; p < P; p++) {
+                            const int h1 = __shfl(H1[p], src, 64), h2 = __shfl(H2[p], src, 64);
+                            const int e1 = __shfl(E1[p], src, 64), f1 = __shfl(F1[p], src, 64);
+                            H1[p] = from_next ? NEG2 : h1;
+                            H2[p] = from_next ? NEG2 : h2;
+                            E1[p] = from_next ? NEG2 : e1;
+                            F1[p] = from_next ? NEG2 : f1;
+                        }
+#pragma unroll
+                        for (int r = 0; r < C; r++) {
+                            const int i_new = base + s * C + lane * C + r;
+                            const int pl = __shfl(Plo[r], src, 64), ph = __shfl(Phi[r], src, 64);
+                            const int bs = __shfl(Bs[r], src, 64);
+                            const int a = acode(i_new - 1);
+                            Plo[r] = from_next ? prof[0][a] : pl;
+                            Phi[r] = from_next ? prof[1][a] : ph;
+                            Bs[r] = from_next ? sel_row(r, bcode(k - i_new - 1)) : bs;
+                        }
+                    }
+                    base += s * C;
+                }
+                if (hi > base + 64 * C - 1) { status = HALF_WIDTH_OVERFLOW; break; }
+            }
+            const int oeD = pk2(oe + d1), eD = pk2(e + d1), gD = pk2(128 + d1 + d2);
+            const int upH = (int)__builtin_amdgcn_alignbit((uint32_t)H1[P - 1], (uint32_t)dpp_shr1(NEG2, H1[P - 1]), 16);
+            const int upF = (int)__builtin_amdgcn_alignbit((uint32_t)F1[P - 1], (uint32_t)dpp_shr1(NEG2, F1[P - 1]), 16);
+            const int upD = (int)__builtin_amdgcn_alignbit((uint32_t)H2[P - 1], (uint32_t)dpp_shr1(NEG2, H2[P - 1]), 16);
+            int Hn[P], En[P], Fn[P];
+            uint32_t nib = 0;
+            auto cell_pass = [&](auto edge_tag) {
+                constexpr bool EDGE = decltype(edge_tag)::value;
+                const int i0 = base + lane * C;
+#pragma unroll
+                for (int p = 0; p < P; p++) {
+                    const int Hu = p ? H1[p - 1] : upH;
+                    const int Fu = p ? F1[p - 1] : upF;
+                    const int Hd = p ? H2[p - 1] : upD;
+                    const int hlo = pk_subs(H1[p], oeD), ele = pk_subs(E1[p], eD);
+                    const int huo = pk_subs(Hu, oeD), fue = pk_subs(Fu, eD);
+                    const int E = pk_max(hlo, ele), F = pk_max(huo, fue);
+                    const int sE = pk_subs(hlo, ele), sF = pk_subs(huo, fue);
+                    const uint32_t s2 = (uint32_t)Hd +
+                                        __builtin_amdgcn_perm((uint32_t)Phi[p], (uint32_t)Plo[p], (uint32_t)Bs[p]) +
+                                        __builtin_amdgcn_perm((uint32_t)Phi[p + P], (uint32_t)Plo[p + P], (uint32_t)Bs[p + P]);
+                    const int G = pk_subs((int)s2, gD);
+                    const int t = pk_max(E, F);
+                    const int H = pk_max(G, t);
+                    const int sD = pk_subs(G, t), sEF = pk_subs(E, F);
+                    int h = pk_kill(H);
+                    if (EDGE) {
+                        const bool vl = (unsigned)(i0 + p - clo) <= (unsigned)(chi - clo);
+                        const bool vh = (unsigned)(i0 + p + P - clo) <= (unsigned)(chi - clo);
+                        const uint32_t m = (vl ? 0x0000ffffu : 0u) | (vh ? 0xffff0000u : 0u);
+                        En[p] = (int)bfi(m, (uint32_t)E, (uint32_t)NEG2);
+                        Fn[p] = (int)bfi(m, (uint32_t)F, (uint32_t)NEG2);
+                        h = (int)bfi(m, (uint32_t)h, (uint32_t)NEG2);
+                    } else {
+                        En[p] = E;
+                        Fn[p] = F;
+                    }
+                    Hn[p] = h;
+                    const uint32_t ca = bfi(0x80008000u, (uint32_t)sD, (uint32_t)sEF >> 1);
+                    const uint32_t cb2 = bfi(0x80008000u, (uint32_t)sE, (uint32_t)sF >> 1);
+                    const uint32_t cc = bfi(0xC000C000u, ca, cb2 >> 2);
+                    nib = p ? bfi(0xF000F000u >> (4 * p), cc >> (4 * p), nib) : cc;
+                }
+            };
+            const bool edge = base < clo || base + 64 * C - 1 > nA32;
+            if (edge) cell_pass(std::true_type());
+            else cell_pass(std::false_type());
+            // live rows: bit p (row p) and bit 16 + p (row p + P) of lmask
+            uint32_t dead = 0;
+#pragma unroll
+            for (int p = 0; p < P; p++) dead |= ((uint32_t)Hn[p] >> (15 - p)) & (0x00010001u << p);
+            const uint32_t lmask = ~dead & (((1u << P) - 1u) * 0x10001u);
+            int lmin0 = 1, lmax0 = 0;
+            {
+                const uint64_t m = __ballot(lmask != 0);
+                if (m) {
+                    const int L1 = __builtin_ctzll(m), L2 = 63 - __builtin_clzll(m);
+                    const uint32_t f1 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L1);
+                    const uint32_t f2 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L2);
+                    const int r1 = (f1 & 0xffffu) ? __builtin_ctz(f1 & 0xffffu) : P + __builtin_ctz(f1 >> 16);
+                    const int r2 = (f2 >> 16) ? P + (31 - __builtin_clz(f2 >> 16)) : 31 - __builtin_clz(f2 & 0xffffu);
+                    lmin0 = base + L1 * C + r1;
+                    lmax0 = base + L2 * C + r2;
+                }
+            }
+            {
+                int l_lo = 0, l_hi = -1;
+                if (nonempty) {
+                    l_lo = (lo - base) / C;
+                    l_hi = (hi - base) / C;
+                }
+                const uint32_t ng = (uint32_t)(l_hi - l_lo + 1);
+                const uint32_t need = 4 * ng;
+                if (fill + need + 8u * (uint32_t)(k - k0 + 1) > CH) {
+                    const int nc = pool_alloc(pool, hint, lane);
+                    if (nc < 0) { status = HALF_ARENA_OVERFLOW; break; }
+                    if (lane == 0) {
+                        ((uint32_t *)cb)[2] = fill;
+                        uint32_t *nh = (uint32_t *)chunk(nc);
+                        nh[0] = (uint32_t)cur;
+                        nh[1] = (uint32_t)k;
+                    }
+                    cur = nc;
+                    cb = chunk(nc);
+                    k0 = k;
+                    fill = 16;
+                }
+                uint32_t *rec = (uint32_t *)(cb + fill);
+                if (lane >= l_lo && lane <= l_hi) rec[lane - l_lo] = nib;
+                if (lane == 0)
+                    *(uint2 *)(cb + CH - 8u * (uint32_t)(k - k0 + 1)) =
+                        make_uint2(fill, nonempty ? (uint32_t)(base + l_lo * C) : 0u);
+                fill += need;
+                if (nonempty) cells += (uint64_t)(hi - lo + 1);
+            }
+            // best: a live value above Y (relative to t_k) beats it; then the first row reaching the maximum
+            int mx = Hn[0];
+#pragma unroll
+            for (int p = 1; p < P; p++) mx = pk_max(mx, Hn[p]);
+            mx = imax(lo16(mx), hi16(mx));
+            int dnow = 0;
+            if (__ballot(mx > Y)) {
+                const int admax = wave_max_dpp(mx);
+                const uint32_t a2 = (uint32_t)pk2(admax);
+                uint32_t eq = 0;
+#pragma unroll
+                for (int p = 0; p < P; p++) {
+                    const uint32_t x = (uint32_t)Hn[p] ^ a2;
+                    eq |= ((x & 0xffffu) == 0 ? (1u << p) : 0u) | ((x >> 16) == 0 ? (0x10000u << p) : 0u);
+                }
+                const uint64_t m = __ballot(eq != 0);
+                const int L = __builtin_ctzll(m);
+                const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)eq, L);
+                const int row = L * C + ((f & 0xffffu) ? __builtin_ctz(f & 0xffffu) : P + __builtin_ctz(f >> 16));
+                dnow = admax - Y;
+                best += dnow;
+                bi = base + row;
+                bj = k - bi;
+                if (best >= SFE_SCORE_LIMIT) { status = HALF_SCORE_RANGE; break; }
+            }
+            d2 = d1;
+            d1 = dnow;
+#pragma unroll
+            for (int p = 0; p < P; p++) {
+                H2[p] = H1[p];
+                H1[p] = Hn[p];
+                E1[p] = En[p];
+                F1[p] = Fn[p];
+            }
+            {
+                // rows move down by one: row 0 takes the lane above's row C - 1 (lane 0: the code entering)
+                const int carry = lo_of_hi(dpp_shr1(sel_hi(bcode_next(k - base)), Bs[C - 1]));
+                const int into_hi = hi_of_lo(Bs[P - 1]);
+#pragma unroll
+                for (int r = C - 1; r > 0; r--) Bs[r] = (r == P) ? into_hi : Bs[r - 1];
+                Bs[0] = carry;
+            }
+            const bool stop = (lmin0 > lmax0) && (lmin1 > lmax1);
+            lmin2 = lmin1; lmax2 = lmax1;
+            lmin1 = lmin0; lmax1 = lmax0;
+            if (stop) break;
+        }
+
+        if (cur >= 0 && lane == 0) ((uint32_t *)cb)[2] = fill;
+
+        uint64_t run_off = 0;
+        uint32_t nruns = 0;
+        if (status == HALF_OK && (bi != 0 || bj != 0))
+            status = trace_half<true>(pool, hint, lane, cur, bi, bj, C, ra, tb_idx, run_off, nruns);
+        else
+            free_chain(pool, cur, lane);
+        if (lane == 0) {
+            HalfResult o;
+            o.best = best;
+            o.i_end = bi;
+            o.j_end = bj;
+            o.status = status;
+            o.cells = cells;
+            o.tb_page = run_off;
+            o.tb_end = nruns;
+            o.k_last = (int32_t)min((int64_t)k, kmax);
+            res[tid] = o;
+        }
+        if (!PERSIST) break;
+    }
+}
+#undef NEG2
 
 // ---------------------------------------------------------------------------
 // Wave-group extension of one long half (Sec. 8: a long anchor-half spread over
@@ -986,7 +1379,7 @@ __global__ void __launch_bounds__(64 * W) k_ydrop_coop(const HalfTask *__restric
         uint64_t run_off = 0;
         uint32_t nruns = 0;
         if (status == HALF_OK && (bi != 0 || bj != 0))
-            status = trace_half(pool, hint, lane, cur, bi, bj, C, ra, tb_idx, run_off, nruns);
+            status = trace_half<false>(pool, hint, lane, cur, bi, bj, C, ra, tb_idx, run_off, nruns);
         else
             free_chain(pool, cur, lane);
         if (lane == 0) {
@@ -1017,10 +1410,25 @@ void launch_ydrop_coop(int cells_per_lane, bool perm, const HalfTask *tasks, con
     }
 }
 
-void launch_ydrop_fused(int cells_per_lane, bool perm, bool persistent, const HalfTask *tasks, WorkQueue wq,
-                        int64_t grid, SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, ChunkPool pool,
-                        RunArena ra, HalfResult *res, int kcap, hipStream_t st) {
+void launch_ydrop_fused(int cells_per_lane, bool perm, bool narrow, bool persistent, const HalfTask *tasks,
+                        WorkQueue wq, int64_t grid, SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc,
+                        ChunkPool pool, RunArena ra, HalfResult *res, int kcap, hipStream_t st) {
     if (grid <= 0) return;
+    if (narrow) {
+#define SFE_LAUNCH16(CC, QQ) \
+    k_ydrop_fused16<CC, QQ><<<(unsigned)grid, 64, 0, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res, kcap)
+#define SFE_BY_C16(QQ)                                    \
+    do {                                                  \
+        if (cells_per_lane <= 2) SFE_LAUNCH16(2, QQ);     \
+        else if (cells_per_lane <= 4) SFE_LAUNCH16(4, QQ); \
+        else if (cells_per_lane <= 6) SFE_LAUNCH16(6, QQ); \
+        else SFE_LAUNCH16(8, QQ);                         \
+    } while (0)
+        if (persistent) SFE_BY_C16(true); else SFE_BY_C16(false);
+#undef SFE_BY_C16
+#undef SFE_LAUNCH16
+        return;
+    }
 #define SFE_LAUNCH(CC, PP, QQ) \
     k_ydrop_fused<CC, PP, QQ><<<(unsigned)grid, 64, 0, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res, kcap)
 #define SFE_BY_C(PP, QQ)                                  \
@@ -1040,9 +1448,23 @@ void launch_ydrop_fused(int cells_per_lane, bool perm, bool persistent, const Ha
 #undef SFE_LAUNCH
 }
 
-int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool persistent) {
+int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool narrow, bool persistent) {
     int nb = 0;
     hipError_t err = hipSuccess;
+    if (narrow) {
+#define SFE_OCC16(CC, QQ) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ydrop_fused16<CC, QQ>, 64, 0)
+#define SFE_OCC_C16(QQ)                                   \
+    do {                                                  \
+        if (cells_per_lane <= 2) SFE_OCC16(2, QQ);        \
+        else if (cells_per_lane <= 4) SFE_OCC16(4, QQ);   \
+        else if (cells_per_lane <= 6) SFE_OCC16(6, QQ);   \
+        else SFE_OCC16(8, QQ);                            \
+    } while (0)
+        if (persistent) SFE_OCC_C16(true); else SFE_OCC_C16(false);
+#undef SFE_OCC_C16
+#undef SFE_OCC16
+        return err == hipSuccess ? nb : -1;
+    }
 #define SFE_OCC(CC, PP, QQ) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ydrop_fused<CC, PP, QQ>, 64, 0)
 #define SFE_OCC_C(PP, QQ)                                 \
     do {                                                  \

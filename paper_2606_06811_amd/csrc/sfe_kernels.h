@@ -66,15 +66,17 @@ void launch_make_tasks(const ExtItem *items, int64_t n, const UnitDesc *units, i
 // fused extension + traceback (k_fused.hip); plain: grid = wq.n blocks, one
 // half each; persistent: `grid` waves pulling halves from the queue
 // kcap > 0: a half still running at antidiagonal kcap stops with HALF_LONG
-void launch_ydrop_fused(int cells_per_lane, bool perm, bool persistent, const HalfTask *tasks, WorkQueue wq,
-                        int64_t grid, SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, ChunkPool pool,
-                        RunArena ra, HalfResult *res, int kcap, hipStream_t st);
+// narrow: the packed 16-bit kernel (perm scores, Y-drop range checked by the
+// caller; cells_per_lane rounds up to an even count)
+void launch_ydrop_fused(int cells_per_lane, bool perm, bool narrow, bool persistent, const HalfTask *tasks,
+                        WorkQueue wq, int64_t grid, SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc,
+                        ChunkPool pool, RunArena ra, HalfResult *res, int kcap, hipStream_t st);
 // A group of 4 waves per half (wave-group window of 256 * cells_per_lane rows,
 // cells_per_lane 2 or 4), one block per half ids[0 .. n).
 void launch_ydrop_coop(int cells_per_lane, bool perm, const HalfTask *tasks, const int32_t *ids, int64_t n,
                        SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, ChunkPool pool, RunArena ra,
                        HalfResult *res, hipStream_t st);
-int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool persistent);
+int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool narrow, bool persistent);
 void launch_ydrop_ring(const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T, SeqSetView Qp,
                        SeqSetView Qm, const ScoreDesc &sc, Arena arena, int32_t *ring, int32_t cap_rows,
                        HalfResult *res, hipStream_t st);

@@ -59,7 +59,8 @@ class _AlignOpts(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("wave_group_cap", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("wave_group_cap", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("wide_scores", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class _TuneEntry(ctypes.Structure):
@@ -212,17 +213,18 @@ def sfe_ctx_create(device: int = 0, stream=None) -> Context:
     return Context(device, stream)
 
 
-def sfe_ctx_set_tuning(ctx: Context, wave_group_cap: int = 0, use_graphs: int = 0):
+def sfe_ctx_set_tuning(ctx: Context, wave_group_cap: int = 0, use_graphs: int = 0, wide_scores: int = 0):
     t = _Tuning()
     t.wave_group_cap = int(wave_group_cap)
     t.use_graphs = int(use_graphs)
+    t.wide_scores = int(wide_scores)
     _check(lib().sfe_ctx_set_tuning(ctx.ptr, ctypes.byref(t)), ctx)
 
 
 def sfe_ctx_get_tuning(ctx: Context) -> dict:
     t = _Tuning()
     _check(lib().sfe_ctx_get_tuning(ctx.ptr, ctypes.byref(t)), ctx)
-    return {"wave_group_cap": t.wave_group_cap, "use_graphs": t.use_graphs}
+    return {"wave_group_cap": t.wave_group_cap, "use_graphs": t.use_graphs, "wide_scores": t.wide_scores}
 
 
 def sfe_autotune(ctx: Context, idx: Index, queries, scoring: dict, sample_bases: int, model=None,

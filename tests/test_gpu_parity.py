@@ -221,6 +221,50 @@ def test_gapped_ydrop_scoring_variants(ctx, ydrop, gap_open, gap_extend):
     compare_extensions(T, Qs, h, alns, ops, sc)
 
 
+INT8_EXTREMES = [[127, -128, -1, -128, -128], [-128, 127, -128, 0, -128], [0, -128, 127, -128, -128],
+                 [-128, -1, -128, 127, -128], [-128, -128, -128, -128, -128]]
+NOT_INT8 = [[200, -114, -31, -123, -100], [-114, 100, -125, -31, -100], [-31, -125, 100, -114, -100],
+            [-123, -31, -114, 91, -100], [-100, -100, -100, -100, -100]]
+# narrow (16-bit) kernel while ydrop + o + e + 2 max|s| + 512 <= 32767: with o=400, e=300
+# and HOXD70 (max |s| 125) the last Y that qualifies is 31305
+NARROW_CASES = {
+    "hoxd70": (synth.HOXD70, 9400, 400, 30),
+    "last_narrow_y": (synth.HOXD70, 31305, 400, 300),
+    "first_wide_y": (synth.HOXD70, 31306, 400, 300),
+    "int8_extremes": (INT8_EXTREMES, 9400, 400, 30),
+    "scores_beyond_int8": (NOT_INT8, 9400, 400, 30),
+    "no_gap_open": (synth.HOXD70, 3000, 0, 1),
+}
+
+
+@pytest.mark.parametrize("wide", [0, 1])
+@pytest.mark.parametrize("case", sorted(NARROW_CASES))
+def test_narrow_and_wide_kernels(ctx, case, wide):
+    """The packed 16-bit extension (values relative to the Y-drop threshold)
+    and the 32-bit one both give the oracle's ends, scores, cells and edit
+    operations, at and just past the range limit of the 16-bit kernel."""
+    sub, ydrop, gap_open, gap_extend = NARROW_CASES[case]
+    log(f"narrow/wide kernel case {case} wide_scores={wide}")
+    rng = synth.rng_for(700 + len(case))
+    n = 2500
+    t = synth.iid_codes(rng, n)
+    q, _ = synth.mutate(rng, t, np.zeros(n, bool), 0.15, indel=0.02)
+    T, Qs = synth.to_ascii(t), [synth.to_ascii(q)]
+    sc = dict(synth.SCORING, sub=sub, ydrop=ydrop, gap_open=gap_open, gap_extend=gap_extend,
+              gapped_thresh=-(1 << 29))
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    m = min(len(T), len(Qs[0]))
+    h = np.zeros(5, sfe.HSP_DTYPE)
+    for x, a in enumerate([0, 7, m // 3, m // 2, m - 2]):
+        h[x] = (a, a, 1, 0, 0, 0, (0, 0, 0))
+    sfe.sfe_ctx_set_tuning(ctx, wide_scores=wide)
+    try:
+        alns, ops = sfe.sfe_gapped_ydrop(ctx, idx, Qs, h, sc)
+    finally:
+        sfe.sfe_ctx_set_tuning(ctx)
+    compare_extensions(T, Qs, h, alns, ops, sc)
+
+
 # ---------------------------------------------------------------------------
 # whole pipeline
 # ---------------------------------------------------------------------------
@@ -258,6 +302,19 @@ def test_align_parity(ctx, align_case, K, cpl, policy, schedule):
     compare_alignments(alns, ops, ref)
     assert st["committed"] == alns.shape[0]
     assert st["extensions"] >= ref["n_extensions"]
+
+
+def test_align_parity_wide_scores(ctx, align_case):
+    """The whole pipeline on the 32-bit extension kernel."""
+    log("align parity with 32-bit extension")
+    T, Q, ref = align_case
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    sfe.sfe_ctx_set_tuning(ctx, wide_scores=1)
+    try:
+        alns, ops, st = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING))
+    finally:
+        sfe.sfe_ctx_set_tuning(ctx)
+    compare_alignments(alns, ops, ref)
 
 
 @pytest.mark.parametrize("policy", [0, 1])
