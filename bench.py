@@ -33,8 +33,10 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz of int32 VALU lane-ops per second
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz of int32 VALU lane-ops per second; packed 16-bit
+# instructions (v_pk_*_i16/u16) do two lane-ops each
 INT32_VALU_PEAK_OPS = 256 * 64 * 2.4e9
+INT16X2_VALU_PEAK_OPS = 2 * INT32_VALU_PEAK_OPS
 YDROP_OPS_PER_CELL = 12      # E 3, F 3, G 2, H 1, prune 2, best 1
 XDROP_OPS_PER_COLUMN = 6     # 2 base extracts, index, lookup, add, max / drop test
 
@@ -193,7 +195,8 @@ def main():
     s = stats[-1]
     hsps_per_s = s["hsps"] / (ms_step / 1e3)
 
-    # dominant kernel: gapped extension (int32 VALU bound); live HIP-event timing
+    # dominant kernel: gapped extension (VALU bound; packed int16 when every launch took the
+    # 16-bit kernel); live HIP-event timing
     yd_ms = sum(x["ms_ydrop_kernel"] for x in stats)
     yd_cells = sum(x["ydrop_kernel_cells"] for x in stats)
     yd_launches = sum(x["ydrop_launches"] for x in stats)
@@ -202,17 +205,22 @@ def main():
     yd_ops_s = YDROP_OPS_PER_CELL * yd_cells / (yd_ms / 1e3) if yd_ms > 0 else 0.0
     sx_ops_s = XDROP_OPS_PER_COLUMN * sx_cols / (sx_ms / 1e3) if sx_ms > 0 else 0.0
     dominant = "ydrop" if yd_ms >= sx_ms else "seed_xdrop"
+    narrow = all(x["narrow_launches"] == x["ydrop_launches"] for x in stats)
+    ext_type = "int16" if narrow else "int32"
     if dominant == "ydrop":
         achieved = yd_ops_s / 1e12
-        note = (f"k_ydrop_fused (extension + traceback): {YDROP_OPS_PER_CELL} int32 ops per DP cell x "
+        kname = "k_ydrop_fused16" if narrow else "k_ydrop_fused"
+        note = (f"{kname} (extension + traceback): {YDROP_OPS_PER_CELL} {ext_type} ops per DP cell x "
                 f"{yd_cells / max(yd_launches, 1):.3g} cells per launch / {yd_ms / max(yd_launches, 1):.3f} ms "
                 f"average launch ({yd_launches} launches)")
     else:
         achieved = sx_ops_s / 1e12
         note = (f"k_seed_xdrop: {XDROP_OPS_PER_COLUMN} int32 ops per scanned column x "
                 f"{sx_cols / max(len(stats), 1):.3g} columns per launch / {sx_ms / max(len(stats), 1):.3f} ms")
-    peak = INT32_VALU_PEAK_OPS / 1e12
-    roofline = dict(bound="alu", achieved=round(achieved, 4), peak=round(peak, 2), unit="Tops/s (int32 lane-ops)",
+    packed = dominant == "ydrop" and narrow
+    peak = (INT16X2_VALU_PEAK_OPS if packed else INT32_VALU_PEAK_OPS) / 1e12
+    unit = "Tops/s (int16 lane-ops, two per packed instruction)" if packed else "Tops/s (int32 lane-ops)"
+    roofline = dict(bound="alu", achieved=round(achieved, 4), peak=round(peak, 2), unit=unit,
                     frac=round(achieved / peak, 5), traffic=None, kernel=dominant, note=note)
 
     cpu = None
@@ -242,7 +250,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": ext_type,
         "data": "synthetic",
         "config": {"workload": desc, "schedule": kinds[-1], "policy": "defer",
                    "round_k": args.round_k or (1 << 20)},

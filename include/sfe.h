@@ -173,6 +173,7 @@ typedef struct {
     int64_t predicted_halves;   /* halves queued by a cost model */
     int64_t mispredicted_halves;/* of those: predicted log2(1 + cells) off by more than 2 */
     double ms_predict;          /* host wall clock of features + model inference */
+    int64_t narrow_launches;    /* of ydrop_launches: launches of the packed 16-bit kernel */
 } sfe_stats;
 
 /* Context on `device` using `hip_stream` (a hipStream_t, or NULL for a

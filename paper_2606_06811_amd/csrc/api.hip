@@ -94,7 +94,7 @@ struct sfe_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // per-call kernel accounting (reset by sfe_align)
     double ydrop_ms = 0, sx_ms = 0;
-    int64_t ydrop_launches = 0, ydrop_cells = 0, sx_launches = 0;
+    int64_t ydrop_launches = 0, ydrop_cells = 0, sx_launches = 0, narrow_launches = 0;
 };
 
 struct sfe_index {
@@ -558,6 +558,7 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         if (fused) {
             c->ydrop_ms += event_ms(c);
             c->ydrop_launches++;
+            if (narrow && sg <= ST_WAVE8) c->narrow_launches++;
         }
         std::vector<int32_t> next = rest, traced;
         bool arena_full = false, runs_full = false, pool_full = false;
@@ -1091,7 +1092,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         if (o.arena_bytes > 0) set_arena(c, std::max<int64_t>(o.arena_bytes, 2 * ARENA_PAGE));
         sfe_stats st{};
         c->ydrop_ms = c->sx_ms = 0;
-        c->ydrop_launches = c->ydrop_cells = c->sx_launches = 0;
+        c->ydrop_launches = c->ydrop_cells = c->sx_launches = c->narrow_launches = 0;
         QueryLayout L;
         upload_queries(c, queries, nq, strands, ix->sd.span, L);
         check_range(ix, queries, nq, sc);
@@ -1381,6 +1382,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             st.ms_extend = t4 - t3;
             st.ms_total = now_ms() - t0;
             st.ydrop_launches = c->ydrop_launches;
+            st.narrow_launches = c->narrow_launches;
             st.ydrop_kernel_cells = c->ydrop_cells;
             st.seed_xdrop_launches = c->sx_launches;
             st.ms_ydrop_kernel = c->ydrop_ms;
