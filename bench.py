@@ -9,11 +9,11 @@ Y-drop extension with traceback and serial commit.  Inputs are synthetic
 
 Two schedules of the gapped stage are timed on the same step: the plain one
 (one wave per anchor-half, halves in batch order) and the learned one: the
-cost model is trained first, on the GPU, from extension logs of the plain
-pipeline on the 1 Mbp pair; the autotuner then times candidate schedules
-(rows per lane, plain or persistent launch with the model's longest-first
-queue, wave groups for long halves) on a 1 Mbp sample of the query and the
-fastest is used.  Both run untimed before the timed steps.  Their outputs must
+cost model is trained first, on the GPU, from extension logs of every HSP of
+the first 2 Mbp of the query; the autotuner then times candidate schedules
+(rows per lane; plain, persistent or adaptive launch with the model's
+longest-first order; wave groups for long halves) on a 1 Mbp sample of the
+query and the fastest is used (adaptive when no tuning is asked for).  Both run untimed before the timed steps.  Their outputs must
 be identical.
 
 Prints one JSON line.  `value` is unique HSPs per second of the whole step
@@ -73,10 +73,18 @@ def cpu_baseline(T, Q, sc, sample_bp: int):
                        f"in {dt:.1f} s")
 
 
-def train_cost_model(ctx, sfe, synth, log_fn):
-    """The learned part: extension logs of the plain pipeline on the 1 Mbp pair,
-    then GPU training of the cost model (He-uniform start, seeded)."""
-    T, Q = synth.pair_small()
+def train_cost_model(ctx, sfe, synth, log_fn, T=None, Q=None, train_bp=0):
+    """The learned part: extension logs of every HSP of a training sample, then
+    GPU training of the cost model (He-uniform start, seeded).  The sample is
+    the first train_bp query bases of the benchmark pair against its whole
+    target (the part the timed steps start with), or the 1 Mbp pair when
+    train_bp is 0."""
+    if train_bp > 0:
+        Q = [q[:train_bp] for q in Q]
+        what = f"the first {train_bp} query bases of the benchmark pair"
+    else:
+        T, Q = synth.pair_small()
+        what = "the 1 Mbp pair"
     idx = sfe.sfe_build_index(ctx, T, synth.SEED_PATTERN, 1, 1)
     hits = sfe.sfe_seed_hits(ctx, idx, Q)
     hsps = sfe.sfe_ungapped_xdrop(ctx, idx, Q, hits, dict(synth.SCORING))
@@ -95,9 +103,9 @@ def train_cost_model(ctx, sfe, synth, log_fn):
     t0 = time.perf_counter()
     losses = model.train(f, t, order, batch=256, lr=2e-3)
     dt = time.perf_counter() - t0
-    log_fn(f"cost model trained on {n} extensions of the 1 Mbp pair: loss {losses[0]:.3f} -> "
+    log_fn(f"cost model trained on {n} extensions of {what}: loss {losses[0]:.3f} -> "
            f"{losses[-1]:.3f} in {len(losses)} steps, {dt:.2f} s")
-    return model, dict(samples=int(n), steps=int(len(losses)), loss_first=float(losses[0]),
+    return model, dict(source=what, samples=int(n), steps=int(len(losses)), loss_first=float(losses[0]),
                        loss_last=float(losses[-1]), train_s=round(dt, 3))
 
 
@@ -108,12 +116,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mid", choices=["mid", "small"])
     ap.add_argument("--round-k", type=int, default=0)
-    ap.add_argument("--schedule", default="both", choices=["plain", "persistent", "learned", "both"],
-                    help="both: time the plain schedule and the learned persistent one (value = learned)")
+    ap.add_argument("--schedule", default="both", choices=["plain", "persistent", "adaptive", "learned", "both"],
+                    help="both: time the plain schedule and the learned, autotuned one (value = learned)")
     ap.add_argument("--cpl", type=int, default=0, help="rows per lane of the first band window (0: default)")
     ap.add_argument("--near-band", type=int, default=0, help="deferral nearness band (0: default, <0: off)")
     ap.add_argument("--tune-bp", type=int, default=1_000_000,
                     help="query bases the autotuner samples for the learned schedule (0: no tuning)")
+    ap.add_argument("--train-bp", type=int, default=2_000_000,
+                    help="query bases of the benchmark pair whose HSP extensions train the cost model "
+                         "(0: the 1 Mbp pair)")
     ap.add_argument("--cpu-sample-bp", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -137,9 +148,9 @@ def main():
     torch.cuda.synchronize()
 
     model, train_info, tune_info = None, None, None
-    tuned = dict(max_cells_per_lane=args.cpl, schedule=sfe.SFE_SCHED_PERSISTENT, wave_group_cap=0)
+    tuned = dict(max_cells_per_lane=args.cpl, schedule=sfe.SFE_SCHED_ADAPTIVE, wave_group_cap=0)
     if args.schedule in ("learned", "both"):
-        model, train_info = train_cost_model(ctx, sfe, synth, log)
+        model, train_info = train_cost_model(ctx, sfe, synth, log, Td, Qd, args.train_bp)
         if args.tune_bp > 0:
             # autotuner: candidate schedules timed on the first tune_bp query bases (untimed setup)
             t0 = time.perf_counter()
@@ -159,10 +170,12 @@ def main():
                                 ops_cap=1 << 26, max_cells_per_lane=args.cpl, near_band=args.near_band)
         else:
             sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=tuned["wave_group_cap"] if kind == "learned" else 0)
+            fixed = sfe.SFE_SCHED_ADAPTIVE if kind == "adaptive" else sfe.SFE_SCHED_PERSISTENT
             out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k,
-                                schedule=tuned["schedule"] if kind == "learned" else sfe.SFE_SCHED_PERSISTENT,
+                                schedule=tuned["schedule"] if kind == "learned" else fixed,
                                 cap=1 << 21, ops_cap=1 << 26, model=model if kind == "learned" else None,
-                                max_cells_per_lane=tuned["max_cells_per_lane"] if kind == "learned" else args.cpl)
+                                max_cells_per_lane=tuned["max_cells_per_lane"] if kind == "learned" else args.cpl,
+                                near_band=args.near_band)
         idx.close()
         return out
 

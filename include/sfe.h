@@ -118,14 +118,18 @@ typedef struct {
 /* Schedules of the gapped extension; all give identical results. */
 #define SFE_SCHED_PLAIN 0       /* one wavefront per anchor-half, one launch per batch */
 #define SFE_SCHED_PERSISTENT 1  /* persistent work-stealing launch over a cost-ordered queue */
+#define SFE_SCHED_ADAPTIVE 2    /* plain launch for a batch of at least sfe_tuning.adaptive_halves
+                                   halves, persistent below (fewer halves in flight at once,
+                                   spread evenly over the SIMDs) */
 
 /* Speculation policies of sfe_align; all give identical results.
  * PREFIX: each batch is the next round_k HSPs of a (query, strand) whose
  *   anchors are not contained in a committed alignment (Alg. 3 as printed).
  * DEFER:  the scan also passes over (defers) an HSP whose anchor lies on an M
  *   column of an earlier extension still waiting for commit, or whose
- *   diagonal is within near_band (64 by default) of an earlier HSP already in
- *   the batch; deferred HSPs are decided in later batches.  A waiting
+ *   diagonal is within near_band (32 by default) of an earlier HSP already in
+ *   the batch while no extension computed so far spans the anchor's region
+ *   (its bounding box); deferred HSPs are decided in later batches.  A waiting
  *   extension holds nothing back when it is expected to be skipped at commit:
  *   its anchor already lies in a committed alignment, or on an M column of an
  *   earlier waiting extension that is not itself expected to be skipped.
@@ -143,14 +147,15 @@ typedef struct {
                                workgroup kernel */
     int32_t policy;         /* SFE_POLICY_* */
     int32_t near_band;      /* SFE_POLICY_DEFER's nearness rule: diagonals within which a later HSP
-                               of the batch waits for an earlier one; 0 = 64, < 0 = rule off */
+                               of the batch waits for an earlier one; 0 = 32, < 0 = rule off */
     int64_t arena_bytes;    /* device memory for traceback codes of the halves in flight,
-                               allocated once per context; 0 = 32 GiB.  A batch whose halves
+                               allocated once per context; 0 = half the free device memory
+                               at first use (at least 32 GiB).  A batch whose halves
                                need more at once runs with fewer in flight; a single half
                                that needs more makes the arena grow. */
-    const struct sfe_model *model; /* NULL, or a cost model: with SFE_SCHED_PERSISTENT the halves of
-                               each batch are queued longest-predicted first.  Never changes
-                               the output. */
+    const struct sfe_model *model; /* NULL, or a cost model: with SFE_SCHED_PERSISTENT or
+                               SFE_SCHED_ADAPTIVE the halves of each batch are queued (or
+                               launched) longest-predicted first.  Never changes the output. */
 } sfe_align_opts;
 
 typedef struct {
@@ -248,15 +253,18 @@ typedef struct {
                                packed 16-bit arithmetic, values relative to the Y-drop threshold,
                                when every score fits in int8 and ydrop + gap_open + gap_extend +
                                2 * max |score| + 512 <= 32767 (same results either way) */
-    int32_t reserved[5];
+    int32_t persist_waves_per_cu; /* waves per compute unit of a persistent launch (capped by
+                               occupancy); 0 = 8, two per SIMD */
+    int32_t adaptive_halves;  /* SFE_SCHED_ADAPTIVE threshold in halves; 0 = 131072 */
+    int32_t reserved[3];
 } sfe_tuning;
 sfe_status sfe_ctx_set_tuning(sfe_ctx *ctx, const sfe_tuning *t);
 sfe_status sfe_ctx_get_tuning(const sfe_ctx *ctx, sfe_tuning *t);
 
 /* Autotuner.  Times sfe_align on a sample of the workload (the first
  * sample_bases of every query, all against idx) under each candidate schedule
- * -- rows per lane 4 / 6 / 8 in the first band window, plain or persistent
- * launch (persistent with opts->model when one is given), wave groups for
+ * -- rows per lane 6 / 8 in the first band window, plain, persistent or
+ * adaptive launch (the last two with opts->model when one is given), wave groups for
  * long halves off or after 8192 antidiagonals -- and keeps the fastest: the
  * context's wave_group_cap is set and opts->max_cells_per_lane / schedule are
  * written.  Other fields of *opts are used as given.  report (may be NULL)

@@ -342,8 +342,18 @@ struct BatchResult {
     int64_t predicted = 0, mispredicted = 0;
 };
 
-// Default traceback arena: 32 GiB of the 288 GB of HBM, allocated on first use.
-const int64_t kDefaultArena = (int64_t)32 << 30;
+// Default traceback arena, allocated on first use: half the device memory then
+// free (at least 32 GiB, in 256 KiB chunks).  The codes of every long half in
+// flight live there at once: a batch of a few thousand halves of 10^6
+// antidiagonals holds a few hundred GB of codes at its peak, and a dry pool
+// makes waves wait for chunks.
+const int64_t kMinArena = (int64_t)32 << 30;
+int64_t default_arena(sfe_ctx *c) {
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    const int64_t half = (int64_t)(freeb / 2) >> 18 << 18;
+    return std::max<int64_t>(kMinArena, half);
+}
 
 // Arena 0 of `bytes` (kept if already that large); arenas 1.. grow from it.
 void ensure_arena(sfe_ctx *c, int64_t bytes) {
@@ -395,16 +405,36 @@ void set_run_head(sfe_ctx *c, uint64_t h) {
     sync(c);
 }
 
-// Blocks of the fused kernel the device holds at once.
-int64_t fused_resident(sfe_ctx *c, int cells_per_lane, bool perm, bool narrow, bool persistent) {
+// Blocks (one wave each) of the persistent fused kernel a compute unit takes at
+// once, at most `wpc`: when occupancy alone allows more, each block also asks
+// for the least amount of (unused) dynamic LDS that brings it down to wpc, so
+// the grid spreads evenly -- wpc per CU, wpc / 4 per SIMD -- instead of piling
+// onto the first CUs.  Returns that amount in `dyn`.
+int persistent_per_cu(sfe_ctx *c, int C, bool perm, bool narrow, int wpc, size_t &dyn) {
     if (c->cu_count <= 0) {
         int n = 0;
         HIPCHK(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, c->device));
         c->cu_count = n;
     }
-    const int per_cu = ydrop_fused_blocks_per_cu(cells_per_lane, perm, narrow, persistent);
+    auto blocks = [&](size_t d) { return ydrop_fused_blocks_per_cu(C, perm, narrow, true, d); };
+    dyn = 0;
+    int per_cu = blocks(0);
     if (per_cu <= 0) fail(SFE_EDEVICE, "occupancy query of the extension kernel failed");
-    return (int64_t)per_cu * c->cu_count;
+    if (per_cu <= wpc) return per_cu;
+    size_t lo = 0, hi = 65536;                  // blocks(lo) > wpc
+    const int at_hi = blocks(hi);
+    if (at_hi <= 0 || at_hi > wpc) {            // cannot get that low: take what the largest request gives
+        if (at_hi > 0) { dyn = hi; per_cu = at_hi; }
+        return per_cu;
+    }
+    while (hi - lo > 256) {
+        const size_t mid = (lo + hi) / 2 / 256 * 256;
+        const int b = blocks(mid);
+        if (b > wpc || b <= 0) lo = mid;
+        else hi = mid;
+    }
+    dyn = hi;
+    return blocks(hi);
 }
 
 // Chunk pool over arena 0: chunks of 256 KB (smaller for a small arena, so
@@ -474,7 +504,7 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         for (int64_t h = 0; h < nh; h++)
             if ((*extent)[h] > std::log2((double)long_cap)) stage[h] = ST_COOP2;
     c->sched_d.ensure(64);
-    if (c->arenas.empty() || !c->arenas[0]->p) ensure_arena(c, kDefaultArena);
+    if (c->arenas.empty() || !c->arenas[0]->p) ensure_arena(c, default_arena(c));
     set_run_head(c, 0);
     RunArena ra = run_arena(c, std::max<uint64_t>(1 << 12, (uint64_t)c->arena_bytes / 256), 0);
     std::vector<int32_t> todo;
@@ -517,11 +547,19 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         Arena ar{};
         if (sg <= ST_WAVE8) {
             const int C = sg == ST_WAVE ? cells_per_lane : 8;
-            bool persistent = schedule == SFE_SCHED_PERSISTENT || lv > 0;
-            // level L > 0 (the pool ran dry at level L - 1): 4^L times fewer
-            // waves than the device holds, pulling from the queue
-            int64_t count = fused_resident(c, C, perm, narrow, persistent);
-            if (lv > 0) count = std::max<int64_t>(1, count >> std::min(62, 2 * lv));
+            const int64_t adaptive = c->tuning.adaptive_halves > 0 ? c->tuning.adaptive_halves : 131072;
+            const bool persistent = schedule == SFE_SCHED_PERSISTENT || lv > 0 ||
+                                    (schedule == SFE_SCHED_ADAPTIVE && cnt < adaptive);
+            // persistent: a few waves per SIMD (long halves then share a SIMD with at most
+            // one other wave); level L > 0 (the pool ran dry at level L - 1): 4^L times
+            // fewer, pulling from the queue
+            const int wpc = c->tuning.persist_waves_per_cu > 0 ? c->tuning.persist_waves_per_cu : 8;
+            size_t dyn = 0;
+            int64_t count = 0;
+            if (persistent) {
+                count = (int64_t)persistent_per_cu(c, C, perm, narrow, wpc, dyn) * c->cu_count;
+                if (lv > 0) count = std::max<int64_t>(1, count >> std::min(62, 2 * lv));
+            }
             ChunkPool pool = make_pool(c);
             nwaves = persistent ? count : 0;
             chunk_bytes = (uint64_t)1 << pool.shift;
@@ -530,7 +568,7 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
             WorkQueue wq{ids, cnt, qhead};
             HIPCHK(hipEventRecord(c->ev0, c->stream));
             launch_ydrop_fused(C, perm, narrow, persistent, tasks, wq, persistent ? count : cnt, T, Qp, Qm, sc, pool,
-                               ra, hres, long_cap, c->stream);
+                               ra, hres, long_cap, dyn, c->stream);
         } else if (sg <= ST_COOP4) {
             // wave groups; level L > 0: at most 256 / 4^(L-1) halves in flight
             const int C = sg == ST_COOP2 ? 2 : 4;
@@ -1087,6 +1125,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         if (opts) o = *opts;
         int strands = o.strands ? o.strands : 3;
         if (strands < 1 || strands > 3) fail(SFE_EINVAL, "strands must be 1, 2 or 3");
+        if (o.schedule < SFE_SCHED_PLAIN || o.schedule > SFE_SCHED_ADAPTIVE) fail(SFE_EINVAL, "unknown schedule");
         const int64_t K = o.round_k > 0 ? o.round_k : (o.policy == SFE_POLICY_DEFER ? (1 << 20) : 256);
         const int cpl = o.max_cells_per_lane > 0 ? std::min(8, std::max(2, o.max_cells_per_lane)) : 6;
         if (o.arena_bytes > 0) set_arena(c, std::max<int64_t>(o.arena_bytes, 2 * ARENA_PAGE));
@@ -1138,7 +1177,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         sync(c);
         // --- cost model: predicted size of every HSP's two halves ----------------------
         std::vector<float> pred;
-        const bool learned = o.model && o.schedule == SFE_SCHED_PERSISTENT && nh > 0;
+        const bool learned = o.model && o.schedule != SFE_SCHED_PLAIN && nh > 0;
         if (o.model && o.model->ctx->device != c->device) fail(SFE_EINVAL, "model lives on another device");
         if (learned) {
             const double tp = now_ms();
@@ -1180,7 +1219,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         BatchResult br;
         const bool defer = o.policy == SFE_POLICY_DEFER;
         const bool progress = getenv("SFE_PROGRESS") != nullptr;
-        const int64_t DB = o.near_band == 0 ? 64 : o.near_band;      // diagonal band of the nearness rule
+        const int64_t DB = o.near_band == 0 ? 32 : o.near_band;      // diagonal band of the nearness rule
         std::vector<std::vector<uint8_t>> doomed(NU);              // pending extensions expected to be skipped
         std::vector<std::vector<size_t>> pend_list(NU);            // positions with an extension waiting for commit
         auto anchor_of = [&](const sfe_hsp &h, uint32_t &ta, uint32_t &qa) {
@@ -1318,7 +1357,10 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 pe.second.assign(br.ops.begin() + (a.flags & SFE_ALN_PASSED ? a.ops_offset : 0),
                                  br.ops.begin() + (a.flags & SFE_ALN_PASSED ? a.ops_offset + a.ops_len : 0));
                 pe.first.ops_offset = 0;
-                if (defer && (a.flags & SFE_ALN_PASSED)) paths[u].add(pe.first, pe.second.data(), p);
+                if (defer && (a.flags & SFE_ALN_PASSED)) {
+                    paths[u].add(pe.first, pe.second.data(), p);
+                    boxes[u].add(pe.first);
+                }
                 if (defer) pend_list[u].push_back(p);
                 state[u][p] = 2;
             }
@@ -1341,7 +1383,6 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                             k.ops_offset = cops.size();
                             cops.insert(cops.end(), it->second.second.begin(), it->second.second.end());
                             seg[u].add(k, cops.data() + k.ops_offset);
-                            if (defer) boxes[u].add(k);
                             committed.push_back(k);
                         }
                         pending[u].erase(it);
@@ -1410,7 +1451,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
 
 sfe_status sfe_ctx_set_tuning(sfe_ctx *c, const sfe_tuning *t) {
     if (!c || !t || t->wave_group_cap < 0 || t->use_graphs < 0 || t->use_graphs > 1 || t->wide_scores < 0 ||
-        t->wide_scores > 1)
+        t->wide_scores > 1 || t->persist_waves_per_cu < 0 || t->persist_waves_per_cu > 64 || t->adaptive_halves < 0)
         return SFE_EINVAL;
     c->tuning = *t;
     return SFE_OK;
@@ -1431,11 +1472,11 @@ sfe_status sfe_autotune(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries,
     int32_t best_cap = saved.wave_group_cap;
     std::vector<sfe_aln> out(1 << 16);
     std::vector<uint32_t> ops(1 << 22);
-    const int cpls[3] = {4, 6, 8};
+    const int cpls[2] = {6, 8};
     const int caps[2] = {0, 8192};
     bool first = true;
     for (int cap : caps)
-        for (int sched = 0; sched < 2; sched++)
+        for (int sched = SFE_SCHED_PLAIN; sched <= SFE_SCHED_ADAPTIVE; sched++)
             for (int cpl : cpls) {
                 sfe_align_opts o = *opts;
                 o.max_cells_per_lane = cpl;

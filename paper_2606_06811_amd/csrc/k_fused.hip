@@ -1412,11 +1412,11 @@ void launch_ydrop_coop(int cells_per_lane, bool perm, const HalfTask *tasks, con
 
 void launch_ydrop_fused(int cells_per_lane, bool perm, bool narrow, bool persistent, const HalfTask *tasks,
                         WorkQueue wq, int64_t grid, SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc,
-                        ChunkPool pool, RunArena ra, HalfResult *res, int kcap, hipStream_t st) {
+                        ChunkPool pool, RunArena ra, HalfResult *res, int kcap, size_t dyn_lds, hipStream_t st) {
     if (grid <= 0) return;
     if (narrow) {
 #define SFE_LAUNCH16(CC, QQ) \
-    k_ydrop_fused16<CC, QQ><<<(unsigned)grid, 64, 0, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res, kcap)
+    k_ydrop_fused16<CC, QQ><<<(unsigned)grid, 64, dyn_lds, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res, kcap)
 #define SFE_BY_C16(QQ)                                    \
     do {                                                  \
         if (cells_per_lane <= 2) SFE_LAUNCH16(2, QQ);     \
@@ -1430,7 +1430,7 @@ void launch_ydrop_fused(int cells_per_lane, bool perm, bool narrow, bool persist
         return;
     }
 #define SFE_LAUNCH(CC, PP, QQ) \
-    k_ydrop_fused<CC, PP, QQ><<<(unsigned)grid, 64, 0, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res, kcap)
+    k_ydrop_fused<CC, PP, QQ><<<(unsigned)grid, 64, dyn_lds, st>>>(tasks, wq, T, Qp, Qm, sc, pool, ra, res, kcap)
 #define SFE_BY_C(PP, QQ)                                  \
     do {                                                  \
         if (cells_per_lane <= 2) SFE_LAUNCH(2, PP, QQ);   \
@@ -1448,11 +1448,11 @@ void launch_ydrop_fused(int cells_per_lane, bool perm, bool narrow, bool persist
 #undef SFE_LAUNCH
 }
 
-int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool narrow, bool persistent) {
+int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool narrow, bool persistent, size_t dyn_lds) {
     int nb = 0;
     hipError_t err = hipSuccess;
     if (narrow) {
-#define SFE_OCC16(CC, QQ) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ydrop_fused16<CC, QQ>, 64, 0)
+#define SFE_OCC16(CC, QQ) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ydrop_fused16<CC, QQ>, 64, dyn_lds)
 #define SFE_OCC_C16(QQ)                                   \
     do {                                                  \
         if (cells_per_lane <= 2) SFE_OCC16(2, QQ);        \
@@ -1465,7 +1465,7 @@ int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool narrow, bool p
 #undef SFE_OCC16
         return err == hipSuccess ? nb : -1;
     }
-#define SFE_OCC(CC, PP, QQ) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ydrop_fused<CC, PP, QQ>, 64, 0)
+#define SFE_OCC(CC, PP, QQ) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ydrop_fused<CC, PP, QQ>, 64, dyn_lds)
 #define SFE_OCC_C(PP, QQ)                                 \
     do {                                                  \
         if (cells_per_lane <= 2) SFE_OCC(2, PP, QQ);      \

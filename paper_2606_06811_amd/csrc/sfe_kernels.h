@@ -68,15 +68,17 @@ void launch_make_tasks(const ExtItem *items, int64_t n, const UnitDesc *units, i
 // kcap > 0: a half still running at antidiagonal kcap stops with HALF_LONG
 // narrow: the packed 16-bit kernel (perm scores, Y-drop range checked by the
 // caller; cells_per_lane rounds up to an even count)
+// dyn_lds: dynamic LDS requested per block and left unused -- it caps how many
+// blocks (waves) a compute unit takes, so a persistent grid spreads evenly
 void launch_ydrop_fused(int cells_per_lane, bool perm, bool narrow, bool persistent, const HalfTask *tasks,
                         WorkQueue wq, int64_t grid, SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc,
-                        ChunkPool pool, RunArena ra, HalfResult *res, int kcap, hipStream_t st);
+                        ChunkPool pool, RunArena ra, HalfResult *res, int kcap, size_t dyn_lds, hipStream_t st);
 // A group of 4 waves per half (wave-group window of 256 * cells_per_lane rows,
 // cells_per_lane 2 or 4), one block per half ids[0 .. n).
 void launch_ydrop_coop(int cells_per_lane, bool perm, const HalfTask *tasks, const int32_t *ids, int64_t n,
                        SeqSetView T, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, ChunkPool pool, RunArena ra,
                        HalfResult *res, hipStream_t st);
-int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool narrow, bool persistent);
+int ydrop_fused_blocks_per_cu(int cells_per_lane, bool perm, bool narrow, bool persistent, size_t dyn_lds);
 void launch_ydrop_ring(const HalfTask *tasks, const int32_t *ids, int64_t n, SeqSetView T, SeqSetView Qp,
                        SeqSetView Qm, const ScoreDesc &sc, Arena arena, int32_t *ring, int32_t cap_rows,
                        HalfResult *res, hipStream_t st);

@@ -19,7 +19,7 @@ _lib = None
 SFE_OK, SFE_EINVAL, SFE_ENOMEM, SFE_ECAPACITY, SFE_ERANGE, SFE_EDEVICE, SFE_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 SFE_XDROP_RAW = 1
 SFE_ALN_PASSED = 1
-SFE_SCHED_PLAIN, SFE_SCHED_PERSISTENT = 0, 1
+SFE_SCHED_PLAIN, SFE_SCHED_PERSISTENT, SFE_SCHED_ADAPTIVE = 0, 1, 2
 SFE_POLICY_DEFER, SFE_POLICY_PREFIX = 0, 1
 
 HIT_DTYPE = np.dtype([("t", "<u4"), ("q", "<u4"), ("query_id", "<u4"), ("strand", "u1"), ("pad", "u1", (3,))])
@@ -60,7 +60,8 @@ class _AlignOpts(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("wave_group_cap", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("wide_scores", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("persist_waves_per_cu", ctypes.c_int32), ("adaptive_halves", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class _TuneEntry(ctypes.Structure):
@@ -213,18 +214,22 @@ def sfe_ctx_create(device: int = 0, stream=None) -> Context:
     return Context(device, stream)
 
 
-def sfe_ctx_set_tuning(ctx: Context, wave_group_cap: int = 0, use_graphs: int = 0, wide_scores: int = 0):
+def sfe_ctx_set_tuning(ctx: Context, wave_group_cap: int = 0, use_graphs: int = 0, wide_scores: int = 0,
+                       persist_waves_per_cu: int = 0, adaptive_halves: int = 0):
     t = _Tuning()
     t.wave_group_cap = int(wave_group_cap)
     t.use_graphs = int(use_graphs)
     t.wide_scores = int(wide_scores)
+    t.persist_waves_per_cu = int(persist_waves_per_cu)
+    t.adaptive_halves = int(adaptive_halves)
     _check(lib().sfe_ctx_set_tuning(ctx.ptr, ctypes.byref(t)), ctx)
 
 
 def sfe_ctx_get_tuning(ctx: Context) -> dict:
     t = _Tuning()
     _check(lib().sfe_ctx_get_tuning(ctx.ptr, ctypes.byref(t)), ctx)
-    return {"wave_group_cap": t.wave_group_cap, "use_graphs": t.use_graphs, "wide_scores": t.wide_scores}
+    return {"wave_group_cap": t.wave_group_cap, "use_graphs": t.use_graphs, "wide_scores": t.wide_scores,
+            "persist_waves_per_cu": t.persist_waves_per_cu, "adaptive_halves": t.adaptive_halves}
 
 
 def sfe_autotune(ctx: Context, idx: Index, queries, scoring: dict, sample_bases: int, model=None,

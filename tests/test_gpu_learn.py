@@ -185,6 +185,15 @@ def test_learned_schedule_is_bit_exact(ctx, case):
     assert np.array_equal(o0, o1)
     assert s1["predicted_halves"] == 2 * s1["extensions"] > 0
     assert 0 <= s1["mispredicted_halves"] <= s1["predicted_halves"]
+    # adaptive: plain launches for large batches, persistent below the threshold (here: every batch
+    # of more than 64 halves goes plain)
+    sfe.sfe_ctx_set_tuning(ctx, adaptive_halves=64, persist_waves_per_cu=2)
+    try:
+        a2, o2, s2 = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), schedule=sfe.SFE_SCHED_ADAPTIVE, model=m)
+    finally:
+        sfe.sfe_ctx_set_tuning(ctx)
+    assert np.array_equal(a0, a2) and np.array_equal(o0, o2)
+    assert s2["predicted_halves"] == 2 * s2["extensions"]
     ref = oracle.pipeline(T, Q, dict(synth.SCORING))
     assert a1.shape[0] == ref["alns"].shape[0]
     assert np.array_equal(a1["score"].astype(np.int64), ref["alns"]["score"])
@@ -243,7 +252,7 @@ def test_autotune_picks_a_schedule_and_keeps_results(ctx, case):
     chosen, entries = sfe.sfe_autotune(ctx, idx, Q, dict(synth.SCORING), sample_bases=20_000, model=m)
     log(f"autotune: chosen {chosen}; {len(entries)} candidates")
     assert len(entries) == 12
-    assert chosen["max_cells_per_lane"] in (4, 6, 8) and chosen["schedule"] in (0, 1)
+    assert chosen["max_cells_per_lane"] in (6, 8) and chosen["schedule"] in (0, 1, 2)
     best = min(entries, key=lambda e: e["ms_extend"])
     assert (best["cells_per_lane"], best["schedule"], best["wave_group_cap"]) == (
         chosen["max_cells_per_lane"], chosen["schedule"], chosen["wave_group_cap"])

@@ -114,6 +114,17 @@ def test_bad_inputs_return_errors(ctx):
         sfe.sfe_build_index(ctx, good, "0110")
     with pytest.raises(sfe.SfeError):
         sfe.sfe_build_index(ctx, good, "1" * 15)
+    idx = sfe.sfe_build_index(ctx, good)
+    with pytest.raises(sfe.SfeError) as e:
+        sfe.sfe_align(ctx, idx, [good], dict(synth.SCORING), schedule=3)
+    assert e.value.status == sfe.SFE_EINVAL
+    for bad in (dict(persist_waves_per_cu=-1), dict(persist_waves_per_cu=65), dict(adaptive_halves=-2)):
+        with pytest.raises(sfe.SfeError):
+            sfe.sfe_ctx_set_tuning(ctx, **bad)
+    sfe.sfe_ctx_set_tuning(ctx, persist_waves_per_cu=4, adaptive_halves=1000)
+    assert sfe.sfe_ctx_get_tuning(ctx)["persist_waves_per_cu"] == 4
+    sfe.sfe_ctx_set_tuning(ctx)
+    idx.close()
 
 
 # ---------------------------------------------------------------------------
@@ -285,13 +296,14 @@ def compare_alignments(alns, ops, ref):
         assert np.array_equal(g, oracle.aln_ops(ref, x)), x
 
 
-PLAIN, PERSIST = sfe.SFE_SCHED_PLAIN, sfe.SFE_SCHED_PERSISTENT
+PLAIN, PERSIST, ADAPT = sfe.SFE_SCHED_PLAIN, sfe.SFE_SCHED_PERSISTENT, sfe.SFE_SCHED_ADAPTIVE
 
 
 @pytest.mark.parametrize("K,cpl,policy,schedule", [
     (1, 0, 1, PLAIN), (7, 0, 1, PLAIN), (64, 0, 1, PLAIN), (1000, 0, 1, PLAIN), (64, 4, 1, PLAIN), (64, 8, 1, PLAIN),
     (1, 0, 0, PLAIN), (3, 0, 0, PLAIN), (0, 0, 0, PLAIN), (0, 4, 0, PLAIN),
-    (1, 0, 1, PERSIST), (64, 0, 1, PERSIST), (0, 0, 0, PERSIST), (0, 8, 0, PERSIST)])
+    (1, 0, 1, PERSIST), (64, 0, 1, PERSIST), (0, 0, 0, PERSIST), (0, 8, 0, PERSIST),
+    (0, 0, 0, ADAPT), (7, 0, 1, ADAPT)])
 def test_align_parity(ctx, align_case, K, cpl, policy, schedule):
     log(f"align parity K={K} cells_per_lane={cpl} policy={policy} schedule={schedule}")
     T, Q, ref = align_case
