@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                 bwb = bcode(bw0 + 64 + lane);
             }
             const int d = pos - bw0;
-            return d < 64 ? __builtin_amdgcn_readlane(bwa, d) : __builtin_amdgcn_readlane(bwb, d - 64);
+            return __builtin_amdgcn_readlane(d < 64 ? bwa : bwb, d & 63);
         };
 
         int H1[C], H2[C], E1[C], F1[C], Plo[C], Phi[C], Bs[C];
@@ -395,9 +395,8 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
         }
         int k = 1;
         const int klong = kcap > 0 ? kcap : 0x7fffffff;
-        for (; status == HALF_OK && k <= kmax32; k++) {
-            if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
-            if (k > klong) { status = HALF_LONG; break; }
+        const int kend = min(kmax32, min(klong, ROW_LIMIT - 1));
+        for (; status == HALF_OK && k <= kend; k++) {
             int lo = 0x7fffffff, hi = -1;
             if (lmin1 <= lmax1) { lo = lmin1; hi = lmax1 + 1; }
             if (lmin2 <= lmax2) { lo = min(lo, lmin2 + 1); hi = max(hi, lmax2 + 1); }
@@ -406,8 +405,8 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
             lo = max(lo, clo);
             hi = min(hi, chi);
             const bool nonempty = lo <= hi;
-            if (nonempty) {
-                const int s = (lo - 1 - base) / C;
+            {
+                const int s = nonempty ? (lo - 1 - base) / C : 0;
                 if (s >= 1) {
                     while (a_hi < base + (s + 64) * C + 64) {
                         ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane);
@@ -450,7 +449,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                     }
                     base += s * C;
                 }
-                if (hi > base + 64 * C - 1) { status = HALF_WIDTH_OVERFLOW; break; }
+                if (nonempty && hi > base + 64 * C - 1) { status = HALF_WIDTH_OVERFLOW; break; }
             }
             const int thr = best - Y;
             const int upH = dpp_shr1(NEG, H1[C - 1]);
@@ -496,16 +495,15 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
             else cell_pass(std::false_type());
             // live rows of the antidiagonal: first and last lane with a live row, then
             // that lane's first / last live row
-            int lmin0 = 1, lmax0 = 0;
+            int lmin0, lmax0;
             {
+                // branch-free: with no live row m is 0 and the selects give the empty range
                 const uint64_t m = __ballot(lmask != 0);
-                if (m) {
-                    const int L1 = __builtin_ctzll(m), L2 = 63 - __builtin_clzll(m);
-                    const uint32_t f1 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L1);
-                    const uint32_t f2 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L2);
-                    lmin0 = base + L1 * C + __builtin_ctz(f1);
-                    lmax0 = base + L2 * C + (31 - __builtin_clz(f2));
-                }
+                const int L1 = __builtin_ctzll(m | (1ull << 63)), L2 = 63 - __builtin_clzll(m | 1ull);
+                const uint32_t f1 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L1);
+                const uint32_t f2 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L2);
+                lmin0 = m ? base + L1 * C + __builtin_ctz(f1 | 0x80000000u) : 1;
+                lmax0 = m ? base + L2 * C + (31 - __builtin_clz(f2 | 1u)) : 0;
             }
             // record of antidiagonal k: rows of the lanes covering [lo, hi]
             {
@@ -530,13 +528,15 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
                     k0 = k;
                     fill = 16;
                 }
+                // unconditional stores: lanes outside the record write the chunk header's
+                // spare word, and every lane writes the same index entry
                 uint32_t *rec = (uint32_t *)(cb + fill);
-                if (lane >= l_lo && lane <= l_hi) rec[lane - l_lo] = nib;
-                if (lane == 0)
-                    *(uint2 *)(cb + CH - 8u * (uint32_t)(k - k0 + 1)) =
-                        make_uint2(fill, nonempty ? (uint32_t)(base + l_lo * C) : 0u);
+                const bool mine = lane >= l_lo && lane <= l_hi;
+                *(mine ? rec + (lane - l_lo) : (uint32_t *)(cb + 12)) = nib;
+                *(uint2 *)(cb + CH - 8u * (uint32_t)(k - k0 + 1)) =
+                    make_uint2(fill, nonempty ? (uint32_t)(base + l_lo * C) : 0u);
                 fill += need;
-                if (nonempty) cells += (uint64_t)(hi - lo + 1);
+                cells += nonempty ? (uint64_t)(hi - lo + 1) : 0u;
             }
             // best: only when some live cell beats it; then the first row reaching the new maximum
             if (__ballot(lmax > best)) {
@@ -571,6 +571,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
             if (stop) break;
         }
 
+        if (status == HALF_OK && k > kend && k <= kmax32) status = k >= ROW_LIMIT ? HALF_SCORE_RANGE : HALF_LONG;
         if (cur >= 0 && lane == 0) ((uint32_t *)cb)[2] = fill;
 
         uint64_t run_off = 0;
@@ -701,7 +702,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
                 bwb = bcode(bw0 + 64 + lane);
             }
             const int d = pos - bw0;
-            return d < 64 ? __builtin_amdgcn_readlane(bwa, d) : __builtin_amdgcn_readlane(bwb, d - 64);
+            return __builtin_amdgcn_readlane(d < 64 ? bwa : bwb, d & 63);
         };
         auto sel_row = [&](int r, int code) { return r < P ? sel_lo(code) : sel_hi(code); };
 
@@ -744,9 +745,8 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
         }
         int k = 1;
         const int klong = kcap > 0 ? kcap : 0x7fffffff;
-        for (; status == HALF_OK && k <= kmax32; k++) {
-            if (k >= ROW_LIMIT) { status = HALF_SCORE_RANGE; break; }
-            if (k > klong) { status = HALF_LONG; break; }
+        const int kend = min(kmax32, min(klong, ROW_LIMIT - 1));
+        for (; status == HALF_OK && k <= kend; k++) {
             int lo = 0x7fffffff, hi = -1;
             if (lmin1 <= lmax1) { lo = lmin1; hi = lmax1 + 1; }
             if (lmin2 <= lmax2) { lo = min(lo, lmin2 + 1); hi = max(hi, lmax2 + 1); }
@@ -755,8 +755,8 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
             lo = max(lo, clo);
             hi = min(hi, chi);
             const bool nonempty = lo <= hi;
-            if (nonempty) {
-                const int s = (lo - 1 - base) / C;
+            {
+                const int s = nonempty ? (lo - 1 - base) / C : 0;
                 if (s >= 1) {
                     while (a_hi < base + (s + 64) * C + 64) {
                         ring_fill(aring, T, tk.a0, tk.adir, nA, a_hi, lane);
@@ -804,7 +804,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
                     }
                     base += s * C;
                 }
-                if (hi > base + 64 * C - 1) { status = HALF_WIDTH_OVERFLOW; break; }
+                if (nonempty && hi > base + 64 * C - 1) { status = HALF_WIDTH_OVERFLOW; break; }
             }
             const int oeD = pk2(oe + d1), eD = pk2(e + d1), gD = pk2(128 + d1 + d2);
             const int upH = (int)__builtin_amdgcn_alignbit((uint32_t)H1[P - 1], (uint32_t)dpp_shr1(NEG2, H1[P - 1]), 16);
@@ -858,18 +858,17 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
 #pragma unroll
             for (int p = 0; p < P; p++) dead |= ((uint32_t)Hn[p] >> (15 - p)) & (0x00010001u << p);
             const uint32_t lmask = ~dead & (((1u << P) - 1u) * 0x10001u);
-            int lmin0 = 1, lmax0 = 0;
+            int lmin0, lmax0;
             {
+                // branch-free: with no live row m is 0 and the selects give the empty range
                 const uint64_t m = __ballot(lmask != 0);
-                if (m) {
-                    const int L1 = __builtin_ctzll(m), L2 = 63 - __builtin_clzll(m);
-                    const uint32_t f1 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L1);
-                    const uint32_t f2 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L2);
-                    const int r1 = (f1 & 0xffffu) ? __builtin_ctz(f1 & 0xffffu) : P + __builtin_ctz(f1 >> 16);
-                    const int r2 = (f2 >> 16) ? P + (31 - __builtin_clz(f2 >> 16)) : 31 - __builtin_clz(f2 & 0xffffu);
-                    lmin0 = base + L1 * C + r1;
-                    lmax0 = base + L2 * C + r2;
-                }
+                const int L1 = __builtin_ctzll(m | (1ull << 63)), L2 = 63 - __builtin_clzll(m | 1ull);
+                const uint32_t f1 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L1);
+                const uint32_t f2 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L2);
+                const int r1 = (f1 & 0xffffu) ? __builtin_ctz(f1 | 0x80000000u) : P + __builtin_ctz((f1 >> 16) | 0x8000u);
+                const int r2 = (f2 >> 16) ? P + (31 - __builtin_clz(f2 >> 16)) : 31 - __builtin_clz((f2 & 0xffffu) | 1u);
+                lmin0 = m ? base + L1 * C + r1 : 1;
+                lmax0 = m ? base + L2 * C + r2 : 0;
             }
             {
                 int l_lo = 0, l_hi = -1;
@@ -893,13 +892,15 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
                     k0 = k;
                     fill = 16;
                 }
+                // unconditional stores: lanes outside the record write the chunk header's
+                // spare word, and every lane writes the same index entry
                 uint32_t *rec = (uint32_t *)(cb + fill);
-                if (lane >= l_lo && lane <= l_hi) rec[lane - l_lo] = nib;
-                if (lane == 0)
-                    *(uint2 *)(cb + CH - 8u * (uint32_t)(k - k0 + 1)) =
-                        make_uint2(fill, nonempty ? (uint32_t)(base + l_lo * C) : 0u);
+                const bool mine = lane >= l_lo && lane <= l_hi;
+                *(mine ? rec + (lane - l_lo) : (uint32_t *)(cb + 12)) = nib;
+                *(uint2 *)(cb + CH - 8u * (uint32_t)(k - k0 + 1)) =
+                    make_uint2(fill, nonempty ? (uint32_t)(base + l_lo * C) : 0u);
                 fill += need;
-                if (nonempty) cells += (uint64_t)(hi - lo + 1);
+                cells += nonempty ? (uint64_t)(hi - lo + 1) : 0u;
             }
             // best: a live value above Y (relative to t_k) beats it; then the first row reaching the maximum
             int mx = Hn[0];
@@ -949,6 +950,7 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
             if (stop) break;
         }
 
+        if (status == HALF_OK && k > kend && k <= kmax32) status = k >= ROW_LIMIT ? HALF_SCORE_RANGE : HALF_LONG;
         if (cur >= 0 && lane == 0) ((uint32_t *)cb)[2] = fill;
 
         uint64_t run_off = 0;

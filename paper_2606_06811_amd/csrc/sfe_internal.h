@@ -106,10 +106,12 @@ struct HalfResult {
 // bit c of bits[] set while chunk c is held by a half.  A half keeps its
 // traceback codes in a backward-linked chain of chunks, each laid out as
 //   header (16 bytes): u32 previous chunk of the chain (~0 for the first),
-//     u32 k0 = antidiagonal of its first record, u32 bytes of records used;
+//     u32 k0 = antidiagonal of its first record, u32 bytes of records used,
+//     u32 scratch (the extension kernels' lanes outside a record store there);
 //   records upward from offset 16, one per antidiagonal: one u32 of 4-bit
 //     codes per lane group of G rows covering the computed range (row
-//     r0 + w*G + x in bits 4x .. 4x+3 of word w);
+//     r0 + w*G + x in bits 4x .. 4x+3 of word w; the 16-bit kernel's layout
+//     is described with its decoder);
 //   index downward from the end: the uint2 at 2^shift - 8*(x+1) holds
 //     (offset of the record of antidiagonal k0 + x, its first row r0).
 // Code bits as in the arena above.  Edit runs being traced go to a second
