@@ -838,13 +838,15 @@ struct PathSet {
         paths.push_back(P);
         for (uint32_t b = a.t_start >> SH; b <= (a.t_end - 1) >> SH; b++) bins[b].push_back(id);
     }
-    template <class Ok>
-    bool contains(uint32_t t, uint32_t q, Ok ok) const {
+    // (t, q) on an M column of a path whose owner passes `pre` (cheap, tested before the
+    // search) and then `post` (tested only on a match)
+    template <class Pre, class Post>
+    bool contains(uint32_t t, uint32_t q, Pre pre, Post post) const {
         auto it = bins.find(t >> SH);
         if (it == bins.end()) return false;
         for (uint32_t id : it->second) {
             const Path &P = paths[id];
-            if (t < P.t0 || t >= P.t1 || q < P.q0 || q >= P.q1 || !ok(P.owner)) continue;
+            if (t < P.t0 || t >= P.t1 || q < P.q0 || q >= P.q1 || !pre(P.owner)) continue;
             // last run starting at or before t
             size_t lo = P.first, hi = P.first + P.count;
             while (hi - lo > 1) {
@@ -853,7 +855,7 @@ struct PathSet {
                 else hi = mid;
             }
             if (rt[lo] <= t && t < rt[lo] + rl[lo] &&
-                (int64_t)t - (int64_t)q - ((int64_t)P.t0 - (int64_t)P.q0) == (int64_t)rd[lo])
+                (int64_t)t - (int64_t)q - ((int64_t)P.t0 - (int64_t)P.q0) == (int64_t)rd[lo] && post(P.owner))
                 return true;
         }
         return false;
@@ -862,22 +864,16 @@ struct PathSet {
 
 // M runs of computed extensions of one unit, each tagged with the position of
 // its HSP in the walking order.
-struct PathIndex {
+// Every passing extension's M runs of one (query, strand) unit, owner = its
+// position in the walking order; committed ones are flagged in `committed`.
+// Alg. 1's containment test reads the committed ones; the deferral rule reads
+// the ones still waiting for commit.
+struct UnitPaths {
     PathSet set;
-    void add(const sfe_aln &a, const uint32_t *ops, size_t owner) { set.add(a, ops, owner); }
-    // (t, q) lies on an M column of an extension, still waiting for commit
-    // (state[owner] == 2) and not marked in `doomed`, whose HSP comes before `pos`
-    bool contains_before(uint32_t t, uint32_t q, size_t pos, const std::vector<uint8_t> &state,
-                         const std::vector<uint8_t> &doomed) const {
-        return set.contains(t, q, [&](size_t o) { return o < pos && state[o] == 2 && !doomed[o]; });
+    std::vector<uint8_t> committed;
+    bool in_committed(uint32_t t, uint32_t q) const {
+        return set.contains(t, q, [&](size_t o) { return committed[o] != 0; }, [](size_t) { return true; });
     }
-};
-
-// Committed M columns of one (query, strand) unit.
-struct SegList {
-    PathSet set;
-    bool contains(uint32_t t, uint32_t q) const { return set.contains(t, q, [](size_t) { return true; }); }
-    void add(const sfe_aln &a, const uint32_t *ops) { set.add(a, ops, 0); }
 };
 
 sfe_status guard(sfe_ctx *c, const std::function<void()> &f) {
@@ -1201,17 +1197,30 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         for (int64_t x = 0; x < nh; x++) per_unit[unit_of[2 * hs[x].query_id + hs[x].strand]].push_back(x);
         // per HSP state: 0 unresolved, 1 skipped (contained), 2 extension pending, 3 resolved, 4 in this batch
         std::vector<std::vector<uint8_t>> state(NU);
-        std::vector<std::unordered_map<size_t, std::pair<sfe_aln, std::vector<uint32_t>>>> pending(NU);
+        // extension of each position once computed: alignment, batch whose edit runs hold its ops
+        std::vector<std::vector<sfe_aln>> ext(NU);
+        std::vector<std::vector<uint32_t>> ext_batch(NU);
+        std::vector<std::vector<uint32_t>> batch_ops;          // edit runs of every batch so far
         std::vector<std::vector<size_t>> open(NU);               // positions in state 0, ascending
+        std::vector<UnitPaths> paths(NU);
+        // deferral rule: a waiting extension is "doomed" when it will most likely be skipped at
+        // commit (memo per scan: stamp, value; `perm` = its anchor lies in a committed alignment)
+        std::vector<std::vector<uint32_t>> doom_stamp(NU);
+        std::vector<std::vector<uint8_t>> doom_val(NU), doom_perm(NU);
         for (size_t u = 0; u < NU; u++) {
-            state[u].assign(per_unit[u].size(), 0);
-            open[u].resize(per_unit[u].size());
-            for (size_t p = 0; p < per_unit[u].size(); p++) open[u][p] = p;
+            const size_t n = per_unit[u].size();
+            state[u].assign(n, 0);
+            open[u].resize(n);
+            for (size_t p = 0; p < n; p++) open[u][p] = p;
+            ext[u].resize(n);
+            ext_batch[u].assign(n, 0);
+            paths[u].committed.assign(n, 0);
+            doom_stamp[u].assign(n, 0);
+            doom_val[u].assign(n, 0);
+            doom_perm[u].assign(n, 0);
         }
         std::vector<size_t> cursor(NU, 0);
-        std::vector<SegList> seg(NU);
         std::vector<BoxGrid> boxes(NU);
-        std::vector<PathIndex> paths(NU);                        // M runs of every passing extension computed
         std::vector<sfe_aln> committed;
         std::vector<uint32_t> cops;
         std::vector<ExtItem> items;
@@ -1220,8 +1229,28 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         const bool defer = o.policy == SFE_POLICY_DEFER;
         const bool progress = getenv("SFE_PROGRESS") != nullptr;
         const int64_t DB = o.near_band == 0 ? 32 : o.near_band;      // diagonal band of the nearness rule
-        std::vector<std::vector<uint8_t>> doomed(NU);              // pending extensions expected to be skipped
-        std::vector<std::vector<size_t>> pend_list(NU);            // positions with an extension waiting for commit
+        uint32_t scan_no = 0;
+        // doomed: the anchor of waiting extension p lies in a committed alignment, or on the
+        // path of an earlier waiting extension that is not itself doomed (depth-capped; the
+        // rule only steers scheduling, never results)
+        std::function<bool(size_t, size_t, int)> doomed = [&](size_t u, size_t p, int depth) -> bool {
+            if (doom_perm[u][p]) return true;
+            if (doom_stamp[u][p] == scan_no) return doom_val[u][p] != 0;
+            doom_stamp[u][p] = scan_no;
+            doom_val[u][p] = 0;
+            const sfe_aln &a = ext[u][p];
+            const auto &stt = state[u];
+            bool d = false;
+            if (paths[u].in_committed(a.anchor_t, a.anchor_q)) {
+                doom_perm[u][p] = 1;
+                d = true;
+            } else if (depth < 64) {
+                d = paths[u].set.contains(a.anchor_t, a.anchor_q, [&](size_t o) { return o < p && stt[o] == 2; },
+                                          [&](size_t o) { return !doomed(u, o, depth + 1); });
+            }
+            doom_val[u][p] = d ? 1 : 0;
+            return d;
+        };
         auto anchor_of = [&](const sfe_hsp &h, uint32_t &ta, uint32_t &qa) {
             uint32_t off = (h.len - 1) / 2;
             ta = h.t0 + off;
@@ -1234,28 +1263,10 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             const double th = now_ms();
             items.clear();
             item_ref.clear();
+            scan_no++;
             for (size_t u = 0; u < NU; u++) {                      // phase 1: serial scan per unit
                 auto &lst = per_unit[u];
                 auto &stt = state[u];
-                if (defer) {
-                    // a pending extension whose anchor already lies in a committed alignment, or on
-                    // the path of an earlier pending one that is not itself doomed, will most likely
-                    // be skipped at commit: its path does not hold back later HSPs
-                    // (2: anchor in a committed alignment, which stays so; 1: on a waiting path)
-                    auto &dm = doomed[u];
-                    if (dm.size() != lst.size()) dm.assign(lst.size(), 0);
-                    auto &pend = pend_list[u];
-                    pend.erase(std::remove_if(pend.begin(), pend.end(), [&](size_t p) { return stt[p] != 2; }),
-                               pend.end());
-                    std::sort(pend.begin(), pend.end());
-                    for (size_t p : pend) {
-                        if (dm[p] == 2) continue;
-                        const sfe_aln &a = pending[u][p].first;
-                        dm[p] = seg[u].contains(a.anchor_t, a.anchor_q)                              ? 2
-                                : paths[u].contains_before(a.anchor_t, a.anchor_q, p, stt, dm) ? 1
-                                                                                               : 0;
-                    }
-                }
                 int64_t taken = 0;
                 std::unordered_map<int64_t, std::vector<int64_t>> near;   // diagonal bucket -> selected diagonals
                 std::vector<size_t> still;
@@ -1266,10 +1277,11 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     if (stt[p] != 0) continue;
                     uint32_t ta, qa;
                     anchor_of(hs[lst[p]], ta, qa);
-                    if (seg[u].contains(ta, qa)) { stt[p] = 1; continue; }
+                    if (paths[u].in_committed(ta, qa)) { stt[p] = 1; continue; }
                     if (defer) {
                         // on the path of an earlier extension that may still commit: wait for it
-                        if (paths[u].contains_before(ta, qa, p, stt, doomed[u])) {
+                        if (paths[u].set.contains(ta, qa, [&](size_t o) { return o < p && stt[o] == 2; },
+                                                  [&](size_t o) { return !doomed(u, o, 0); })) {
                             if (progress) why[u][p] += 1;
                             still.push_back(p);
                             continue;
@@ -1277,7 +1289,6 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                         // inside a committed alignment but off its path: such HSPs are extended
                         // side by side (each may start a separate alignment of the region)
                         if (DB > 0) {
-                            const bool known_region = boxes[u].inside(ta, qa);
                             const int64_t d = (int64_t)ta - (int64_t)qa;
                             const int64_t b = d >= 0 ? d / DB : -((-d + DB - 1) / DB);
                             bool close = false;
@@ -1287,7 +1298,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                                 for (int64_t dd : it->second)
                                     if (std::llabs(dd - d) <= DB) { close = true; break; }
                             }
-                            if (close && !known_region) {                                  // likely the same region
+                            if (close && !boxes[u].inside(ta, qa)) {                      // likely the same region
                                 if (progress) why[u][p] += 256;
                                 still.push_back(p);
                                 continue;
@@ -1347,21 +1358,21 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             const double th2 = now_ms();
             st.overflow_reruns += br.reruns;
             st.extensions += (int64_t)items.size();
+            const uint32_t bno = (uint32_t)batch_ops.size();
+            batch_ops.push_back(std::move(br.ops));
+            br.ops = std::vector<uint32_t>();
+            const uint32_t *bops = batch_ops.back().data();
             for (size_t x = 0; x < items.size(); x++) {
                 const sfe_aln &a = br.alns[x];
                 const int32_t u = item_ref[x].first;
                 const size_t p = item_ref[x].second;
                 st.cells += (int64_t)a.cells;
-                auto &pe = pending[u][p];
-                pe.first = a;
-                pe.second.assign(br.ops.begin() + (a.flags & SFE_ALN_PASSED ? a.ops_offset : 0),
-                                 br.ops.begin() + (a.flags & SFE_ALN_PASSED ? a.ops_offset + a.ops_len : 0));
-                pe.first.ops_offset = 0;
-                if (defer && (a.flags & SFE_ALN_PASSED)) {
-                    paths[u].add(pe.first, pe.second.data(), p);
-                    boxes[u].add(pe.first);
+                ext[u][p] = a;
+                ext_batch[u][p] = bno;
+                if (a.flags & SFE_ALN_PASSED) {
+                    paths[u].set.add(a, bops + a.ops_offset, p);
+                    if (defer) boxes[u].add(a);
                 }
-                if (defer) pend_list[u].push_back(p);
                 state[u][p] = 2;
             }
             const double th3 = now_ms();
@@ -1374,25 +1385,24 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     const size_t p = cur;
                     if (stt[p] == 1 || stt[p] == 3) { cur++; continue; }
                     if (stt[p] == 2) {
-                        auto it = pending[u].find(p);
-                        const sfe_aln &a = it->second.first;
-                        if (seg[u].contains(a.anchor_t, a.anchor_q)) {
+                        const sfe_aln &a = ext[u][p];
+                        if (paths[u].in_committed(a.anchor_t, a.anchor_q)) {
                             st.shadow++;
                         } else if (a.flags & SFE_ALN_PASSED) {
                             sfe_aln k = a;
                             k.ops_offset = cops.size();
-                            cops.insert(cops.end(), it->second.second.begin(), it->second.second.end());
-                            seg[u].add(k, cops.data() + k.ops_offset);
+                            const uint32_t *src = batch_ops[ext_batch[u][p]].data() + a.ops_offset;
+                            cops.insert(cops.end(), src, src + a.ops_len);
+                            paths[u].committed[p] = 1;
                             committed.push_back(k);
                         }
-                        pending[u].erase(it);
                         stt[p] = 3;
                         cur++;
                         continue;
                     }
                     uint32_t ta, qa;
                     anchor_of(hs[lst[p]], ta, qa);
-                    if (seg[u].contains(ta, qa)) { stt[p] = 1; cur++; continue; }
+                    if (paths[u].in_committed(ta, qa)) { stt[p] = 1; cur++; continue; }
                     break;                                          // needs an extension first
                 }
             }
@@ -1403,7 +1413,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             fprintf(stderr, "[sfe] host scan/commit time %.1f ms (scan %.1f, bookkeeping %.1f, commit %.1f)\n", host_ms,
                     host_ms - book_ms - commit_ms, book_ms, commit_ms);
         for (size_t u = 0; u < NU; u++)
-            if (!pending[u].empty() || cursor[u] != per_unit[u].size()) fail(SFE_EINTERNAL, "commit did not finish");
+            if (cursor[u] != per_unit[u].size()) fail(SFE_EINTERNAL, "commit did not finish");
         st.committed = (int64_t)committed.size();
         const double t4 = now_ms();
         // --- output in (query, strand, t_start, q_start, t_end, q_end, anchor) order ---
