@@ -857,7 +857,9 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
             uint32_t dead = 0;
 #pragma unroll
             for (int p = 0; p < P; p++) dead |= ((uint32_t)Hn[p] >> (15 - p)) & (0x00010001u << p);
-            const uint32_t lmask = ~dead & (((1u << P) - 1u) * 0x10001u);
+            // live rows of the lane in row order (bit r = row r)
+            const uint32_t live = ~dead & (((1u << P) - 1u) * 0x10001u);
+            const uint32_t lmask = (live & 0xffffu) | ((live >> 16) << P);
             int lmin0, lmax0;
             {
                 // branch-free: with no live row m is 0 and the selects give the empty range
@@ -865,10 +867,8 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
                 const int L1 = __builtin_ctzll(m | (1ull << 63)), L2 = 63 - __builtin_clzll(m | 1ull);
                 const uint32_t f1 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L1);
                 const uint32_t f2 = (uint32_t)__builtin_amdgcn_readlane((int)lmask, L2);
-                const int r1 = (f1 & 0xffffu) ? __builtin_ctz(f1 | 0x80000000u) : P + __builtin_ctz((f1 >> 16) | 0x8000u);
-                const int r2 = (f2 >> 16) ? P + (31 - __builtin_clz(f2 >> 16)) : 31 - __builtin_clz((f2 & 0xffffu) | 1u);
-                lmin0 = m ? base + L1 * C + r1 : 1;
-                lmax0 = m ? base + L2 * C + r2 : 0;
+                lmin0 = m ? base + L1 * C + __builtin_ctz(f1 | 0x80000000u) : 1;
+                lmax0 = m ? base + L2 * C + (31 - __builtin_clz(f2 | 1u)) : 0;
             }
             {
                 int l_lo = 0, l_hi = -1;
@@ -910,17 +910,18 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
             int dnow = 0;
             if (__ballot(mx > Y)) {
                 const int admax = wave_max_dpp(mx);
-                const uint32_t a2 = (uint32_t)pk2(admax);
-                uint32_t eq = 0;
+                // every value is <= admax: a half equals it exactly when its difference is not negative
+                const int a2 = pk2(admax);
+                uint32_t below = 0;
 #pragma unroll
-                for (int p = 0; p < P; p++) {
-                    const uint32_t x = (uint32_t)Hn[p] ^ a2;
-                    eq |= ((x & 0xffffu) == 0 ? (1u << p) : 0u) | ((x >> 16) == 0 ? (0x10000u << p) : 0u);
-                }
+                for (int p = 0; p < P; p++)
+                    below |= ((uint32_t)pk_subs(Hn[p], a2) >> (15 - p)) & (0x00010001u << p);
+                const uint32_t eqh = ~below & (((1u << P) - 1u) * 0x10001u);
+                const uint32_t eq = (eqh & 0xffffu) | ((eqh >> 16) << P);
                 const uint64_t m = __ballot(eq != 0);
                 const int L = __builtin_ctzll(m);
                 const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)eq, L);
-                const int row = L * C + ((f & 0xffffu) ? __builtin_ctz(f & 0xffffu) : P + __builtin_ctz(f >> 16));
+                const int row = L * C + __builtin_ctz(f);
                 dnow = admax - Y;
                 best += dnow;
                 bi = base + row;

@@ -28,15 +28,18 @@ __device__ __forceinline__ int dpp_shr1(int old, int src) {
 __device__ __forceinline__ int dpp_shl1(int old, int src) {
     return __builtin_amdgcn_update_dpp(old, src, 0x130, 0xf, 0xf, false);
 }
-// Maximum over the wave (uniform result): in-row shifts, then the four row maxima.
+// Maximum over the wave of values >= NEG (uniform result): row_shr 1, 2, 4, 8
+// within each row of 16 lanes (lanes without a source see NEG), then
+// row_bcast 15 and 31 carry row maxima into the rows above; lane 63 ends with
+// the maximum.
 __device__ __forceinline__ int wave_max_dpp(int v) {
-    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));
-    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));
-    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));
-    v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));
-    int a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
-    int c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
-    return imax(imax(a, b), imax(c, d));
+    v = imax(v, __builtin_amdgcn_update_dpp(NEG, v, 0x111, 0xf, 0xf, false));
+    v = imax(v, __builtin_amdgcn_update_dpp(NEG, v, 0x112, 0xf, 0xf, false));
+    v = imax(v, __builtin_amdgcn_update_dpp(NEG, v, 0x114, 0xf, 0xf, false));
+    v = imax(v, __builtin_amdgcn_update_dpp(NEG, v, 0x118, 0xf, 0xf, false));
+    v = imax(v, __builtin_amdgcn_update_dpp(NEG, v, 0x142, 0xa, 0xf, false));
+    v = imax(v, __builtin_amdgcn_update_dpp(NEG, v, 0x143, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 #define ROW_LIMIT (1 << 30)       // antidiagonals beyond this stop the half with HALF_SCORE_RANGE
