@@ -38,6 +38,11 @@ import numpy as np  # noqa: E402
 INT32_VALU_PEAK_OPS = 256 * 64 * 2.4e9
 INT16X2_VALU_PEAK_OPS = 2 * INT32_VALU_PEAK_OPS
 YDROP_OPS_PER_CELL = 12      # E 3, F 3, G 2, H 1, prune 2, best 1
+# HBM bytes per extension launch of the mid workload's plain step (rocprofv3 FETCH_SIZE x 2.000 +
+# WRITE_SIZE x 1.000, the factors a 1 GiB device copy gives; the traffic summary under profiles/
+# holds the commands), valid only for the kernel source the counters were taken on
+YDROP_TRAFFIC_BYTES = 96.593e9
+YDROP_TRAFFIC_SOURCE_SHA256 = "6c6ec07e66aa6b57"
 XDROP_OPS_PER_COLUMN = 6     # 2 base extracts, index, lookup, add, max / drop test
 
 
@@ -233,8 +238,15 @@ def main():
     packed = dominant == "ydrop" and narrow
     peak = (INT16X2_VALU_PEAK_OPS if packed else INT32_VALU_PEAK_OPS) / 1e12
     unit = "Tops/s (int16 lane-ops, two per packed instruction)" if packed else "Tops/s (int32 lane-ops)"
+    traffic = None
+    if dominant == "ydrop" and narrow and args.workload == "mid":
+        import hashlib
+        src = os.path.join(ROOT, "paper_2606_06811_amd", "csrc", "k_fused.hip")
+        with open(src, "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest().startswith(YDROP_TRAFFIC_SOURCE_SHA256):
+                traffic = YDROP_TRAFFIC_BYTES
     roofline = dict(bound="alu", achieved=round(achieved, 4), peak=round(peak, 2), unit=unit,
-                    frac=round(achieved / peak, 5), traffic=None, kernel=dominant, note=note)
+                    frac=round(achieved / peak, 5), traffic=traffic, kernel=dominant, note=note)
 
     cpu = None
     if not args.no_cpu_baseline:
