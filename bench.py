@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py runs on one GPU only: there is no multi-GPU path (queries would shard by unit)",
               file=sys.stderr)
         raise SystemExit(2)
 
