@@ -61,9 +61,12 @@ double now_ms() {
 }
 
 struct SeqSet {
-    DBuf bases, nbits, sbits;
+    DBuf bases, nbits, sbits, nsum;
     int64_t total = 0;   // bases including padding
-    SeqSetView view() const { return SeqSetView{(const uint32_t *)bases.p, (const uint32_t *)nbits.p, (const uint32_t *)sbits.p}; }
+    SeqSetView view() const {
+        return SeqSetView{(const uint32_t *)bases.p, (const uint32_t *)nbits.p, (const uint32_t *)sbits.p,
+                          (const uint32_t *)nsum.p};
+    }
 };
 
 }  // namespace
@@ -182,6 +185,13 @@ void pack_set(sfe_ctx *c, const sfe_seq *seqs, int32_t n, int rc, SeqSet &set, s
         HIPCHK(hipGetLastError());
         if (src == c->staging.p) sync(c);   // staging is reused by the next sequence
     }
+    // one summary bit per N-plane word, so that readers skip the plane where it is empty
+    const int64_t nwords = total / 32 + 4;
+    const int64_t nsw = nwords / 32 + 4;
+    set.nsum.ensure((size_t)nsw * 4);
+    HIPCHK(hipMemsetAsync(set.nsum.p, 0, (size_t)nsw * 4, c->stream));
+    k_nsum<<<grid(nwords, 256), 256, 0, c->stream>>>(set.nbits.as<uint32_t>(), nwords, set.nsum.as<uint32_t>());
+    HIPCHK(hipGetLastError());
     int hbad = 0;
     HIPCHK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream));
     sync(c);

@@ -52,6 +52,16 @@ __global__ void k_pack(const uint8_t *__restrict__ txt, int64_t len, int64_t out
     if (badl) atomicOr(bad, 1);
 }
 
+// nsum bit x = N-plane word x is not zero (one ballot per 64 words; nsum zeroed before).
+__global__ void k_nsum(const uint32_t *__restrict__ nbits, int64_t nwords, uint32_t *__restrict__ nsum) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t m = __ballot(x < nwords && nbits[x < nwords ? x : 0] != 0);
+    if ((threadIdx.x & 63) == 0 && x < nwords) {
+        nsum[x >> 5] = (uint32_t)m;
+        nsum[(x >> 5) + 1] = (uint32_t)(m >> 32);
+    }
+}
+
 // keys[x] = seed key of target window x*step, or `sentinel` when invalid.
 __global__ void k_index_keys(SeqSetView T, int64_t nslots, int32_t step, SeedDesc sd, uint32_t sentinel,
                              uint32_t *__restrict__ keys, uint32_t *__restrict__ pos) {
@@ -163,8 +173,12 @@ __device__ __forceinline__ Codes16 codes16(const SeqSetView &S, int64_t p) {
     if (sh) c2 = (uint32_t)((((uint64_t)S.bases[w + 1] << 32) | c2) >> sh);
     const int64_t nw = p >> 5;
     const int nsh = (int)(p & 31);
-    uint32_t n = S.nbits[nw] >> nsh;
-    if (nsh > 16) n |= S.nbits[nw + 1] << (32 - nsh);
+    // the N plane is read only where its summary bits say it holds an N
+    const uint32_t flags =
+        (uint32_t)((((uint64_t)S.nsum[(nw >> 5) + 1] << 32) | S.nsum[nw >> 5]) >> (nw & 31)) & 3u;
+    uint32_t n = 0;
+    if (flags & 1u) n = S.nbits[nw] >> nsh;
+    if (nsh > 16 && (flags & 2u)) n |= S.nbits[nw + 1] << (32 - nsh);
     return Codes16{c2, n};
 }
 __device__ __forceinline__ int code_at(const Codes16 &c, int u) {

@@ -22,6 +22,7 @@ struct SeqSetView {
     const uint32_t *bases;
     const uint32_t *nbits;
     const uint32_t *sbits;
+    const uint32_t *nsum;   // bit x set when N-plane word x (bases 32x .. 32x + 31) holds an N
 };
 
 // code 0..3, or 4 for N

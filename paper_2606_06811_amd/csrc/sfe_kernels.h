@@ -60,6 +60,8 @@ __global__ void k_hsp_unique_flags(const sfe_hsp *h, const uint32_t *perm, int64
 __global__ void k_hsp_compact(const sfe_hsp *h, const uint32_t *perm, const uint32_t *flag, const uint32_t *dst,
                               int64_t n, sfe_hsp *out);
 
+__global__ void k_nsum(const uint32_t *nbits, int64_t nwords, uint32_t *nsum);
+
 // gapped stage (k_extend.hip)
 void launch_make_tasks(const ExtItem *items, int64_t n, const UnitDesc *units, int64_t nt, HalfTask *tasks,
                        hipStream_t st);
