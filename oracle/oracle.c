@@ -16,10 +16,12 @@
  *
  * Sections (paper):
  *   Sec. 1  seeds over a position table, local DP at candidate regions
- *   Sec. 4  Alg. 1 (strict serial LASTZ): IsMasked/IsContained -> IsFiltered
- *           -> YDropExtension -> Score >= tau -> Commit + UpdateMaskingLists
- *   Sec. 5  Alg. 3 (speculative): serial scan of <= K seeds, independent
- *           extensions, serial commit with checkContain
+ *   Sec. 4  Alg. 1 (the strict serial walk): an HSP whose anchor is covered
+ *           by an earlier commit is passed over, others are extended and
+ *           committed when they reach the gapped threshold
+ *   Sec. 5  Alg. 3 (speculative): batches of up to K uncovered HSPs are
+ *           extended independently and committed in order, the anchor test
+ *           re-applied at commit
  *   Sec. 7  the 12-of-19 spaced seed 1110100110010101111, transition tolerance
  *   Sec. 8  X-drop is a 1-D DP without gaps; Y-drop stops when the score
  *           falls a fixed amount below the best; anchors are extended as two
@@ -469,10 +471,10 @@ int64_t orc_extend(const uint8_t *tc, int64_t nt, const uint8_t *qc, int64_t nq,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Segment lists of committed alignments (Alg. 1 UpdateMaskingLists;        */
-/* IsContained is read as: the anchor column lies on an M column of an     */
-/* alignment committed earlier in the same (query, strand)).               */
-/* A chained hash table from diagonal d = t - q to [t_begin, t_end) runs.   */
+/* Committed M columns of one (query, strand) unit, for the anchor test of  */
+/* Alg. 1 and Alg. 3: an anchor is covered when it lies on an M column of   */
+/* an alignment committed earlier in the same unit.  Each M run is kept as  */
+/* (diagonal d = t - q, [t_begin, t_end)) in a hash table chained by d.     */
 /* ------------------------------------------------------------------------ */
 typedef struct run { int64_t d, tb, te; struct run *next; } run;
 #define NBUCKET (1 << 18)
@@ -518,17 +520,18 @@ static void seg_add_alignment(seglist *s, const orc_aln *a, const uint32_t *runs
 }
 
 /* ------------------------------------------------------------------------ */
-/* Commit loop for one (query, strand) unit; units are independent.        */
+/* The commit walk of one (query, strand) unit (units are independent).    */
 /*                                                                          */
-/* K <= 0 runs Alg. 1: walk the HSPs in the given (canonical) order; skip   */
-/* one whose anchor is contained; else extend it and commit it when its     */
-/* score reaches the gapped threshold.                                      */
+/* K <= 0, Alg. 1: the HSPs are visited in the given (canonical) order; an  */
+/* HSP whose anchor is covered by the commit list is passed over, any other */
+/* is extended, and the extension joins the commit list when its score is   */
+/* at least the gapped threshold.                                           */
 /*                                                                          */
-/* K >= 1 runs Alg. 3: phase 1 scans forward collecting up to K HSPs whose  */
-/* anchors are not contained; phase 2 extends all of them; phase 3 walks    */
-/* the batch in order and commits an extension when its anchor is not       */
-/* contained (checkContain, re-applied against every commit so far) and its */
-/* score reaches the threshold.                                             */
+/* K >= 1, Alg. 3: batches of up to K HSPs whose anchors are not covered    */
+/* are gathered in order, all of them are extended, and the batch is then   */
+/* walked in order again, each extension joining the commit list unless its */
+/* anchor has meanwhile become covered (also by a commit of the same batch) */
+/* or its score is below the threshold.                                     */
 /* ------------------------------------------------------------------------ */
 static void aln_push(orc_result *r, const orc_aln *a, const uint32_t *runs, int64_t nruns)
 {
@@ -563,15 +566,15 @@ void orc_commit_unit(const uint8_t *tc, int64_t nt, const uint8_t *qc, int64_t n
         for (int64_t j = 0; j < n; j++) {
             int64_t off = anchor_off(hsps[j].len);
             int64_t ta = hsps[j].t0 + off, qa = hsps[j].q0 + off;
-            if (seg_contains(&seg, ta, qa)) continue;           /* IsMasked / IsContained */
+            if (seg_contains(&seg, ta, qa)) continue;           /* anchor covered: pass over */
             orc_aln a;
             extend_anchor(tc, nt, qc, nq, ta, qa, sc, &a, &runs, &nruns, &runcap);
             res->n_extensions++;
             res->ext_cells += a.cells;
-            if (a.score >= sc->gapped_thresh) {                 /* Score(a) >= tau */
+            if (a.score >= sc->gapped_thresh) {                 /* threshold is inclusive */
                 a.query_id = query_id; a.strand = strand;
-                aln_push(res, &a, runs, nruns);                 /* CommitAlignment */
-                seg_add_alignment(&seg, &a, runs, nruns);       /* UpdateMaskingLists */
+                aln_push(res, &a, runs, nruns);                 /* into the output */
+                seg_add_alignment(&seg, &a, runs, nruns);       /* its M runs now cover */
             }
         }
     } else {
@@ -583,12 +586,12 @@ void orc_commit_unit(const uint8_t *tc, int64_t nt, const uint8_t *qc, int64_t n
         int64_t j = 0;
         while (j < n) {
             int64_t nbatch = 0;
-            while (nbatch < kb && j < n) {                      /* phase 1: serial scan */
+            while (nbatch < kb && j < n) {                      /* gather the batch */
                 int64_t off = anchor_off(hsps[j].len);
                 if (!seg_contains(&seg, hsps[j].t0 + off, hsps[j].q0 + off)) batch[nbatch++] = j;
                 j++;
             }
-            for (int64_t b = 0; b < nbatch; b++) {              /* phase 2: independent extensions */
+            for (int64_t b = 0; b < nbatch; b++) {              /* extensions are independent */
                 const orc_hsp *h = &hsps[batch[b]];
                 int64_t off = anchor_off(h->len);
                 int64_t cap = 0;
@@ -598,7 +601,7 @@ void orc_commit_unit(const uint8_t *tc, int64_t nt, const uint8_t *qc, int64_t n
                 res->n_extensions++;
                 res->ext_cells += ext[b].cells;
             }
-            for (int64_t b = 0; b < nbatch; b++) {              /* phase 3: serial commit */
+            for (int64_t b = 0; b < nbatch; b++) {              /* in-order commit of the batch */
                 orc_aln *a = &ext[b];
                 if (!seg_contains(&seg, a->anchor_t, a->anchor_q) && a->score >= sc->gapped_thresh) {
                     a->query_id = query_id; a->strand = strand;

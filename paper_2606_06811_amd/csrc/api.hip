@@ -1274,7 +1274,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             items.clear();
             item_ref.clear();
             scan_no++;
-            for (size_t u = 0; u < NU; u++) {                      // phase 1: serial scan per unit
+            for (size_t u = 0; u < NU; u++) {                      // Alg. 3 batch gathering, per unit
                 auto &lst = per_unit[u];
                 auto &stt = state[u];
                 int64_t taken = 0;
@@ -1341,7 +1341,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 }
             }
             run_batch(c, ix, items, sc, cpl, o.schedule, br, learned ? &cost : nullptr,
-                      learned ? &extent : nullptr);                                   // phase 2
+                      learned ? &extent : nullptr);                                   // the batch on the GPU
             st.predicted_halves += br.predicted;
             st.mispredicted_halves += br.mispredicted;
             if (progress) {
@@ -1387,7 +1387,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             }
             const double th3 = now_ms();
             book_ms += th3 - th2;
-            for (size_t u = 0; u < NU; u++) {                      // phase 3: serial commit, in order
+            for (size_t u = 0; u < NU; u++) {                      // in-order commit (Alg. 1 decisions)
                 auto &lst = per_unit[u];
                 auto &stt = state[u];
                 size_t &cur = cursor[u];

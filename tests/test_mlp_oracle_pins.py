@@ -154,6 +154,36 @@ def test_features_hand_worked():
     assert np.allclose(f, np.array(g["features"]), rtol=0, atol=1e-12)
 
 
+def windows_case():
+    """The hand-worked window case: sequences, HSPs and expected feature values."""
+    g = json.load(open(os.path.join(HERE, "golden", "features_windows.json")))
+    t = bytearray(b"A" * g["target_len"])
+    for pos, ch in g["target_set"].items():
+        t[int(pos)] = ord(ch)
+    q = bytearray(b"A" * g["query_len"])
+    for pos, ch in g["query_set"].items():
+        q[int(pos)] = ord(ch)
+    return g, np.frombuffer(bytes(t), np.uint8).copy(), np.frombuffer(bytes(q), np.uint8).copy()
+
+
+def test_features_windows_hand_worked():
+    """Every window of the features crossed on both sides: neighbour counts at
+    |dt| = 5000 / 5001 and 10000 / 10001, diagonal offsets 64 / 65, GC and
+    soft-mask windows of +-1000 bases with marked bases on their first and last
+    position, and a window clipped at the sequence start."""
+    g, T, Q = windows_case()
+    tc, ts = oracle.encode(T)
+    qc, qs = oracle.encode(Q)
+    h = np.zeros(len(g["hsps"]), dtype=[("t0", "i8"), ("q0", "i8"), ("len", "i8"), ("score", "i8")])
+    for i, r in enumerate(g["hsps"]):
+        h[i] = tuple(r)
+    f = mlp.features(tc, ts, qc, qs, h, 0)
+    for name, cols in g["expect"].items():
+        row = g["names"].index(name)
+        for col, val in cols.items():
+            assert abs(f[row, int(col)] - val) <= 1e-12, (name, col, f[row, int(col)], val)
+
+
 def test_targets_definition():
     t = mlp.targets((7, 2, 3), (0, 0, 0))
     assert np.allclose(t, [3.0, np.log2(6), 0.0, 0.0])

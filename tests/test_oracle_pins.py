@@ -308,3 +308,107 @@ def test_speculative_equals_serial(orc, scoring, tiny_run, K):
         assert np.array_equal(a1, a3)
         assert np.array_equal(o1, o3)
         assert n3 >= n1            # speculation can only add (shadow) work
+
+
+# --------------------------------------------------------------------------
+# the commit walk's pass-over decision, against brute force over M columns
+# --------------------------------------------------------------------------
+def _m_columns(a, ops):
+    """Set of (t, q) M columns of one alignment, walked from its start."""
+    cols = set()
+    t, q = int(a["t_start"]), int(a["q_start"])
+    for op in refimpl.runs_to_steps(ops):
+        if op == 0:
+            cols.add((t, q))
+            t, q = t + 1, q + 1
+        elif op == 1:
+            q += 1
+        else:
+            t += 1
+    return cols
+
+
+def _expected_walk(orc, tc, qc, hsps, sc):
+    """Alg. 1 with the anchor test done by brute force: a set of every M
+    column committed so far.  Extensions come from orc.extend (pinned above
+    by Gotoh / Smith-Waterman); only the pass-over decision is recomputed."""
+    covered = set()
+    commits, n_ext = [], 0
+    for h in hsps:
+        off = (int(h["len"]) - 1) // 2
+        ta, qa = int(h["t0"]) + off, int(h["q0"]) + off
+        if (ta, qa) in covered:
+            continue
+        a, ops = orc.extend(tc, qc, ta, qa, sc)
+        n_ext += 1
+        if int(a["score"]) >= sc["gapped_thresh"]:
+            commits.append((a, ops))
+            covered |= _m_columns(a, ops)
+    return commits, n_ext
+
+
+def _boundary_probes(a, ops, limit):
+    """One-column HSPs whose anchors sit on and just beside the M runs of an
+    alignment: a run's first and last column, the columns one before and one
+    after it on the same diagonal, and the first column shifted to each
+    neighbouring diagonal."""
+    probes = []
+    t, q = int(a["t_start"]), int(a["q_start"])
+    runs = 0
+    for w in ops:
+        ln, op = int(w) >> 2, int(w) & 3
+        if op == 0:
+            if runs < limit:
+                for pt, pq in ((t - 1, q - 1), (t, q), (t + ln - 1, q + ln - 1), (t + ln, q + ln),
+                               (t + 1, q), (t, q + 1)):
+                    probes.append((pt, pq))
+            runs += 1
+            t, q = t + ln, q + ln
+        elif op == 1:
+            q += ln
+        else:
+            t += ln
+    return probes
+
+
+@pytest.mark.parametrize("K", [0, 1, 5])
+def test_commit_pass_over_matches_brute_force(orc, scoring, K):
+    """Every HSP the walk passes over has its anchor on an M column of an
+    earlier commit, and every HSP it extends does not (Alg. 1; Alg. 3 with
+    batch size K commits the same).  The HSP list is built so that anchors
+    fall exactly on, and one column beside, the ends of committed M runs."""
+    t, q = related_pair(81, 2500, 0.12)
+    sc = dict(scoring)
+    first, fops = orc.extend(t, q, 1200, 1200 + (q.shape[0] - t.shape[0]) // 2, dict(sc, gapped_thresh=-BIG))
+    # the walk starts with an HSP on a homologous column (on the first extension's path)
+    steps = refimpl.runs_to_steps(fops)
+    tt, qq = int(first["t_start"]), int(first["q_start"])
+    anchor = None
+    for op in steps:
+        if op == 0 and tt > 1100 and anchor is None:
+            anchor = (tt, qq)
+        tt, qq = (tt + 1, qq + 1) if op == 0 else ((tt, qq + 1) if op == 1 else (tt + 1, qq))
+    assert anchor is not None
+    a0, o0 = orc.extend(t, q, anchor[0], anchor[1], sc)
+    assert int(a0["score"]) >= sc["gapped_thresh"]
+    probes = [anchor] + [p for p in _boundary_probes(a0, o0, 25)
+                         if 0 <= p[0] < t.shape[0] and 0 <= p[1] < q.shape[0]]
+    hsps = np.zeros(len(probes), orc.HSP_DTYPE)
+    hsps["t0"] = [p[0] for p in probes]
+    hsps["q0"] = [p[1] for p in probes]
+    hsps["len"] = 1
+    hsps["score"] = 5000
+    want, want_ext = _expected_walk(orc, t, q, hsps, sc)
+    got, gops, n_ext, _ = orc.commit_unit(t, q, hsps, sc, K)
+    # some probes are covered and some are not: both branches of the decision are exercised
+    assert 1 < len(want) and want_ext < len(probes)
+    assert len(got) == len(want)
+    for x, (a, ops) in enumerate(want):
+        g = got[x]
+        for f in ("t_start", "t_end", "q_start", "q_end", "score", "anchor_t", "anchor_q"):
+            assert int(g[f]) == int(a[f]), (x, f)
+        assert np.array_equal(gops[g["ops_off"]:g["ops_off"] + g["ops_len"]], ops)
+    if K <= 0:
+        assert n_ext == want_ext
+    else:
+        assert n_ext >= want_ext
