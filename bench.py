@@ -1,24 +1,31 @@
 """Benchmark of the seed -> X-drop -> Y-drop pipeline on one MI355X.
 
-One step = one pass of the whole hot path over the mid-size workload: build
-the position table of a 50 Mbp target (2-bit packing, seed keys, sort),
-seed hits of a 50 Mbp query on both strands fused with the ungapped X-drop
-filter, the HSP set (dedup + order), and the speculative batched gapped
-Y-drop extension with traceback and serial commit.  Inputs are synthetic
-(seeded), resident in HBM before the timed region.
+One step = one pass of the whole hot path over one batch of synthetic input:
+seed hits of the query (both strands) fused with the ungapped X-drop filter,
+the HSP set (dedup + order), and the speculative batched gapped Y-drop
+extension with traceback and serial commit.  Workloads:
 
-Two schedules of the gapped stage are timed on the same step: the plain one
-(one wave per anchor-half, halves in batch order) and the learned one: the
-cost model is trained first, on the GPU, from extension logs of every HSP of
-the first 2 Mbp of the query; the autotuner then times candidate schedules
-(rows per lane; plain, persistent or adaptive launch with the model's
-longest-first order; wave groups for long halves) on a 1 Mbp sample of the
-query and the fastest is used (adaptive when no tuning is asked for).  Both run untimed before the timed steps.  Their outputs must
+  mid         50 Mbp x 50 Mbp (200 repeat families, 1 % low complexity, 10 + 10
+              SVs per Mbp, 25 % divergence); the step also rebuilds the
+              position table of the target;
+  mid-stress  the same with 3 + 3 SVs per Mbp (homology blocks up to ~630 kbp);
+  chrom       1 Gbp target (1000 repeat families, index resident in HBM, built
+              once and timed apart) vs a 200 Mbp query (20 large SVs, 35 %
+              divergence) streamed as 10 Mbp chunks: step k aligns chunk k;
+  small       1 Mbp x 1 Mbp, 15 % divergence.
+
+Inputs are synthetic (seeded), resident in HBM before the timed region.
+
+Two schedules of the gapped stage run on the same steps: plain (one wave per
+anchor-half, halves in batch order) and learned: the cost model, trained on
+the GPU from extension logs of the first query bases, orders every batch
+(persistent queue or adaptive launch, longest predicted first); the
+autotuner picks among the schedules that use the model.  Their outputs must
 be identical.
 
 Prints one JSON line.  `value` is unique HSPs per second of the whole step
-with the learned schedule; the plain schedule's figures, gapped GCUPS and the
-other stage rates ride along.
+with the faster of the two schedules (`config.schedule` names it); the other
+schedule's figures, gapped GCUPS and the other stage rates ride along.
 """
 from __future__ import annotations
 
@@ -42,7 +49,8 @@ YDROP_OPS_PER_CELL = 12      # E 3, F 3, G 2, H 1, prune 2, best 1
 # WRITE_SIZE x 1.000, the factors a 1 GiB device copy gives; the traffic summary under profiles/
 # holds the commands), valid only for the kernel source the counters were taken on
 YDROP_TRAFFIC_BYTES = 96.593e9
-YDROP_TRAFFIC_SOURCE_SHA256 = "6c6ec07e66aa6b57"
+YDROP_TRAFFIC_SOURCE_SHA256 = "no-measurement-for-the-current-sources"
+YDROP_TRAFFIC_WORKLOAD = "mid"
 XDROP_OPS_PER_COLUMN = 6     # 2 base extracts, index, lookup, add, max / drop test
 
 
@@ -54,7 +62,17 @@ def make_workload(name: str):
     from paper_2606_06811_amd import synth
     if name == "mid":
         T, Q = synth.pair_mid()
-        desc = "50 Mbp target (200 repeat families x 50 copies, 1% soft-masked low complexity) vs 50 Mbp query (SVs + 25% divergence, 2% indels)"
+        desc = ("50 Mbp target (200 repeat families x 50 copies, 1% soft-masked low complexity) vs 50 Mbp query "
+                "(10 inversions + 10 translocations of 20 kbp per Mbp, 25% divergence, 2% indels)")
+    elif name == "mid-stress":
+        T, Q = synth.pair_mid(sv_per_mbp=3)
+        desc = ("50 Mbp target (200 repeat families x 50 copies, 1% soft-masked low complexity) vs 50 Mbp query "
+                "(3 inversions + 3 translocations of 20 kbp per Mbp, 25% divergence, 2% indels)")
+    elif name == "chrom":
+        T, Q = synth.pair_chromosome()
+        desc = ("1 Gbp target (1000 repeat families x 50 copies, 1% soft-masked low complexity, index resident in "
+                "HBM) vs 200 Mbp query (10 inversions + 10 translocations of 1-5 Mbp, 35% divergence, 2% indels) "
+                "streamed in 10 Mbp chunks, one chunk per step")
     elif name == "small":
         T, Q = synth.pair_small()
         desc = "1 Mbp target vs 1 Mbp query (3 inversions, 3 translocations of 20 kbp, 15% divergence, 2% indels)"
@@ -63,22 +81,54 @@ def make_workload(name: str):
     return T, Q, desc
 
 
-def cpu_baseline(T, Q, sc, sample_bp: int):
-    """The oracle, single-threaded, on the first sample_bp query bases vs the whole target."""
+def host_cpu():
+    """Model name and logical CPU count of the host (for the baseline's record)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(T, q, sc, what: str):
+    """The oracle, single-threaded, on one bounded sample of the workload."""
     import oracle
     oracle.build()
-    q = [Q[0][:sample_bp].copy()]
     t0 = time.perf_counter()
-    res = oracle.pipeline(T, q, sc)
+    res = oracle.pipeline(T, [q], sc)
     dt = time.perf_counter() - t0
     nh = sum(int(u["hsps"].shape[0]) for u in res["units"])
-    return dict(value=nh / dt, unit="HSPs/s", cores=1, kind="oracle",
-                sample=f"first {sample_bp} query bases (both strands) vs the full target; "
-                       f"{nh} unique HSPs, {res['alns'].shape[0]} alignments, {res['ext_cells']} DP cells "
-                       f"in {dt:.1f} s")
+    model, ncpu = host_cpu()
+    info = dict(value=nh / dt, unit="HSPs/s", cores=1, kind="oracle", host_cpu=model, host_logical_cpus=ncpu,
+                sample=f"{what}; {nh} unique HSPs, {res['alns'].shape[0]} alignments, {res['ext_cells']} DP "
+                       f"cells in {dt:.1f} s on one core")
+    return info, res
 
 
-def train_cost_model(ctx, sfe, synth, log_fn, T=None, Q=None, train_bp=0):
+def sample_parity(ctx, sfe, T, q, sc, ref):
+    """The same sample on the GPU (plain schedule): alignments and edit operations must equal the oracle's."""
+    import oracle
+    import torch
+    dev = torch.device("cuda:0")
+    idx = sfe.sfe_build_index(ctx, torch.from_numpy(T).to(dev), "1110100110010101111", 1, 1)
+    alns, ops, _ = sfe.sfe_align(ctx, idx, [torch.from_numpy(q).to(dev)], sc, cap=1 << 16, ops_cap=1 << 22)
+    idx.close()
+    ra = ref["alns"]
+    ok = alns.shape[0] == ra.shape[0]
+    for f in ("query_id", "strand", "t_start", "t_end", "q_start", "q_end", "score", "anchor_t", "anchor_q", "cells"):
+        ok = ok and bool(np.array_equal(alns[f].astype(np.int64), ra[f].astype(np.int64)))
+    for x in range(alns.shape[0] if ok else 0):
+        g = ops[int(alns["ops_offset"][x]):int(alns["ops_offset"][x]) + int(alns["ops_len"][x])]
+        ok = ok and bool(np.array_equal(g, oracle.aln_ops(ref, x)))
+    return ok, int(alns.shape[0])
+
+
+def train_cost_model(ctx, sfe, synth, log_fn, T=None, Q=None, train_bp=0, index=None):
     """The learned part: extension logs of every HSP of a training sample, then
     GPU training of the cost model (He-uniform start, seeded).  The sample is
     the first train_bp query bases of the benchmark pair against its whole
@@ -90,11 +140,14 @@ def train_cost_model(ctx, sfe, synth, log_fn, T=None, Q=None, train_bp=0):
     else:
         T, Q = synth.pair_small()
         what = "the 1 Mbp pair"
-    idx = sfe.sfe_build_index(ctx, T, synth.SEED_PATTERN, 1, 1)
+    t0 = time.perf_counter()
+    idx = index if (index is not None and train_bp > 0) else sfe.sfe_build_index(ctx, T, synth.SEED_PATTERN, 1, 1)
     hits = sfe.sfe_seed_hits(ctx, idx, Q)
     hsps = sfe.sfe_ungapped_xdrop(ctx, idx, Q, hits, dict(synth.SCORING))
     f, t = sfe.sfe_extension_log(ctx, idx, Q, hsps, dict(synth.SCORING))
-    idx.close()
+    if idx is not index:
+        idx.close()
+    log_fn(f"extension log of {hsps.shape[0]} HSPs in {time.perf_counter() - t0:.1f} s")
     rng = np.random.default_rng(12345)
     parts = []
     for o, i in ((64, 16), (64, 64), (64, 64), (4, 64)):
@@ -114,22 +167,43 @@ def train_cost_model(ctx, sfe, synth, log_fn, T=None, Q=None, train_bp=0):
                        loss_last=float(losses[-1]), train_s=round(dt, 3))
 
 
+def kernel_sources_digest():
+    """Digest of the extension kernel's source and every header it includes (the
+    stored HBM traffic figure is valid only for exactly these files)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2606_06811_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("k_fused.hip", "ydrop_common.h", "sfe_internal.h", "sfe_kernels.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "sfe.h"), "rb") as fh:
+        h.update(b"sfe.h\0" + fh.read())
+    return h.hexdigest()
+
+
+def length_histogram(alns):
+    """Committed alignments by target span, in powers of two (bin b: [2^b, 2^(b+1)) bases)."""
+    span = (alns["t_end"].astype(np.int64) - alns["t_start"].astype(np.int64)).clip(min=1)
+    b = np.floor(np.log2(span)).astype(np.int64)
+    return {f"2^{int(k)}": int(v) for k, v in zip(*np.unique(b, return_counts=True))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=["mid", "small"])
+    ap.add_argument("--workload", default="mid", choices=["mid", "mid-stress", "chrom", "small"])
     ap.add_argument("--round-k", type=int, default=0)
-    ap.add_argument("--schedule", default="both", choices=["plain", "persistent", "adaptive", "learned", "both"],
-                    help="both: time the plain schedule and the learned, autotuned one (value = learned)")
+    ap.add_argument("--schedule", default="both", choices=["plain", "learned", "both"],
+                    help="both: time the plain schedule and the learned one (the model orders every batch)")
     ap.add_argument("--cpl", type=int, default=0, help="rows per lane of the first band window (0: default)")
     ap.add_argument("--near-band", type=int, default=0, help="deferral nearness band (0: default, <0: off)")
-    ap.add_argument("--tune-bp", type=int, default=1_000_000,
-                    help="query bases the autotuner samples for the learned schedule (0: no tuning)")
-    ap.add_argument("--train-bp", type=int, default=2_000_000,
-                    help="query bases of the benchmark pair whose HSP extensions train the cost model "
-                         "(0: the 1 Mbp pair)")
+    ap.add_argument("--policy", type=int, default=0, help="0 DEFER, 1 PREFIX (Alg. 3 as printed)")
+    ap.add_argument("--tune-bp", type=int, default=-1,
+                    help="query bases the autotuner samples for the learned schedule (0: no tuning; -1: default)")
+    ap.add_argument("--train-bp", type=int, default=-1,
+                    help="query bases whose HSP extensions train the cost model (-1: default)")
     ap.add_argument("--cpu-sample-bp", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -137,13 +211,19 @@ def main():
         print("bench.py runs on one GPU only: there is no multi-GPU path (queries would shard by unit)",
               file=sys.stderr)
         raise SystemExit(2)
+    chrom = args.workload == "chrom"
+    if args.tune_bp < 0:
+        args.tune_bp = 200_000 if chrom else 1_000_000
+    if args.train_bp < 0:
+        args.train_bp = 200_000 if chrom else 2_000_000
 
     import torch
     from paper_2606_06811_amd import sfe, synth
 
     t0 = time.time()
     T, Q, desc = make_workload(args.workload)
-    log(f"workload generated in {time.time() - t0:.1f} s: target {T.shape[0]} bp, query {Q[0].shape[0]} bp")
+    log(f"workload generated in {time.time() - t0:.1f} s: target {T.shape[0]} bp, {len(Q)} queries, "
+        f"{sum(q.shape[0] for q in Q)} bp")
     sc = dict(synth.SCORING)
     dev = torch.device("cuda:0")
     Td = torch.from_numpy(T).to(dev)
@@ -152,66 +232,86 @@ def main():
     ctx = sfe.sfe_ctx_create(0, stream.cuda_stream)
     torch.cuda.synchronize()
 
+    resident = None
+    index_ms = None
+    if chrom:
+        # the target's position table stays resident; its build is timed apart from the steps
+        t0 = time.perf_counter()
+        resident = sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
+        torch.cuda.synchronize()
+        index_ms = 1e3 * (time.perf_counter() - t0)
+        log(f"position table of the {T.shape[0]} bp target built in {index_ms:.0f} ms")
+
     model, train_info, tune_info = None, None, None
     tuned = dict(max_cells_per_lane=args.cpl, schedule=sfe.SFE_SCHED_ADAPTIVE, wave_group_cap=0)
     if args.schedule in ("learned", "both"):
-        model, train_info = train_cost_model(ctx, sfe, synth, log, Td, Qd, args.train_bp)
+        model, train_info = train_cost_model(ctx, sfe, synth, log, Td, Qd[:1], args.train_bp, resident)
         if args.tune_bp > 0:
-            # autotuner: candidate schedules timed on the first tune_bp query bases (untimed setup)
+            # autotuner over the schedules that use the model, on the first tune_bp bases of the first query
             t0 = time.perf_counter()
-            idx = sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
-            tuned, entries = sfe.sfe_autotune(ctx, idx, Qd, sc, sample_bases=args.tune_bp, model=model,
-                                              round_k=args.round_k)
-            idx.close()
+            idx = resident or sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
+            tuned, entries = sfe.sfe_autotune(ctx, idx, Qd[:1], sc, sample_bases=args.tune_bp, model=model,
+                                              round_k=args.round_k, policy=args.policy)
+            if idx is not resident:
+                idx.close()
             tune_info = dict(sample_bases=args.tune_bp, chosen=tuned, seconds=round(time.perf_counter() - t0, 2),
                              candidates=entries)
             log(f"autotune on {args.tune_bp} query bases: {tuned} in {tune_info['seconds']} s")
 
-    def step(kind):
-        idx = sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
+    sched_name = {sfe.SFE_SCHED_PLAIN: "plain", sfe.SFE_SCHED_PERSISTENT: "persistent",
+                  sfe.SFE_SCHED_ADAPTIVE: "adaptive"}
+    peak_used = [0]
+
+    def step(kind, k):
+        q = [Qd[k % len(Qd)]] if chrom else Qd
+        idx = resident or sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
+        common = dict(round_k=args.round_k, cap=1 << 21, ops_cap=1 << 26, near_band=args.near_band,
+                      policy=args.policy)
         if kind == "plain":
             sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
-            out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k, schedule=sfe.SFE_SCHED_PLAIN, cap=1 << 21,
-                                ops_cap=1 << 26, max_cells_per_lane=args.cpl, near_band=args.near_band)
+            out = sfe.sfe_align(ctx, idx, q, sc, schedule=sfe.SFE_SCHED_PLAIN, max_cells_per_lane=args.cpl,
+                                **common)
         else:
-            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=tuned["wave_group_cap"] if kind == "learned" else 0)
-            fixed = sfe.SFE_SCHED_ADAPTIVE if kind == "adaptive" else sfe.SFE_SCHED_PERSISTENT
-            out = sfe.sfe_align(ctx, idx, Qd, sc, round_k=args.round_k,
-                                schedule=tuned["schedule"] if kind == "learned" else fixed,
-                                cap=1 << 21, ops_cap=1 << 26, model=model if kind == "learned" else None,
-                                max_cells_per_lane=tuned["max_cells_per_lane"] if kind == "learned" else args.cpl,
-                                near_band=args.near_band)
-        idx.close()
+            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=tuned["wave_group_cap"])
+            out = sfe.sfe_align(ctx, idx, q, sc, schedule=tuned["schedule"], model=model,
+                                max_cells_per_lane=tuned["max_cells_per_lane"], **common)
+        if idx is not resident:
+            idx.close()
+        free, total = torch.cuda.mem_get_info(dev)
+        peak_used[0] = max(peak_used[0], total - free)
         return out
 
     def run(kind):
         for w in range(args.warmup):
-            a, o, s = step(kind)
+            a, o, s = step(kind, args.steps + w)
             log(f"[{kind}] warmup {w}: {s['hsps']} HSPs, {s['committed']} alignments, {s['rounds']} rounds, "
                 f"{s['ms_total']:.0f} ms")
         torch.cuda.synchronize()
-        stats = []
+        stats, outs = [], []
         t_start = time.perf_counter()
         for k in range(args.steps):
-            a, o, s = step(kind)
+            a, o, s = step(kind, k)
             stats.append(s)
+            outs.append((a, o))
             log(f"[{kind}] step {k}: {s['ms_total']:.0f} ms in align (seed+xdrop {s['ms_seed_xdrop']:.0f}, "
-                f"hsp set {s['ms_hsp_set']:.0f}, predict {s['ms_predict']:.0f}, extend {s['ms_extend']:.0f})")
+                f"hsp set {s['ms_hsp_set']:.0f}, predict {s['ms_predict']:.0f}, extend {s['ms_extend']:.0f}; "
+                f"{s['rounds']} rounds)")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
-        return dict(ms_step=1e3 * elapsed / args.steps, stats=stats, alns=a, ops=o)
+        return dict(ms_step=1e3 * elapsed / args.steps, stats=stats, outs=outs)
 
     kinds = ["plain", "learned"] if args.schedule == "both" else [args.schedule]
     res = {k: run(k) for k in kinds}
-    head = res[kinds[-1]]
     bit_exact = None
     if len(kinds) == 2:
-        bit_exact = bool(np.array_equal(res["plain"]["alns"], res["learned"]["alns"])
-                         and np.array_equal(res["plain"]["ops"], res["learned"]["ops"]))
+        bit_exact = all(np.array_equal(a1, a2) and np.array_equal(o1, o2)
+                        for (a1, o1), (a2, o2) in zip(res["plain"]["outs"], res["learned"]["outs"]))
+    head_kind = min(kinds, key=lambda k: res[k]["ms_step"])
+    head = res[head_kind]
     stats = head["stats"]
     ms_step = head["ms_step"]
-    s = stats[-1]
-    hsps_per_s = s["hsps"] / (ms_step / 1e3)
+    hsps = sum(x["hsps"] for x in stats) / len(stats)
+    hsps_per_s = hsps / (ms_step / 1e3)
 
     # dominant kernel: gapped extension (VALU bound; packed int16 when every launch took the
     # 16-bit kernel); live HIP-event timing
@@ -239,31 +339,46 @@ def main():
     peak = (INT16X2_VALU_PEAK_OPS if packed else INT32_VALU_PEAK_OPS) / 1e12
     unit = "Tops/s (int16 lane-ops, two per packed instruction)" if packed else "Tops/s (int32 lane-ops)"
     traffic = None
-    if dominant == "ydrop" and narrow and args.workload == "mid":
-        import hashlib
-        src = os.path.join(ROOT, "paper_2606_06811_amd", "csrc", "k_fused.hip")
-        with open(src, "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest().startswith(YDROP_TRAFFIC_SOURCE_SHA256):
-                traffic = YDROP_TRAFFIC_BYTES
+    if (dominant == "ydrop" and narrow and args.workload == YDROP_TRAFFIC_WORKLOAD
+            and kernel_sources_digest().startswith(YDROP_TRAFFIC_SOURCE_SHA256)):
+        traffic = YDROP_TRAFFIC_BYTES
     roofline = dict(bound="alu", achieved=round(achieved, 4), peak=round(peak, 2), unit=unit,
                     frac=round(achieved / peak, 5), traffic=traffic, kernel=dominant, note=note)
 
-    cpu = None
+    cpu, parity_ok = None, None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(T, Q, sc, args.cpu_sample_bp)
+        if chrom:
+            # the oracle's position table of the whole 1 Gbp target would take minutes to sort:
+            # the sample is the first query bases of chunk 0 against the 20 Mbp of target it derives from
+            Ts, qs = T[:20_000_000], Q[0][:args.cpu_sample_bp].copy()
+            what = (f"first {args.cpu_sample_bp} bases of query chunk 0 (both strands) vs the first 20 Mbp of "
+                    f"the target")
+        else:
+            Ts, qs = T, Q[0][:args.cpu_sample_bp].copy()
+            what = f"first {args.cpu_sample_bp} query bases (both strands) vs the full target"
+        cpu, ref = cpu_baseline(Ts, qs, sc, what)
+        parity_ok, n_par = sample_parity(ctx, sfe, Ts, qs, sc, ref)
+        log(f"cpu baseline {cpu['value']:.2f} HSPs/s; the GPU on the same sample: "
+            f"{'identical' if parity_ok else 'DIFFERENT'} ({n_par} alignments)")
 
     def summary(k):
         r = res[k]
-        x = r["stats"][-1]
-        return dict(ms_per_step=round(r["ms_step"], 2), hsps_per_s=round(x["hsps"] / (r["ms_step"] / 1e3), 2),
-                    alignments_per_s=round(x["committed"] / (r["ms_step"] / 1e3), 2),
-                    ms_extend=round(x["ms_extend"], 2), ms_ydrop_kernel=round(x["ms_ydrop_kernel"], 2),
-                    predicted_halves=x["predicted_halves"], mispredicted_halves=x["mispredicted_halves"],
-                    misprediction_rate=(round(x["mispredicted_halves"] / x["predicted_halves"], 4)
-                                        if x["predicted_halves"] else None),
-                    ms_predict=round(x["ms_predict"], 2))
+        xs = r["stats"]
+        pred = sum(x["predicted_halves"] for x in xs)
+        mis = sum(x["mispredicted_halves"] for x in xs)
+        return dict(ms_per_step=round(r["ms_step"], 2),
+                    hsps_per_s=round(sum(x["hsps"] for x in xs) / len(xs) / (r["ms_step"] / 1e3), 2),
+                    alignments_per_s=round(sum(x["committed"] for x in xs) / len(xs) / (r["ms_step"] / 1e3), 2),
+                    ms_extend=round(sum(x["ms_extend"] for x in xs) / len(xs), 2),
+                    ms_ydrop_kernel=round(sum(x["ms_ydrop_kernel"] for x in xs) / len(xs), 2),
+                    predicted_halves=pred, mispredicted_halves=mis,
+                    misprediction_rate=round(mis / pred, 4) if pred else None,
+                    ms_predict=round(sum(x["ms_predict"] for x in xs) / len(xs), 2),
+                    schedule=("plain" if k == "plain" else sched_name[tuned["schedule"]] + " + cost model"))
 
+    s = stats[-1]
+    hsps_ms = sum(x["ms_seed_xdrop"] for x in stats)
     line = {
         "metric": "HSPs/s + gapped GCUPS, 1 MI355X; learned-binned vs plain batch, bit-exact",
         "value": round(hsps_per_s, 2),
@@ -277,22 +392,28 @@ def main():
         "vs_baseline": None,
         "dtype": ext_type,
         "data": "synthetic",
-        "config": {"workload": desc, "schedule": kinds[-1], "policy": "defer",
-                   "round_k": args.round_k or (1 << 20)},
-        "gapped_gcups": round(s["cells"] / (s["ms_extend"] / 1e3) / 1e9, 3) if s["ms_extend"] > 0 else None,
+        "config": {"workload": desc, "schedule": summary(head_kind)["schedule"],
+                   "policy": "prefix" if args.policy == 1 else "defer",
+                   "round_k": sfe.sfe_align_opts_resolve(round_k=args.round_k, policy=args.policy,
+                                                         near_band=args.near_band)["round_k"]},
+        "gapped_gcups": round(sum(x["cells"] for x in stats) / (sum(x["ms_extend"] for x in stats) / 1e3) / 1e9, 3),
         "gapped_gcups_kernel": round(yd_cells / (yd_ms / 1e3) / 1e9, 3) if yd_ms > 0 else None,
-        "seed_hits_per_s": round(s["seed_hits"] / (s["ms_seed_xdrop"] / 1e3), 1) if s["ms_seed_xdrop"] > 0 else None,
-        "alignments_per_s": round(s["committed"] / (ms_step / 1e3), 2),
+        "seed_hits_per_s": round(sum(x["seed_hits"] for x in stats) / (hsps_ms / 1e3), 1) if hsps_ms > 0 else None,
+        "alignments_per_s": round(sum(x["committed"] for x in stats) / len(stats) / (ms_step / 1e3), 2),
         "schedules": {k: summary(k) for k in kinds},
         "learned_vs_plain": (round(res["plain"]["ms_step"] / res["learned"]["ms_step"], 4)
                              if len(kinds) == 2 else None),
         "bit_exact_learned_vs_plain": bit_exact,
+        "parity_sample": parity_ok,
         "cost_model_training": train_info,
         "autotune": tune_info,
         "counts": {k: s[k] for k in ("seed_hits", "hsps_raw", "hsps", "rounds", "extensions", "committed",
                                      "shadow", "cells", "overflow_reruns", "xdrop_columns")},
         "stage_ms": {k: round(s[k], 2) for k in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total",
                                                  "ms_ydrop_kernel", "ms_seed_xdrop_kernel", "ms_predict")},
+        "region_length_histogram": length_histogram(head["outs"][-1][0]),
+        "index_build_ms": round(index_ms, 1) if index_ms is not None else None,
+        "peak_hbm_used_bytes": int(peak_used[0]),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

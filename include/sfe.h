@@ -50,12 +50,16 @@ typedef int32_t sfe_status;
 #define SFE_ERANGE (-4)     /* a sequence breaks the int32 score or uint32 coordinate range */
 #define SFE_EDEVICE (-5)    /* a HIP runtime call failed */
 #define SFE_EINTERNAL (-6)  /* an internal consistency check failed */
+#define SFE_EIO (-7)        /* a file could not be opened, read or written */
 
 typedef struct sfe_ctx sfe_ctx;
 typedef struct sfe_index sfe_index;
 
 /* A spaced seed (Sec. 7): pattern of '1' (care) and '0' (don't care), first
- * and last characters '1', span <= 32, weight (number of '1') <= 14.
+ * and last characters '1', span <= 32, weight (number of '1') <= 14.  The
+ * weight cap comes from the position table's dense offsets array, 4^weight + 1
+ * u32 entries: 1 GiB at weight 14, 16 GiB at 16 -- the paper's seeds (weight
+ * 12 of span 19, and 14 of 22) fit. 
  * transitions = 1 also accepts windows whose care positions differ in exactly
  * one place by a transition (A<->G, C<->T).  A target position p is indexed
  * iff p % step == 0. */
@@ -147,7 +151,9 @@ typedef struct {
                                workgroup kernel */
     int32_t policy;         /* SFE_POLICY_* */
     int32_t near_band;      /* SFE_POLICY_DEFER's nearness rule: diagonals within which a later HSP
-                               of the batch waits for an earlier one; 0 = 32, < 0 = rule off */
+                               of the batch waits for an earlier one; 0 = 32, < 0 = rule off
+                               (round_k 0 then means 256: without the rule the first batch would
+                               hold every HSP of every region at once) */
     int64_t arena_bytes;    /* device memory for traceback codes of the halves in flight,
                                allocated once per context; 0 = half the free device memory
                                at first use (at least 32 GiB).  A batch whose halves
@@ -157,6 +163,15 @@ typedef struct {
                                SFE_SCHED_ADAPTIVE the halves of each batch are queued (or
                                launched) longest-predicted first.  Never changes the output. */
 } sfe_align_opts;
+
+/* The options sfe_align runs with: *in (NULL: all zero) with every automatic
+ * field filled in -- strands 3; max_cells_per_lane 6 (others clamped into
+ * [2, 8]); near_band 32 (negative: -1, rule off); round_k 2^20 under
+ * SFE_POLICY_DEFER with the nearness rule on, otherwise 256 (Alg. 3's batch
+ * size; the paper settles on 48 to 64 for CPU threads).  SFE_EINVAL for an
+ * unknown schedule or policy or a negative field that has no meaning.  Host
+ * only: touches no device, so it also checks options before a context exists. */
+sfe_status sfe_align_opts_resolve(const sfe_align_opts *in, sfe_align_opts *out);
 
 typedef struct {
     int64_t seed_hits;          /* hits evaluated by the X-drop filter */
@@ -263,9 +278,10 @@ sfe_status sfe_ctx_get_tuning(const sfe_ctx *ctx, sfe_tuning *t);
 
 /* Autotuner.  Times sfe_align on a sample of the workload (the first
  * sample_bases of every query, all against idx) under each candidate schedule
- * -- rows per lane 6 / 8 in the first band window, plain, persistent or
- * adaptive launch (the last two with opts->model when one is given), wave groups for
- * long halves off or after 8192 antidiagonals -- and keeps the fastest: the
+ * -- rows per lane 6 / 8 in the first band window; plain, persistent or
+ * adaptive launch, only the last two (with the model) when opts->model is
+ * given; wave groups for long halves off or after 8192 antidiagonals --
+ * three times each, and keeps the fastest (by its best time): the
  * context's wave_group_cap is set and opts->max_cells_per_lane / schedule are
  * written.  Other fields of *opts are used as given.  report (may be NULL)
  * receives every candidate's extension time.  No choice changes results. */
@@ -335,6 +351,17 @@ sfe_status sfe_model_grad(sfe_model *m, const float *x, const float *t, int64_t 
  * step, may be NULL) receives each batch's loss before its update. */
 sfe_status sfe_model_train(sfe_model *m, const float *x, const float *t, int64_t n, const int32_t *order,
                            int64_t n_order, int32_t batch, float lr, float *losses);
+/* Persistence (a versioned blob): a 32-byte header -- magic "SFEMLP\0\0",
+ * u32 version 1, u32 layout 1 (the 16-64-64-64-4 network above), u32
+ * parameter count SFE_MLP_NPARAMS, u32 0, i64 Adam steps taken -- then the
+ * FP32 master parameters, the Adam first and second moments (SFE_MLP_NPARAMS
+ * floats each) and a u64 FNV-1a hash of all preceding bytes; little-endian,
+ * 116056 bytes.  A loaded model continues training exactly where the saved
+ * one stopped.  sfe_model_load with ctx and out both NULL only checks the
+ * file.  Errors: SFE_EIO (cannot open, read or write), SFE_EINVAL (not a model
+ * file of this version and layout: wrong size, magic, header or hash). */
+sfe_status sfe_model_save(const sfe_model *m, const char *path);
+sfe_status sfe_model_load(sfe_ctx *ctx, const char *path, sfe_model **out);
 
 const char *sfe_status_str(sfe_status s);
 const char *sfe_last_error(const sfe_ctx *ctx);

@@ -251,10 +251,6 @@ int max_abs_sub(const ScoreDesc &d) {
     return m;
 }
 
-// Scores are int32 throughout; the kernels stop and report SFE_ERANGE as soon
-// as any score reaches 2^29, which keeps every intermediate value in range.
-void check_range(const sfe_index *, const sfe_seq *, int32_t, const ScoreDesc &) {}
-
 template <class T>
 void cub_exclusive_sum(sfe_ctx *c, const T *in, T *out, int64_t n) {
     size_t bytes = 0;
@@ -353,25 +349,59 @@ struct BatchResult {
 };
 
 // Default traceback arena, allocated on first use: half the device memory then
-// free (at least 32 GiB, in 256 KiB chunks).  The codes of every long half in
+// free, and at least 32 GiB when the device has that much to spare (never
+// more than the free memory less 2 GiB).  The codes of every long half in
 // flight live there at once: a batch of a few thousand halves of 10^6
 // antidiagonals holds a few hundred GB of codes at its peak, and a dry pool
 // makes waves wait for chunks.
 const int64_t kMinArena = (int64_t)32 << 30;
-int64_t default_arena(sfe_ctx *c) {
+const int64_t kArenaFloor = (int64_t)64 << 20;
+const int64_t kArenaSpare = (int64_t)2 << 30;
+int64_t default_arena(sfe_ctx *) {
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    const int64_t half = (int64_t)(freeb / 2) >> 18 << 18;
-    return std::max<int64_t>(kMinArena, half);
+    const int64_t f = (int64_t)freeb;
+    const int64_t want = std::min(std::max(kMinArena, f / 2), std::max(f - kArenaSpare, f / 2));
+    return std::max(want >> 18 << 18, kArenaFloor);
 }
 
-// Arena 0 of `bytes` (kept if already that large); arenas 1.. grow from it.
+// Arena 0 of `bytes` when it fits (kept if already that large).  A request
+// the device cannot hold is retried at half the size, down to 64 MiB and to
+// no less than just above the current size (growth); below that the call
+// fails with SFE_ENOMEM.
 void ensure_arena(sfe_ctx *c, int64_t bytes) {
     if (c->arenas.empty()) c->arenas.emplace_back(new DBuf);
-    if (c->arena_bytes >= bytes && c->arenas[0]->p) return;
-    c->arenas[0]->ensure((size_t)bytes);
-    c->arena_bytes = bytes;
+    DBuf &a = *c->arenas[0];
+    if (c->arena_bytes >= bytes && a.p) return;
+    const int64_t had = a.p ? c->arena_bytes : 0;
+    if (a.p) {
+        HIPCHK(hipFree(a.p));
+        a.p = nullptr;
+        a.n = 0;
+        c->arena_bytes = 0;
+    }
+    for (int64_t b = std::max<int64_t>(bytes >> 18 << 18, (int64_t)1 << 18);;) {
+        if (b <= had) fail(SFE_ENOMEM, "no device memory left for the traceback arena");
+        if (hipMalloc(&a.p, (size_t)b) == hipSuccess) {
+            a.n = (size_t)b;
+            c->arena_bytes = b;
+            break;
+        }
+        (void)hipGetLastError();
+        a.p = nullptr;
+        b = (b / 2) >> 18 << 18;
+        if (b < kArenaFloor) fail(SFE_ENOMEM, "no device memory left for the traceback arena");
+    }
     c->arena_heads.ensure(8 * 32);
+}
+
+// Grows arena 0 for a half whose codes did not fit with one wave in flight:
+// four times larger, or as large as the free memory allows.
+void grow_arena(sfe_ctx *c) {
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    const int64_t most = c->arena_bytes + (int64_t)freeb - kArenaSpare;
+    ensure_arena(c, std::min<int64_t>(c->arena_bytes * 4, most));
 }
 
 void set_arena(sfe_ctx *c, int64_t bytes) {
@@ -592,12 +622,21 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
                                   c->stream);
             }
         } else {
-            const int32_t cap = 4096 << (2 * (sg - ST_RING));
-            if (sg - ST_RING > 10) fail(SFE_EINTERNAL, "band width beyond 2^24 rows");
+            // ring of 4096 * 4^s rows, s <= 6 (2^24 rows: the 16M-row band limit of the kernels)
+            if (sg - ST_RING > 6) fail(SFE_EINTERNAL, "band width beyond 2^24 rows");
+            const int64_t cap = (int64_t)4096 << (2 * (sg - ST_RING));
             ar = arena_at(c, ai);
             HIPCHK(hipMemsetAsync(ar.head, 0, 8, c->stream));
-            int32_t *ring = (int32_t *)c->ring_d.ensure((size_t)cnt * 7 * cap * 4);
-            launch_ydrop_ring(tasks, ids, cnt, T, Qp, Qm, sc, ar, ring, cap, hres, c->stream);
+            // seven int32 rows of ring per half; as many halves per launch as half the free memory holds
+            size_t freeb = 0, totalb = 0;
+            HIPCHK(hipMemGetInfo(&freeb, &totalb));
+            const int64_t per_half = 7 * cap * 4;
+            const int64_t fit = std::max<int64_t>(1, (int64_t)(freeb / 2 + c->ring_d.n / 2) / per_half);
+            const int64_t slice = std::min<int64_t>(cnt, fit);
+            int32_t *ring = (int32_t *)c->ring_d.ensure((size_t)(slice * per_half));
+            for (int64_t o = 0; o < cnt; o += slice)
+                launch_ydrop_ring(tasks, ids + o, std::min(slice, cnt - o), T, Qp, Qm, sc, ar, ring, (int32_t)cap, hres,
+                                  c->stream);
         }
         HIPCHK(hipGetLastError());
         if (fused) HIPCHK(hipEventRecord(c->ev1, c->stream));
@@ -679,7 +718,7 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
             }
         }
         if (arena_full) ai++;
-        if (pool_full) ensure_arena(c, c->arena_bytes * 4);
+        if (pool_full) grow_arena(c);
         if (getenv("SFE_PROGRESS")) {
             if (fused)
                 fprintf(stderr, "[sfe]   launch: %s C=%d level %d, %lld halves, %lld waves, %llu KiB chunks, next %zu\n",
@@ -906,6 +945,56 @@ sfe_status guard(sfe_ctx *c, const std::function<void()> &f) {
 
 }  // namespace
 
+// Model file: a 32-byte header (magic "SFEMLP\0\0", u32 version 1, u32 layout 1
+// = 16-64-64-64-4 ReLU network with the parameter order of sfe.h, u32
+// parameter count, u32 zero, i64 Adam steps taken), the FP32 master
+// parameters, the two Adam moment vectors, then a u64 FNV-1a hash of every
+// preceding byte.  Little-endian.
+namespace {
+const char kModelMagic[8] = {'S', 'F', 'E', 'M', 'L', 'P', 0, 0};
+const size_t kModelHeader = 32;
+const size_t kModelBytes = kModelHeader + 3 * (size_t)SFE_MLP_NPARAMS * 4 + 8;
+
+uint64_t fnv1a(const uint8_t *p, size_t n) {
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; i++) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Reads and checks a model file; SFE_EIO when it cannot be read, SFE_EINVAL
+// when it is not a model of this layout.
+sfe_status read_model_file(const char *path, std::vector<uint8_t> &buf, std::string &why) {
+    FILE *f = fopen(path, "rb");
+    if (!f) { why = std::string("cannot open ") + path; return SFE_EIO; }
+    buf.assign(kModelBytes + 1, 0);
+    const size_t got = fread(buf.data(), 1, buf.size(), f);
+    const bool err = ferror(f) != 0;
+    fclose(f);
+    if (err) { why = std::string("cannot read ") + path; return SFE_EIO; }
+    if (got != kModelBytes) { why = "model file has the wrong size"; return SFE_EINVAL; }
+    buf.resize(kModelBytes);
+    uint32_t ver = 0, layout = 0, np = 0, zero = 0;
+    memcpy(&ver, buf.data() + 8, 4);
+    memcpy(&layout, buf.data() + 12, 4);
+    memcpy(&np, buf.data() + 16, 4);
+    memcpy(&zero, buf.data() + 20, 4);
+    int64_t steps = 0;
+    memcpy(&steps, buf.data() + 24, 8);
+    if (memcmp(buf.data(), kModelMagic, 8) != 0) { why = "not a model file (magic)"; return SFE_EINVAL; }
+    if (ver != 1 || layout != 1 || np != SFE_MLP_NPARAMS || zero != 0 || steps < 0) {
+        why = "model file of another version, layout or size";
+        return SFE_EINVAL;
+    }
+    uint64_t h = 0;
+    memcpy(&h, buf.data() + kModelBytes - 8, 8);
+    if (h != fnv1a(buf.data(), kModelBytes - 8)) { why = "model file checksum mismatch"; return SFE_EINVAL; }
+    return SFE_OK;
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1039,7 +1128,6 @@ sfe_status sfe_ungapped_xdrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *qu
         ScoreDesc sc = check_scoring(scp);
         QueryLayout L;
         upload_queries(c, queries, nq, 3, ix->sd.span, L);
-        check_range(ix, queries, nq, sc);
         *n_hsps = 0;
         if (n == 0) return;
         if (!hits) fail(SFE_EINVAL, "null hits");
@@ -1097,7 +1185,6 @@ sfe_status sfe_gapped_ydrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *quer
         ScoreDesc sc = check_scoring(scp);
         QueryLayout L;
         upload_queries(c, queries, nq, 3, ix->sd.span, L);
-        check_range(ix, queries, nq, sc);
         *n_ops = 0;
         if (n == 0) return;
         if (!hsps || !out) fail(SFE_EINVAL, "null hsps or output");
@@ -1120,6 +1207,32 @@ sfe_status sfe_gapped_ydrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *quer
     });
 }
 
+sfe_status sfe_align_opts_resolve(const sfe_align_opts *in, sfe_align_opts *out) {
+    if (!out) return SFE_EINVAL;
+    sfe_align_opts o{};
+    if (in) o = *in;
+    if (o.strands == 0) o.strands = 3;
+    if (o.strands < 1 || o.strands > 3) return SFE_EINVAL;
+    if (o.schedule < SFE_SCHED_PLAIN || o.schedule > SFE_SCHED_ADAPTIVE) return SFE_EINVAL;
+    if (o.policy != SFE_POLICY_DEFER && o.policy != SFE_POLICY_PREFIX) return SFE_EINVAL;
+    if (o.arena_bytes < 0) return SFE_EINVAL;
+    if (o.max_cells_per_lane == 0) o.max_cells_per_lane = 6;
+    if (o.max_cells_per_lane < 0) return SFE_EINVAL;
+    o.max_cells_per_lane = std::min(8, std::max(2, o.max_cells_per_lane));
+    if (o.near_band == 0) o.near_band = 32;
+    if (o.near_band < 0) o.near_band = -1;
+    if (o.round_k < 0) return SFE_EINVAL;
+    if (o.round_k == 0) {
+        // Every HSP of a (query, strand) that nothing defers enters the batch: with the
+        // nearness rule on, the rule keeps each region's later HSPs back; without it a
+        // batch would hold every HSP of a region at once, so it is capped like Alg. 3's.
+        const bool rule_on = o.policy == SFE_POLICY_DEFER && o.near_band > 0;
+        o.round_k = rule_on ? (1 << 20) : 256;
+    }
+    *out = o;
+    return SFE_OK;
+}
+
 sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, int32_t nq, const sfe_scoring *scp,
                      const sfe_align_opts *opts, sfe_aln *out, int64_t cap, int64_t *n_alns, uint32_t *ops,
                      int64_t ops_cap, int64_t *n_ops, sfe_stats *stats) {
@@ -1128,19 +1241,16 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         const double t0 = now_ms();
         ScoreDesc sc = check_scoring(scp);
         sfe_align_opts o{};
-        if (opts) o = *opts;
-        int strands = o.strands ? o.strands : 3;
-        if (strands < 1 || strands > 3) fail(SFE_EINVAL, "strands must be 1, 2 or 3");
-        if (o.schedule < SFE_SCHED_PLAIN || o.schedule > SFE_SCHED_ADAPTIVE) fail(SFE_EINVAL, "unknown schedule");
-        const int64_t K = o.round_k > 0 ? o.round_k : (o.policy == SFE_POLICY_DEFER ? (1 << 20) : 256);
-        const int cpl = o.max_cells_per_lane > 0 ? std::min(8, std::max(2, o.max_cells_per_lane)) : 6;
+        if (sfe_align_opts_resolve(opts, &o) != SFE_OK) fail(SFE_EINVAL, "invalid sfe_align options");
+        const int strands = o.strands;
+        const int64_t K = o.round_k;
+        const int cpl = o.max_cells_per_lane;
         if (o.arena_bytes > 0) set_arena(c, std::max<int64_t>(o.arena_bytes, 2 * ARENA_PAGE));
         sfe_stats st{};
         c->ydrop_ms = c->sx_ms = 0;
         c->ydrop_launches = c->ydrop_cells = c->sx_launches = c->narrow_launches = 0;
         QueryLayout L;
         upload_queries(c, queries, nq, strands, ix->sd.span, L);
-        check_range(ix, queries, nq, sc);
         // --- seeds + X-drop (fused) --------------------------------------------------
         const double t1 = now_ms();
         int64_t nch = (int64_t)L.chunks.size();
@@ -1238,7 +1348,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         BatchResult br;
         const bool defer = o.policy == SFE_POLICY_DEFER;
         const bool progress = getenv("SFE_PROGRESS") != nullptr;
-        const int64_t DB = o.near_band == 0 ? 32 : o.near_band;      // diagonal band of the nearness rule
+        const int64_t DB = o.near_band;                              // diagonal band of the nearness rule (< 0: off)
         uint32_t scan_no = 0;
         // doomed: the anchor of waiting extension p lies in a committed alignment, or on the
         // path of an earlier waiting extension that is not itself doomed (depth-capped; the
@@ -1494,9 +1604,11 @@ sfe_status sfe_autotune(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries,
     std::vector<uint32_t> ops(1 << 22);
     const int cpls[2] = {6, 8};
     const int caps[2] = {0, 8192};
+    // with a cost model only the schedules that use it compete
+    const int sched_lo = opts->model ? SFE_SCHED_PERSISTENT : SFE_SCHED_PLAIN;
     bool first = true;
     for (int cap : caps)
-        for (int sched = SFE_SCHED_PLAIN; sched <= SFE_SCHED_ADAPTIVE; sched++)
+        for (int sched = sched_lo; sched <= SFE_SCHED_ADAPTIVE; sched++)
             for (int cpl : cpls) {
                 sfe_align_opts o = *opts;
                 o.max_cells_per_lane = cpl;
@@ -1506,7 +1618,9 @@ sfe_status sfe_autotune(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries,
                 sfe_stats st{};
                 int64_t na = 0, no = 0;
                 sfe_status r = SFE_OK;
-                for (int rep_i = first ? 2 : 1; rep_i > 0; rep_i--) {      // the first run also warms up
+                double ms = 1e300;
+                // three timed runs (the fastest counts); the very first candidate warms up once more
+                for (int rep_i = first ? 4 : 3; rep_i > 0; rep_i--) {
                     for (;;) {
                         r = sfe_align(c, ix, sample.data(), nq, scp, &o, out.data(), (int64_t)out.size(), &na,
                                       ops.data(), (int64_t)ops.size(), &no, &st);
@@ -1518,15 +1632,16 @@ sfe_status sfe_autotune(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries,
                         break;
                     }
                     if (r != SFE_OK) break;
+                    if (!(first && rep_i == 4)) ms = std::min(ms, st.ms_extend);
                 }
                 first = false;
                 if (r != SFE_OK) {
                     c->tuning = saved;
                     return r;
                 }
-                if (rep.n < 16) rep.entries[rep.n++] = sfe_tune_entry{cpl, sched, cap, 0, st.ms_extend};
-                if (st.ms_extend < best_ms) {
-                    best_ms = st.ms_extend;
+                if (rep.n < 16) rep.entries[rep.n++] = sfe_tune_entry{cpl, sched, cap, 0, ms};
+                if (ms < best_ms) {
+                    best_ms = ms;
                     best = o;
                     best_cap = cap;
                     rep.best = rep.n - 1;
@@ -1740,6 +1855,64 @@ sfe_status sfe_model_train(sfe_model *m, const float *x, const float *t, int64_t
     });
 }
 
+
+sfe_status sfe_model_save(const sfe_model *m, const char *path) {
+    if (!m || !path) return SFE_EINVAL;
+    sfe_ctx *c = m->ctx;
+    return guard(c, [&] {
+        const size_t NP = SFE_MLP_NPARAMS;
+        std::vector<uint8_t> buf(kModelBytes, 0);
+        memcpy(buf.data(), kModelMagic, 8);
+        const uint32_t hdr[4] = {1u, 1u, (uint32_t)NP, 0u};
+        memcpy(buf.data() + 8, hdr, 16);
+        memcpy(buf.data() + 24, &m->step, 8);
+        uint8_t *body = buf.data() + kModelHeader;
+        copy_out(c, body, m->master.p, NP * 4);
+        copy_out(c, body + NP * 4, m->m.p, NP * 4);
+        copy_out(c, body + 2 * NP * 4, m->v.p, NP * 4);
+        sync(c);
+        const uint64_t h = fnv1a(buf.data(), kModelBytes - 8);
+        memcpy(buf.data() + kModelBytes - 8, &h, 8);
+        FILE *f = fopen(path, "wb");
+        if (!f) fail(SFE_EIO, std::string("cannot create ") + path);
+        const size_t put = fwrite(buf.data(), 1, buf.size(), f);
+        const bool bad = fclose(f) != 0 || put != buf.size();
+        if (bad) fail(SFE_EIO, std::string("cannot write ") + path);
+    });
+}
+
+sfe_status sfe_model_load(sfe_ctx *c, const char *path, sfe_model **out) {
+    if (!path || (!c) != (!out)) return SFE_EINVAL;
+    if (out) *out = nullptr;
+    std::vector<uint8_t> buf;
+    std::string why;
+    const sfe_status st = read_model_file(path, buf, why);
+    if (st != SFE_OK) {
+        if (c) c->last_error = why;
+        return st;
+    }
+    if (!c) return SFE_OK;             // check only
+    const size_t NP = SFE_MLP_NPARAMS;
+    const uint8_t *body = buf.data() + kModelHeader;
+    std::vector<float> params(NP);
+    memcpy(params.data(), body, NP * 4);
+    sfe_model *m = nullptr;
+    sfe_status r = sfe_model_create(c, params.data(), &m);
+    if (r != SFE_OK) return r;
+    r = guard(c, [&] {
+        copy_in(c, m->m.p, body + NP * 4, NP * 4);
+        copy_in(c, m->v.p, body + 2 * NP * 4, NP * 4);
+        memcpy(&m->step, buf.data() + 24, 8);
+        sync(c);
+    });
+    if (r != SFE_OK) {
+        sfe_model_destroy(m);
+        return r;
+    }
+    *out = m;
+    return SFE_OK;
+}
+
 const char *sfe_status_str(sfe_status s) {
     switch (s) {
     case SFE_OK: return "ok";
@@ -1749,6 +1922,7 @@ const char *sfe_status_str(sfe_status s) {
     case SFE_ERANGE: return "value range exceeded";
     case SFE_EDEVICE: return "device error";
     case SFE_EINTERNAL: return "internal error";
+    case SFE_EIO: return "file input/output failed";
     default: return "unknown status";
     }
 }

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsfe.so")
 _lib = None
 
-SFE_OK, SFE_EINVAL, SFE_ENOMEM, SFE_ECAPACITY, SFE_ERANGE, SFE_EDEVICE, SFE_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+SFE_OK, SFE_EINVAL, SFE_ENOMEM, SFE_ECAPACITY, SFE_ERANGE, SFE_EDEVICE, SFE_EINTERNAL, SFE_EIO = \
+    0, -1, -2, -3, -4, -5, -6, -7
 SFE_XDROP_RAW = 1
 SFE_ALN_PASSED = 1
 SFE_SCHED_PLAIN, SFE_SCHED_PERSISTENT, SFE_SCHED_ADAPTIVE = 0, 1, 2
@@ -116,13 +117,17 @@ def lib():
         L.sfe_model_predict.argtypes = [P, P, I64, P]
         L.sfe_model_grad.argtypes = [P, P, P, I64, P, P]
         L.sfe_model_train.argtypes = [P, P, P, I64, P, I64, I32, ctypes.c_float, P]
+        L.sfe_model_save.argtypes = [P, ctypes.c_char_p]
+        L.sfe_model_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(P)]
+        L.sfe_align_opts_resolve.argtypes = [ctypes.POINTER(_AlignOpts), ctypes.POINTER(_AlignOpts)]
         L.sfe_status_str.argtypes = [I32]
         L.sfe_status_str.restype = ctypes.c_char_p
         L.sfe_last_error.argtypes = [P]
         L.sfe_last_error.restype = ctypes.c_char_p
         for f in ("sfe_ctx_create", "sfe_build_index", "sfe_seed_hits", "sfe_ungapped_xdrop", "sfe_gapped_ydrop",
                   "sfe_align", "sfe_ctx_set_tuning", "sfe_ctx_get_tuning", "sfe_autotune", "sfe_hsp_features", "sfe_extension_log", "sfe_model_create", "sfe_model_params",
-                  "sfe_model_predict", "sfe_model_grad", "sfe_model_train"):
+                  "sfe_model_predict", "sfe_model_grad", "sfe_model_train", "sfe_model_save", "sfe_model_load",
+                  "sfe_align_opts_resolve"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -341,6 +346,24 @@ def sfe_align(ctx: Context, idx: Index, queries, scoring: dict, round_k: int = 0
         return out[:na.value], ops[:no.value], s
 
 
+def sfe_align_opts_resolve(round_k: int = 0, schedule: int = SFE_SCHED_PLAIN, strands: int = 0,
+                           max_cells_per_lane: int = 0, policy: int = SFE_POLICY_DEFER, near_band: int = 0,
+                           arena_bytes: int = 0) -> dict:
+    """The options sfe_align would run with (host only; raises SfeError on invalid ones)."""
+    o = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(policy),
+                   int(near_band), int(arena_bytes), None)
+    r = _AlignOpts()
+    st = lib().sfe_align_opts_resolve(ctypes.byref(o), ctypes.byref(r))
+    if st != SFE_OK:
+        raise SfeError(st, "invalid sfe_align options")
+    return {f: getattr(r, f) for f, _ in _AlignOpts._fields_ if f != "model"}
+
+
+def sfe_model_check_file(path: str) -> int:
+    """Status of sfe_model_load's file check alone (no device): SFE_OK, SFE_EINVAL or SFE_EIO."""
+    return int(lib().sfe_model_load(None, os.fsencode(path), None))
+
+
 def _f32(a, shape=None):
     if hasattr(a, "data_ptr"):
         return a
@@ -411,6 +434,18 @@ class Model:
         _check(lib().sfe_model_train(self.ptr, _ptr(x), _ptr(t), x.shape[0], _ptr(order), order.shape[0],
                                      int(batch), float(lr), _ptr(losses)), self.ctx)
         return losses[:steps]
+
+    def save(self, path: str):
+        _check(lib().sfe_model_save(self.ptr, os.fsencode(path)), self.ctx)
+
+    @classmethod
+    def load(cls, ctx: Context, path: str) -> "Model":
+        p = ctypes.c_void_p()
+        _check(lib().sfe_model_load(ctx.ptr, os.fsencode(path), ctypes.byref(p)), ctx)
+        m = cls.__new__(cls)
+        m.ctx, m.ptr = ctx, p
+        ctx._children.add(m)
+        return m
 
     def close(self):
         if self.ptr:

@@ -51,9 +51,20 @@ def rng_for(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
 
+_CDF = np.cumsum(COMPOSITION) / COMPOSITION.sum()
+_CHUNK = 1 << 23
+_MUT_CHUNK = 1 << 24
+
+
 def iid_codes(rng: np.random.Generator, n: int) -> np.ndarray:
-    """n i.i.d. base codes 0..3 (A C G T) with the GC-41 % composition."""
-    return rng.choice(4, size=n, p=COMPOSITION).astype(np.uint8)
+    """n i.i.d. base codes 0..3 (A C G T) with the GC-41 % composition.
+    Drawn 8 Mi bases at a time (the same draws as one inverse-CDF pass, without
+    its 16 bytes of temporaries per base)."""
+    out = np.empty(n, dtype=np.uint8)
+    for a in range(0, n, _CHUNK):
+        b = min(n, a + _CHUNK)
+        out[a:b] = np.searchsorted(_CDF, rng.random(b - a), side="right")
+    return out
 
 
 def to_ascii(codes: np.ndarray, soft: np.ndarray | None = None) -> np.ndarray:
@@ -64,7 +75,18 @@ def to_ascii(codes: np.ndarray, soft: np.ndarray | None = None) -> np.ndarray:
 
 
 def mutate(rng, codes, soft, d, indel=0.02):
-    """Substitutions at rate d (transition:transversion 2:1) plus indels."""
+    """Substitutions at rate d (transition:transversion 2:1) plus indels.
+    Sequences longer than 16 Mi bases are mutated 16 Mi bases at a time (the
+    same model; bounded temporaries)."""
+    n = codes.shape[0]
+    if n > _MUT_CHUNK:
+        parts = [_mutate_one(rng, codes[a:a + _MUT_CHUNK], soft[a:a + _MUT_CHUNK], d, indel)
+                 for a in range(0, n, _MUT_CHUNK)]
+        return np.concatenate([c for c, _ in parts]), np.concatenate([m for _, m in parts])
+    return _mutate_one(rng, codes, soft, d, indel)
+
+
+def _mutate_one(rng, codes, soft, d, indel):
     n = codes.shape[0]
     codes = codes.copy()
     sub = rng.random(n) < d
@@ -192,11 +214,14 @@ def pair_small(n=1_000_000, divergence=0.15, seed=1, n_inv=3, n_trans=3, seg_len
 
 
 def pair_mid(n=50_000_000, divergence=0.25, seed=2, families=200, copies=50,
-             sv_per_mbp=3, seg_len=20_000, low_complexity=0.01):
+             sv_per_mbp=10, seg_len=20_000, low_complexity=0.01):
     """The mid-size pipeline workload: n-base target with repeat families
     (300-6000 bp consensus, `copies` copies at 10-20 % divergence) and 1 %
     soft-masked low-complexity runs; the query gets sv_per_mbp inversions and
-    sv_per_mbp translocations of seg_len per Mbp, then mutate(divergence)."""
+    sv_per_mbp translocations of seg_len per Mbp, then mutate(divergence).
+    At 10 per Mbp the colinear blocks between breakpoints run up to ~200 kbp
+    (median 20 kbp), so gapped regions span ~50 bp to 200 kbp; at 3 per Mbp
+    (the stress variant) blocks reach ~630 kbp."""
     rng = rng_for(seed)
     t = iid_codes(rng, n)
     ts = np.zeros(n, dtype=bool)
@@ -236,4 +261,61 @@ def pair_chunks(n=100_000_000, n_chunks=4096, seed=3, families=200, copies=50,
             c, m = revcomp_codes(c, m)
         c, m = mutate(crng, c, m, crng.uniform(div_lo, div_hi))
         queries.append(to_ascii(c, m))
+    return to_ascii(t, ts), queries
+
+
+def large_svs(rng, codes, soft, n_inv, n_trans, len_lo, len_hi):
+    """n_inv inversions and n_trans translocations of uniform length in
+    [len_lo, len_hi]: the sequence is cut into n_inv + n_trans equal slots and
+    one segment placed at random inside each (so they never overlap); the
+    inversions are reverse-complemented in place, then the translocated
+    segments are cut out and each pasted at a random position."""
+    n = codes.shape[0]
+    k = n_inv + n_trans
+    slot = n // k
+    if len_hi > slot:
+        raise ValueError("segments longer than their slots")
+    lens = rng.integers(len_lo, len_hi + 1, size=k)
+    starts = [int(x * slot + rng.integers(0, slot - lens[x] + 1)) for x in range(k)]
+    order = rng.permutation(k)
+    inv = [(starts[i], int(lens[i])) for i in order[:n_inv]]
+    trans = sorted((starts[i], int(lens[i])) for i in order[n_inv:])
+    codes, soft = codes.copy(), soft.copy()
+    for a, L in inv:
+        c, m = revcomp_codes(codes[a:a + L], soft[a:a + L])
+        codes[a:a + L], soft[a:a + L] = c, m
+    keep = np.ones(n, dtype=bool)
+    pieces = []
+    for a, L in trans:
+        pieces.append((codes[a:a + L].copy(), soft[a:a + L].copy()))
+        keep[a:a + L] = False
+    codes, soft = codes[keep], soft[keep]
+    for c, m in pieces:
+        p = int(rng.integers(0, codes.shape[0] + 1))
+        codes = np.concatenate([codes[:p], c, codes[p:]])
+        soft = np.concatenate([soft[:p], m, soft[p:]])
+    return codes, soft
+
+
+def pair_chromosome(n=1_000_000_000, query_len=200_000_000, chunk=10_000_000, divergence=0.35, seed=5,
+                    families=1000, copies=50, low_complexity=0.01, n_inv=10, n_trans=10,
+                    sv_lo=1_000_000, sv_hi=5_000_000, chunk_ids=None):
+    """The chromosome-scale workload: an n-base target with repeat families
+    (the mid recipe, `families` of them) and 1 % soft-masked low-complexity
+    runs; the query genome gets n_inv inversions and n_trans translocations of
+    1-5 Mbp, then mutate(divergence); the query is its first query_len bases,
+    streamed as consecutive `chunk`-base pieces (separate query sequences).
+    chunk_ids selects some of the pieces (all by default)."""
+    rng = rng_for(seed)
+    t = iid_codes(rng, n)
+    ts = np.zeros(n, dtype=bool)
+    t, ts = add_repeats(rng, t, ts, families, copies, 300, 6000, 0.10, 0.20)
+    t, ts = add_low_complexity(rng, t, ts, low_complexity)
+    qc, qs = large_svs(rng, t, ts, n_inv, n_trans, sv_lo, sv_hi)
+    # mutate a little more than query_len bases (indels change the length) and cut
+    head = min(qc.shape[0], query_len + query_len // 20 + 1024)
+    qc, qs = mutate(rng, qc[:head], qs[:head], divergence)
+    qc, qs = qc[:query_len], qs[:query_len]
+    ids = range((qc.shape[0] + chunk - 1) // chunk) if chunk_ids is None else chunk_ids
+    queries = [to_ascii(qc[i * chunk:(i + 1) * chunk], qs[i * chunk:(i + 1) * chunk]) for i in ids]
     return to_ascii(t, ts), queries

@@ -141,13 +141,25 @@ def test_grad_parity(ctx):
     log(f"grad: loss {loss:.6g} vs {rl:.6g}, relative L2 error {rel:.3g}")
     assert abs(loss - rl) <= 1e-4 * abs(rl)
     assert rel <= 2e-2
-    # every layer block, not only the large ones
+    # element by element in every parameter block: |g - g_ref| <= 1e-2 |g_ref| + 1e-3 max|g_ref of the block|.
+    # Both sides round activations and back-propagated signals to BF16 at the same points; only the FP32
+    # summation order differs, which can move a value across a BF16 rounding boundary (one ulp, 2^-8) for a
+    # few of the ~10^5 rounded values.  Such a flip changes one sample's share (1/300 of the mean) of the
+    # gradient by 0.4 %, far below 1e-3 of the block's largest element; the relative term covers elements
+    # whose value is a sum with little cancellation.
     o = 0
+    worst = 0.0
     for rows, cols in mlp.SHAPES:
         for size in (rows * cols, rows):
             blk = slice(o, o + size)
-            assert np.linalg.norm(g[blk] - rg[blk]) <= 5e-2 * np.linalg.norm(rg[blk]) + 1e-6
+            scale = float(np.abs(rg[blk]).max())
+            bound = 1e-2 * np.abs(rg[blk]) + 1e-3 * scale + 1e-9
+            dev = np.abs(g[blk] - rg[blk])
+            worst = max(worst, float((dev / bound).max()))
+            bad = np.nonzero(dev > bound)[0]
+            assert bad.size == 0, (o, bad[:8], g[blk][bad[:8]], rg[blk][bad[:8]])
             o += size
+    log(f"grad: worst element deviation {worst:.3g} of its bound")
 
 
 def test_train_parity(ctx):
@@ -164,6 +176,14 @@ def test_train_parity(ctx):
     assert losses.shape == rl.shape
     assert np.allclose(losses, rl, rtol=2e-2, atol=1e-3)
     assert np.linalg.norm((p - p0) - (rp - p0)) <= 5e-2 * np.linalg.norm(rp - p0)
+    # element by element: every parameter's change within 5 % of the oracle's change plus a tenth of one
+    # Adam step (lr).  Adam normalises each element's update by its own gradient history, so a gradient
+    # element that differs by rounding moves its parameter by at most a fraction of lr per step.
+    dev = np.abs((p - p0) - (rp - p0))
+    bound = 5e-2 * np.abs(rp - p0) + 1e-4
+    log(f"train: worst parameter deviation {float((dev / bound).max()):.3g} of its bound")
+    bad = np.nonzero(dev > bound)[0]
+    assert bad.size == 0, (bad[:8], (p - p0)[bad[:8]], (rp - p0)[bad[:8]])
     assert losses[-1] < losses[0]
 
 
@@ -251,8 +271,9 @@ def test_autotune_picks_a_schedule_and_keeps_results(ctx, case):
     m = sfe.Model(ctx, init_params(13))
     chosen, entries = sfe.sfe_autotune(ctx, idx, Q, dict(synth.SCORING), sample_bases=20_000, model=m)
     log(f"autotune: chosen {chosen}; {len(entries)} candidates")
-    assert len(entries) == 12
-    assert chosen["max_cells_per_lane"] in (6, 8) and chosen["schedule"] in (0, 1, 2)
+    # with a model only the schedules that use it compete: persistent and adaptive
+    assert len(entries) == 8 and {e["schedule"] for e in entries} == {1, 2}
+    assert chosen["max_cells_per_lane"] in (6, 8) and chosen["schedule"] in (1, 2)
     best = min(entries, key=lambda e: e["ms_extend"])
     assert (best["cells_per_lane"], best["schedule"], best["wave_group_cap"]) == (
         chosen["max_cells_per_lane"], chosen["schedule"], chosen["wave_group_cap"])
@@ -263,3 +284,38 @@ def test_autotune_picks_a_schedule_and_keeps_results(ctx, case):
         sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
     a0, o0, _ = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING))
     assert np.array_equal(a0, a1) and np.array_equal(o0, o1)
+    # without a model the plain launch competes too
+    chosen2, entries2 = sfe.sfe_autotune(ctx, idx, Q, dict(synth.SCORING), sample_bases=20_000)
+    sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
+    assert len(entries2) == 12 and {e["schedule"] for e in entries2} == {0, 1, 2}
+
+
+def test_model_save_load_round_trip(ctx, tmp_path):
+    """A saved model loads with identical parameters, predictions and Adam state:
+    training the loaded copy continues exactly as the original does."""
+    rng = np.random.default_rng(17)
+    X = rng.uniform(0, 1, (200, 16)).astype(np.float32)
+    T = rng.uniform(0, 12, (200, 4)).astype(np.float32)
+    order = rng.permutation(200).astype(np.int32)
+    m = sfe.Model(ctx, init_params(11))
+    m.train(X, T, order, batch=50, lr=1e-3)
+    path = str(tmp_path / "cost.sfem")
+    m.save(path)
+    assert sfe.sfe_model_check_file(path) == sfe.SFE_OK
+    m2 = sfe.Model.load(ctx, path)
+    assert np.array_equal(m2.params(), m.params())
+    assert np.array_equal(m2.predict(X), m.predict(X))
+    l1 = m.train(X, T, order, batch=50, lr=1e-3)
+    l2 = m2.train(X, T, order, batch=50, lr=1e-3)
+    assert np.array_equal(l1, l2)
+    assert np.array_equal(m2.params(), m.params())
+    # a damaged file is refused through the context as well
+    raw = bytearray(open(path, "rb").read())
+    raw[40] ^= 1
+    bad = tmp_path / "bad.sfem"
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(sfe.SfeError) as e:
+        sfe.Model.load(ctx, str(bad))
+    assert e.value.status == sfe.SFE_EINVAL
+    m.close()
+    m2.close()

@@ -391,3 +391,42 @@ def test_long_halves_on_wave_groups(ctx, n, div, indel, cap):
             g = ops[int(alns["ops_offset"][x]):int(alns["ops_offset"][x]) + int(alns["ops_len"][x])]
             assert np.array_equal(g, o), x
     sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
+
+
+# ---------------------------------------------------------------------------
+# the int32 score guard
+# ---------------------------------------------------------------------------
+def test_score_range_errors(ctx):
+    """Scores that reach 2^29 stop the call with SFE_ERANGE, in the ungapped
+    filter (alone and inside the pipeline) and in the gapped extension: a
+    20 kbp sequence aligned to itself at 30000 per matching column passes 2^29
+    after ~17,900 columns."""
+    rng = synth.rng_for(77)
+    S = synth.to_ascii(synth.iid_codes(rng, 20_000))
+    sc = dict(synth.SCORING)
+    sc["sub"] = [[30000 if a == b and a < 4 else -30000 for b in range(5)] for a in range(5)]
+    sc["xdrop"] = 1 << 20
+    sc["ydrop"] = 1 << 20
+    idx = sfe.sfe_build_index(ctx, S, PATTERN, 1, 1)
+    log("score range: sfe_align")
+    with pytest.raises(sfe.SfeError) as e:
+        sfe.sfe_align(ctx, idx, [S], sc)
+    assert e.value.status == sfe.SFE_ERANGE
+    log("score range: sfe_ungapped_xdrop")
+    hits = np.zeros(1, sfe.HIT_DTYPE)
+    hits[0] = (100, 100, 0, 0, (0, 0, 0))
+    with pytest.raises(sfe.SfeError) as e:
+        sfe.sfe_ungapped_xdrop(ctx, idx, [S], hits, sc, raw=True)
+    assert e.value.status == sfe.SFE_ERANGE
+    log("score range: sfe_gapped_ydrop")
+    h = np.zeros(1, sfe.HSP_DTYPE)
+    h[0] = (100, 100, 1, 30000, 0, 0, (0, 0, 0))
+    with pytest.raises(sfe.SfeError) as e:
+        sfe.sfe_gapped_ydrop(ctx, idx, [S], h, sc)
+    assert e.value.status == sfe.SFE_ERANGE
+    # the same half with a score that stays below the guard succeeds
+    sc["sub"] = [[300 if a == b and a < 4 else -300 for b in range(5)] for a in range(5)]
+    sc["ydrop"] = 9400
+    alns, ops = sfe.sfe_gapped_ydrop(ctx, idx, [S], h, sc)
+    assert int(alns["score"][0]) == 300 * 20_000
+    idx.close()
