@@ -346,6 +346,19 @@ sfe_status sfe_model_params(const sfe_model *m, float *params);
 sfe_status sfe_model_predict(sfe_model *m, const float *x, int64_t n, float *y);
 /* Gradient (SFE_MLP_NPARAMS) and loss of the whole set (x, t) as one batch. */
 sfe_status sfe_model_grad(sfe_model *m, const float *x, const float *t, int64_t n, float *grad, float *loss);
+/* sfe_model_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same results, but no allocation of any kind.  x
+ * (n x SFE_MLP_NFEAT), t (n x SFE_MLP_NOUT), grad (SFE_MLP_NPARAMS) and loss
+ * (1 float) must be device memory; 1 <= n <= SFE_NOALLOC_MAX_SAMPLES
+ * (SFE_EINVAL otherwise).  The working memory (sample ids, per-block partial
+ * gradients: about 10 MB) is one fixed array per device, set up when a
+ * context is created on that device and shared by every call there: calls
+ * that overlap on one device race.  The call is ordered on the context's
+ * stream and returns without waiting for it. */
+#define SFE_NOALLOC_MAX_SAMPLES 16384
+sfe_status sfe_model_grad_noalloc(sfe_model *m, const float *x, const float *t, int64_t n, float *grad,
+                                  float *loss);
 /* Adam steps over the batches of `order` (n_order sample ids in [0, n),
  * consumed `batch` at a time, a short last batch used as is); losses (one per
  * step, may be NULL) receives each batch's loss before its update. */

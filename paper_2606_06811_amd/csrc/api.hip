@@ -9,6 +9,7 @@
 #include <chrono>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <tuple>
 #include <cstdio>
 #include <cstdlib>
@@ -995,6 +996,40 @@ sfe_status read_model_file(const char *path, std::vector<uint8_t> &buf, std::str
 }
 }  // namespace
 
+// Working memory of sfe_model_grad_noalloc, one fixed array per device: the
+// sample ids, then per-block squared errors, then per-block partial gradients
+// (64 samples per block) for up to SFE_NOALLOC_MAX_SAMPLES samples -- about
+// 10 MB, held by every device the library runs on until the process ends.
+// Host code never passes the array's name to a kernel: it takes the device
+// address from hipGetSymbolAddress, once per device, when a context is made.
+namespace {
+constexpr size_t kNoAllocBlocks = (SFE_NOALLOC_MAX_SAMPLES + 63) / 64;
+constexpr size_t kScratchIds = (size_t)SFE_NOALLOC_MAX_SAMPLES * 4;
+constexpr size_t kScratchSse = (kNoAllocBlocks * 4 + 255) / 256 * 256;
+constexpr size_t kScratchPart = kNoAllocBlocks * SFE_MLP_NPARAMS * 4;
+constexpr size_t kScratchBytes = kScratchIds + kScratchSse + kScratchPart;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the device must be current).
+void scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) fail(SFE_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return;
+    void *ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch[device] = (uint8_t *)ptr;
+}
+
+uint8_t *scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (device >= 0 && device < kMaxDevices) ? g_scratch[device] : nullptr;
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1014,6 +1049,7 @@ sfe_status sfe_ctx_create(int device, void *hip_stream, sfe_ctx **out) {
             c->own_stream = true;
         }
         HIPCHK(upload_encoding_table(c->stream));
+        scratch_setup(device);
         HIPCHK(hipEventCreate(&c->ev0));
         HIPCHK(hipEventCreate(&c->ev1));
         c->counters.ensure(64);
@@ -1798,6 +1834,29 @@ sfe_status sfe_model_grad(sfe_model *m, const float *x, const float *t, int64_t 
         copy_out(c, grad, gd, NP * 4);
         if (loss) copy_out(c, loss, ld, 4);
         sync(c);
+    });
+}
+
+sfe_status sfe_model_grad_noalloc(sfe_model *m, const float *x, const float *t, int64_t n, float *grad,
+                                  float *loss) {
+    if (!m || n < 1) return SFE_EINVAL;
+    sfe_ctx *c = m->ctx;
+    return guard(c, [&] {
+        if (n > SFE_NOALLOC_MAX_SAMPLES) fail(SFE_EINVAL, "more samples than the fixed working memory holds");
+        if (!x || !t || !grad || !loss) fail(SFE_EINVAL, "null argument");
+        if (!is_device_ptr(x) || !is_device_ptr(t) || !is_device_ptr(grad) || !is_device_ptr(loss))
+            fail(SFE_EINVAL, "inputs and outputs must be device memory");
+        uint8_t *base = scratch_of(c->device);
+        if (!base) fail(SFE_EINTERNAL, "working memory of this device was not set up");
+        uint32_t *ids = (uint32_t *)base;
+        float *sse = (float *)(base + kScratchIds);
+        float *part = (float *)(base + kScratchIds + kScratchSse);
+        const int nb = (int)((n + 63) / 64);
+        k_iota<<<grid(n, 256), 256, 0, c->stream>>>(ids, n);
+        launch_mlp_grad(x, t, (const int32_t *)ids, (int32_t)n, m->p16.as<uint16_t>(), part, sse, c->stream);
+        launch_mlp_apply(part, nb, sse, (int32_t)n, grad, nullptr, nullptr, nullptr, nullptr, 0.f, 1.f, 1.f, loss,
+                         c->stream);
+        HIPCHK(hipGetLastError());
     });
 }
 

@@ -84,6 +84,7 @@ class _Stats(ctypes.Structure):
                 ("ms_predict", ctypes.c_double), ("narrow_launches", ctypes.c_int64)]
 
 MLP_NFEAT, MLP_NOUT, MLP_NPARAMS = 16, 4, 9668
+NOALLOC_MAX_SAMPLES = 16384
 
 
 def lib():
@@ -117,6 +118,7 @@ def lib():
         L.sfe_model_predict.argtypes = [P, P, I64, P]
         L.sfe_model_grad.argtypes = [P, P, P, I64, P, P]
         L.sfe_model_train.argtypes = [P, P, P, I64, P, I64, I32, ctypes.c_float, P]
+        L.sfe_model_grad_noalloc.argtypes = [P, P, P, I64, P, P]
         L.sfe_model_save.argtypes = [P, ctypes.c_char_p]
         L.sfe_model_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(P)]
         L.sfe_align_opts_resolve.argtypes = [ctypes.POINTER(_AlignOpts), ctypes.POINTER(_AlignOpts)]
@@ -127,7 +129,7 @@ def lib():
         for f in ("sfe_ctx_create", "sfe_build_index", "sfe_seed_hits", "sfe_ungapped_xdrop", "sfe_gapped_ydrop",
                   "sfe_align", "sfe_ctx_set_tuning", "sfe_ctx_get_tuning", "sfe_autotune", "sfe_hsp_features", "sfe_extension_log", "sfe_model_create", "sfe_model_params",
                   "sfe_model_predict", "sfe_model_grad", "sfe_model_train", "sfe_model_save", "sfe_model_load",
-                  "sfe_align_opts_resolve"):
+                  "sfe_align_opts_resolve", "sfe_model_grad_noalloc"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -424,6 +426,12 @@ class Model:
         loss = np.zeros(1, np.float32)
         _check(lib().sfe_model_grad(self.ptr, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss)), self.ctx)
         return float(loss[0]), g
+
+    def grad_noalloc(self, x, t, grad, loss):
+        """sfe_model_grad_noalloc on device tensors (x n x 16, t n x 4, grad 9668, loss 1, float32);
+        ordered on the context's stream, returns without waiting."""
+        _check(lib().sfe_model_grad_noalloc(self.ptr, _ptr(x), _ptr(t), int(x.shape[0]), _ptr(grad), _ptr(loss)),
+               self.ctx)
 
     def train(self, x, t, order, batch: int, lr: float) -> np.ndarray:
         x = _f32(x, (-1, MLP_NFEAT))
