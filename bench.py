@@ -167,6 +167,93 @@ def train_cost_model(ctx, sfe, synth, log_fn, T=None, Q=None, train_bp=0, index=
                        loss_last=float(losses[-1]), train_s=round(dt, 3))
 
 
+def truth_sensitivity(alns, ops, origin, qlen):
+    """Fraction of the query bases that descend from a target base (origin != -1)
+    and lie on an M column pairing them with exactly that base, in some
+    committed alignment of the right strand."""
+    found = np.zeros(qlen, dtype=bool)
+    for x in range(alns.shape[0]):
+        a = alns[x]
+        runs = ops[int(a["ops_offset"]):int(a["ops_offset"]) + int(a["ops_len"])].astype(np.int64)
+        L, op = runs >> 2, runs & 3
+        dt = np.where(op != 1, L, 0)
+        dq = np.where(op != 2, L, 0)
+        t0 = int(a["t_start"]) + np.concatenate([[0], np.cumsum(dt)[:-1]])
+        q0 = int(a["q_start"]) + np.concatenate([[0], np.cumsum(dq)[:-1]])
+        m = op == 0
+        if not m.any():
+            continue
+        reps = L[m]
+        off = np.arange(int(reps.sum())) - np.repeat(np.cumsum(reps) - reps, reps)
+        t = np.repeat(t0[m], reps) + off
+        q = np.repeat(q0[m], reps) + off
+        if int(a["strand"]) == 0:
+            ok = origin[q] == t
+            found[q[ok]] = True
+        else:
+            qf = qlen - 1 - q
+            ok = origin[qf] == -2 - t
+            found[qf[ok]] = True
+    hom = origin != -1
+    return float(found[hom].sum() / max(int(hom.sum()), 1))
+
+
+def seed_study(ctx, sfe, synth, sc, log_fn):
+    """Spaced seeds on the 1 Mbp pair with its truth map: the paper's 12-of-19
+    seed with one transition (step 1) against this project's 14-of-22 seed
+    (step 1 and 2): hits, HSPs, alignments, time and sensitivity."""
+    import torch
+    T, Q, origin = synth.pair_small(truth=True)
+    dev = torch.device("cuda:0")
+    Td, Qd = torch.from_numpy(T).to(dev), [torch.from_numpy(Q[0]).to(dev)]
+    out = []
+    for name, pattern, step in (("12-of-19", synth.SEED_PATTERN, 1), ("14-of-22", synth.SEED_PATTERN_14, 1),
+                                ("14-of-22", synth.SEED_PATTERN_14, 2)):
+        idx = sfe.sfe_build_index(ctx, Td, pattern, 1, step)
+        sfe.sfe_align(ctx, idx, Qd, sc, cap=1 << 16, ops_cap=1 << 24)           # warm-up
+        t0 = time.perf_counter()
+        a, o, st = sfe.sfe_align(ctx, idx, Qd, sc, cap=1 << 16, ops_cap=1 << 24)
+        ms = 1e3 * (time.perf_counter() - t0)
+        idx.close()
+        sens = truth_sensitivity(a, o, origin, Q[0].shape[0])
+        out.append(dict(seed=name, pattern=pattern, step=step, seed_hits=st["seed_hits"], hsps=st["hsps"],
+                        alignments=st["committed"], ms_seed_xdrop=round(st["ms_seed_xdrop"], 2),
+                        ms_total=round(ms, 2), sensitivity=round(sens, 5)))
+        log_fn(f"seed {name} step {step}: {st['seed_hits']} hits, {st['hsps']} HSPs, {st['committed']} alignments, "
+               f"{ms:.0f} ms, sensitivity {sens:.4f}")
+    return dict(workload="1 Mbp target vs 1 Mbp query (15% divergence, 3 + 3 SVs), truth map of every query base",
+                seeds=out)
+
+
+def k_sweep(ctx, sfe, synth, sc, Td, Q0d, index, sample_bp, log_fn):
+    """Alg. 3's batch size and the two speculation policies on the first
+    sample_bp query bases: rounds, extensions, shadow work and time (the
+    trade-off of the paper's Sec. 6); every configuration must give the same
+    alignments."""
+    q = [Q0d[:sample_bp]]
+    idx = index or sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
+    rows, ref = [], None
+    for policy in (sfe.SFE_POLICY_PREFIX, sfe.SFE_POLICY_DEFER):
+        for K in (48, 64, 256, 4096, 1 << 20):
+            a, o, st = sfe.sfe_align(ctx, idx, q, sc, round_k=K, policy=policy, cap=1 << 18, ops_cap=1 << 24)
+            same = True
+            if ref is None:
+                ref = (a, o)
+            else:
+                same = bool(np.array_equal(a, ref[0]) and np.array_equal(o, ref[1]))
+            needed = st["extensions"] - st["shadow"]
+            rows.append(dict(policy="prefix" if policy == sfe.SFE_POLICY_PREFIX else "defer", round_k=K,
+                             rounds=st["rounds"], extensions=st["extensions"], shadow=st["shadow"],
+                             shadow_fraction=round(st["shadow"] / max(needed, 1), 4), cells=st["cells"],
+                             ms_extend=round(st["ms_extend"], 2), ms_total=round(st["ms_total"], 2),
+                             identical=same))
+            log_fn(f"K sweep {rows[-1]['policy']} K={K}: {st['rounds']} rounds, {st['extensions']} extensions, "
+                   f"{st['shadow']} shadow, {st['ms_extend']:.0f} ms extend")
+    if idx is not index:
+        idx.close()
+    return dict(sample=f"first {sample_bp} query bases vs the full target", rows=rows)
+
+
 def kernel_sources_digest():
     """Digest of the extension kernel's source and every header it includes (the
     stored HBM traffic figure is valid only for exactly these files)."""
@@ -206,6 +293,8 @@ def main():
                     help="query bases whose HSP extensions train the cost model (-1: default)")
     ap.add_argument("--cpu-sample-bp", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-studies", action="store_true", help="skip the seed study and the K sweep")
+    ap.add_argument("--sweep-bp", type=int, default=1_000_000, help="query bases of the K sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path (queries would shard by unit)",
@@ -345,6 +434,12 @@ def main():
     roofline = dict(bound="alu", achieved=round(achieved, 4), peak=round(peak, 2), unit=unit,
                     frac=round(achieved / peak, 5), traffic=traffic, kernel=dominant, note=note)
 
+    seeds, sweep = None, None
+    if not args.no_studies:
+        sfe.sfe_ctx_set_tuning(ctx)
+        seeds = seed_study(ctx, sfe, synth, sc, log)
+        sweep = k_sweep(ctx, sfe, synth, sc, Td, Qd[0], resident, args.sweep_bp, log)
+
     cpu, parity_ok = None, None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -416,6 +511,8 @@ def main():
         "peak_hbm_used_bytes": int(peak_used[0]),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "seed_study": seeds,
+        "k_sweep": sweep,
     }
     print(json.dumps(line), flush=True)
 

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfe.so")
-SOURCES = ["api.hip", "k_seed.hip", "k_extend.hip", "k_fused.hip", "k_learn.hip"]
+SOURCES = ["api.hip", "k_seed.hip", "k_extend.hip", "k_fused.hip", "k_learn.hip", "k_sort.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -2,8 +2,6 @@
 // host side of the speculative batched pipeline (Alg. 3 of the paper: a
 // serial scan picks a batch, the GPU extends it, a serial commit keeps the
 // result equal to the strict serial Alg. 1).
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 #include <cmath>
 #include <chrono>
@@ -253,19 +251,15 @@ int max_abs_sub(const ScoreDesc &d) {
 }
 
 template <class T>
-void cub_exclusive_sum(sfe_ctx *c, const T *in, T *out, int64_t n) {
-    size_t bytes = 0;
-    HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, c->stream));
-    c->cub_temp.ensure(bytes);
-    HIPCHK(hipcub::DeviceScan::ExclusiveSum(c->cub_temp.p, bytes, in, out, (int)n, c->stream));
+void exclusive_sum(sfe_ctx *c, const T *in, T *out, int64_t n) {
+    uint64_t *work = (uint64_t *)c->cub_temp.ensure((size_t)scan_work_words(n) * 8);
+    scan_exclusive<T, T>(in, out, n, work, c->stream);
 }
 
-void cub_sort_pairs(sfe_ctx *c, const uint32_t *kin, uint32_t *kout, const uint32_t *vin, uint32_t *vout, int64_t n,
-                    int end_bit) {
-    size_t bytes = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, (int)n, 0, end_bit, c->stream));
-    c->cub_temp.ensure(bytes);
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(c->cub_temp.p, bytes, kin, kout, vin, vout, (int)n, 0, end_bit, c->stream));
+template <class K>
+void sort_pairs(sfe_ctx *c, const K *kin, K *kout, const uint32_t *vin, uint32_t *vout, int64_t n, int end_bit) {
+    void *temp = c->cub_temp.ensure((size_t)radix_temp_bytes(n, (int)sizeof(K)));
+    radix_sort_pairs<K>(kin, kout, vin, vout, n, end_bit, temp, c->stream);
 }
 
 // Uploads the queries (both strands) and describes the (query, strand) units
@@ -316,12 +310,12 @@ int64_t hsp_set(sfe_ctx *c, const sfe_hsp *h, int64_t n) {
     // least significant field first; radix sort is stable
     for (int field = 0; field < 6; field++) {
         k_hsp_key<<<grid(n, 256), 256, 0, c->stream>>>(h, perm, n, field, key);
-        cub_sort_pairs(c, key, key2, perm, perm2, n, field == 3 ? 1 : 32);
+        sort_pairs<uint32_t>(c, key, key2, perm, perm2, n, field == 3 ? 1 : 32);
         std::swap(perm, perm2);
     }
     uint32_t *flag = key, *dst = key2;
     k_hsp_unique_flags<<<grid(n, 256), 256, 0, c->stream>>>(h, perm, n, flag);
-    cub_exclusive_sum(c, flag, dst, n);
+    exclusive_sum<uint32_t>(c, flag, dst, n);
     k_hsp_compact<<<grid(n, 256), 256, 0, c->stream>>>(h, perm, flag, dst, n, c->hsp_sorted.as<sfe_hsp>());
     uint32_t lastf = 0, lastd = 0;
     HIPCHK(hipMemcpyAsync(&lastf, flag + n - 1, 4, hipMemcpyDeviceToHost, c->stream));
@@ -804,10 +798,7 @@ void compute_features(sfe_ctx *c, const sfe_index *ix, const QueryLayout &L, int
     const size_t NU = std::max<size_t>(L.units.size(), 1);
     int64_t *range = (int64_t *)c->feat_range.ensure(2 * NU * 8);
     launch_hsp_anchor_keys(h, n, uo, key, ids, c->stream);
-    size_t bytes = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, key, key2, ids, order, (int)n, 0, 64, c->stream));
-    c->cub_temp.ensure(bytes);
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(c->cub_temp.p, bytes, key, key2, ids, order, (int)n, 0, 64, c->stream));
+    sort_pairs<uint64_t>(c, key, key2, ids, order, n, 64);
     HIPCHK(hipMemsetAsync(range, 0, 2 * NU * 8, c->stream));
     launch_hsp_unit_ranges(h, uo, order, n, okey, range, range + NU, c->stream);
     launch_hsp_features(h, n, uo, c->units_d.as<UnitDesc>(), ix->target.view(), ix->nt, c->qplus.view(),
@@ -834,17 +825,18 @@ std::vector<sfe_hsp> checked_hsps(sfe_ctx *c, const sfe_index *ix, const sfe_seq
 // Bounding boxes of committed alignments of one unit, binned by target position.
 struct BoxGrid {
     static const int SH = 14;
-    std::unordered_map<int64_t, std::vector<int32_t>> bins;
+    std::vector<std::vector<int32_t>> bins;     // by target position >> SH
     std::vector<sfe_aln> boxes;
+    void reset(int64_t nt) { bins.assign((size_t)(nt >> SH) + 2, {}); boxes.clear(); }
     void add(const sfe_aln &a) {
         int32_t id = (int32_t)boxes.size();
         boxes.push_back(a);
-        for (int64_t b = a.t_start >> SH; b <= ((int64_t)a.t_end - 1) >> SH; b++) bins[b].push_back(id);
+        for (int64_t b = a.t_start >> SH; b <= ((int64_t)a.t_end - 1) >> SH; b++) bins[(size_t)b].push_back(id);
     }
     bool inside(uint32_t t, uint32_t q) const {
-        auto it = bins.find((int64_t)t >> SH);
-        if (it == bins.end()) return false;
-        for (int32_t id : it->second) {
+        const size_t b = (size_t)(t >> SH);
+        if (b >= bins.size() || bins[b].empty()) return false;
+        for (int32_t id : bins[b]) {
             const sfe_aln &a = boxes[id];
             if (a.t_start <= t && t < a.t_end && a.q_start <= q && q < a.q_end) return true;
         }
@@ -863,7 +855,8 @@ struct PathSet {
     std::vector<Path> paths;
     std::vector<uint32_t> rt, rl;      // run start (target) and length
     std::vector<int32_t> rd;           // run diagonal minus the alignment's start diagonal
-    std::unordered_map<uint32_t, std::vector<uint32_t>> bins;
+    std::vector<std::vector<uint32_t>> bins;    // by target position >> SH
+    void reset(int64_t nt) { bins.assign((size_t)(nt >> SH) + 2, {}); }
     void add(const sfe_aln &a, const uint32_t *ops, size_t owner) {
         Path P{a.t_start, a.t_end, a.q_start, a.q_end, owner, rt.size(), 0};
         uint32_t t = a.t_start, q = a.q_start;
@@ -892,9 +885,9 @@ struct PathSet {
     // search) and then `post` (tested only on a match)
     template <class Pre, class Post>
     bool contains(uint32_t t, uint32_t q, Pre pre, Post post) const {
-        auto it = bins.find(t >> SH);
-        if (it == bins.end()) return false;
-        for (uint32_t id : it->second) {
+        const size_t b = (size_t)(t >> SH);
+        if (b >= bins.size()) return false;
+        for (uint32_t id : bins[b]) {
             const Path &P = paths[id];
             if (t < P.t0 || t >= P.t1 || q < P.q0 || q >= P.q1 || !pre(P.owner)) continue;
             // last run starting at or before t
@@ -1095,7 +1088,7 @@ sfe_status sfe_build_index(sfe_ctx *c, const sfe_seq *target, const sfe_seed_spe
         ix->offsets.ensure(((size_t)ix->K + 1) * 4);
         if (nslots > 0) {
             k_index_keys<<<grid(nslots, 256), 256, 0, c->stream>>>(ix->target.view(), nslots, sd.step, sd, ix->K, keys, pos0);
-            cub_sort_pairs(c, keys, keys2, pos0, ix->pos.as<uint32_t>(), nslots, 2 * sd.weight + 1);
+            sort_pairs<uint32_t>(c, keys, keys2, pos0, ix->pos.as<uint32_t>(), nslots, 2 * sd.weight + 1);
         }
         k_offsets<<<grid(nslots + 1, 256), 256, 0, c->stream>>>(keys2, nslots, ix->K, ix->offsets.as<uint32_t>());
         HIPCHK(hipGetLastError());
@@ -1135,7 +1128,7 @@ sfe_status sfe_seed_hits(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries
         SeqSetView Qp = c->qplus.view(), Qm = c->qminus.view();
         k_seed_count<<<(unsigned)nch, 64, 0, c->stream>>>(c->units_d.as<UnitDesc>(), c->chunks_d.as<Chunk>(), Qp, Qm,
                                                          ix->offsets.as<uint32_t>(), ix->sd, cnt);
-        cub_exclusive_sum(c, cnt, off, nch * 64);
+        exclusive_sum<uint64_t>(c, cnt, off, nch * 64);
         uint64_t lastc = 0, lasto = 0;
         HIPCHK(hipMemcpyAsync(&lastc, cnt + nch * 64 - 1, 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipMemcpyAsync(&lasto, off + nch * 64 - 1, 8, hipMemcpyDeviceToHost, c->stream));
@@ -1371,12 +1364,15 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             ext[u].resize(n);
             ext_batch[u].assign(n, 0);
             paths[u].committed.assign(n, 0);
+            paths[u].set.reset(ix->nt);
             doom_stamp[u].assign(n, 0);
             doom_val[u].assign(n, 0);
             doom_perm[u].assign(n, 0);
         }
         std::vector<size_t> cursor(NU, 0);
         std::vector<BoxGrid> boxes(NU);
+        if (o.policy == SFE_POLICY_DEFER)
+            for (size_t u = 0; u < NU; u++) boxes[u].reset(ix->nt);
         std::vector<sfe_aln> committed;
         std::vector<uint32_t> cops;
         std::vector<ExtItem> items;
@@ -1415,6 +1411,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         double host_ms = 0, book_ms = 0, commit_ms = 0;
         std::vector<std::vector<uint16_t>> why(progress ? NU : 0);   // deferrals by path (lo byte) and nearness (hi)
         for (size_t u = 0; u < why.size(); u++) why[u].assign(per_unit[u].size(), 0);
+        std::vector<uint64_t> near_bits;       // nearness rule: diagonals taken (per unit, cleared after it)
+        std::vector<size_t> near_touched;
         for (;;) {
             const double th = now_ms();
             items.clear();
@@ -1424,7 +1422,10 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 auto &lst = per_unit[u];
                 auto &stt = state[u];
                 int64_t taken = 0;
-                std::unordered_map<int64_t, std::vector<int64_t>> near;   // diagonal bucket -> selected diagonals
+                // diagonals of the HSPs this batch has taken so far in the unit (bit d + qlen)
+                const int64_t qlen = L.units[u].len;
+                const size_t nwords = (size_t)((ix->nt + qlen + std::max<int64_t>(DB, 0) + 1) / 64 + 2);
+                if (near_bits.size() < nwords) near_bits.resize(nwords, 0);
                 std::vector<size_t> still;
                 still.reserve(open[u].size());
                 size_t q = 0;
@@ -1445,21 +1446,23 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                         // inside a committed alignment but off its path: such HSPs are extended
                         // side by side (each may start a separate alignment of the region)
                         if (DB > 0) {
-                            const int64_t d = (int64_t)ta - (int64_t)qa;
-                            const int64_t b = d >= 0 ? d / DB : -((-d + DB - 1) / DB);
+                            const int64_t x = (int64_t)ta - (int64_t)qa + qlen;
+                            const int64_t lo = std::max<int64_t>(0, x - DB), hi = x + DB;
                             bool close = false;
-                            for (int64_t bb = b - 1; bb <= b + 1 && !close; bb++) {
-                                auto it = near.find(bb);
-                                if (it == near.end()) continue;
-                                for (int64_t dd : it->second)
-                                    if (std::llabs(dd - d) <= DB) { close = true; break; }
+                            for (int64_t w = lo >> 6; w <= (hi >> 6) && !close; w++) {
+                                uint64_t m = near_bits[(size_t)w];
+                                if (w == (lo >> 6)) m &= ~0ull << (lo & 63);
+                                if (w == (hi >> 6)) m &= (hi & 63) == 63 ? ~0ull : ((2ull << (hi & 63)) - 1);
+                                close = m != 0;
                             }
                             if (close && !boxes[u].inside(ta, qa)) {                      // likely the same region
                                 if (progress) why[u][p] += 256;
                                 still.push_back(p);
                                 continue;
                             }
-                            near[b].push_back(d);
+                            uint64_t &word = near_bits[(size_t)(x >> 6)];
+                            if (!word) near_touched.push_back((size_t)(x >> 6));
+                            word |= 1ull << (x & 63);
                         }
                     }
                     items.push_back(ExtItem{ta, qa, (int32_t)u, 0});
@@ -1470,6 +1473,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 for (; q < open[u].size(); q++)
                     if (stt[open[u][q]] == 0) still.push_back(open[u][q]);
                 open[u].swap(still);
+                for (size_t w : near_touched) near_bits[w] = 0;
+                near_touched.clear();
             }
             host_ms += now_ms() - th;
             if (items.empty()) break;

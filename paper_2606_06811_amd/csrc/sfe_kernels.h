@@ -56,6 +56,16 @@ __global__ void k_seed_xdrop(const UnitDesc *units, const Chunk *chunks, SeqSetV
                              ScoreDesc sc, sfe_hsp *out, uint64_t cap, unsigned long long *counters);
 __global__ void k_hsp_key(const sfe_hsp *h, const uint32_t *perm, int64_t n, int field, uint32_t *key);
 __global__ void k_iota(uint32_t *a, int64_t n);
+
+// k_sort.hip: stable LSD radix sort of (key, u32 value) pairs over key bits [0, end_bit), and the
+// exclusive prefix sum; both count in 64 bits.  radix_temp_bytes / scan_work_words size their scratch.
+template <typename K>
+void radix_sort_pairs(const K *kin, K *kout, const uint32_t *vin, uint32_t *vout, int64_t n, int end_bit, void *temp,
+                      hipStream_t st);
+int64_t radix_temp_bytes(int64_t n, int key_bytes);
+template <typename T, typename O>
+void scan_exclusive(const T *in, O *out, int64_t n, uint64_t *work, hipStream_t st);
+int64_t scan_work_words(int64_t n);
 __global__ void k_hsp_unique_flags(const sfe_hsp *h, const uint32_t *perm, int64_t n, uint32_t *flag);
 __global__ void k_hsp_compact(const sfe_hsp *h, const uint32_t *perm, const uint32_t *flag, const uint32_t *dst,
                               int64_t n, sfe_hsp *out);

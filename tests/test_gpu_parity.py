@@ -68,20 +68,22 @@ def oracle_units(T, Q, strands=3):
 # ---------------------------------------------------------------------------
 # seeds
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("transitions,step,strands", [(1, 1, 3), (0, 1, 3), (1, 3, 1), (1, 1, 2)])
-def test_seed_hits_parity(ctx, transitions, step, strands):
-    log(f"seed parity transitions={transitions} step={step} strands={strands}")
+@pytest.mark.parametrize("transitions,step,strands,pattern", [
+    (1, 1, 3, PATTERN), (0, 1, 3, PATTERN), (1, 3, 1, PATTERN), (1, 1, 2, PATTERN),
+    (1, 1, 3, synth.SEED_PATTERN_14), (1, 2, 3, synth.SEED_PATTERN_14)])
+def test_seed_hits_parity(ctx, transitions, step, strands, pattern):
+    log(f"seed parity transitions={transitions} step={step} strands={strands} pattern={pattern}")
     T, Q = make_pair(n=40_000, seed=5, nq=2)
-    idx = sfe.sfe_build_index(ctx, T, PATTERN, transitions, step)
+    idx = sfe.sfe_build_index(ctx, T, pattern, transitions, step)
     got = sfe.sfe_seed_hits(ctx, idx, Q, strands)
     want = []
     for qid, s, tc, ts, c, m in oracle_units(T, Q, strands):
-        t, q = oracle.seed_hits(tc, ts, c, m, PATTERN, transitions, step)
+        t, q = oracle.seed_hits(tc, ts, c, m, pattern, transitions, step)
         w = np.zeros(t.shape[0], sfe.HIT_DTYPE)
         w["t"], w["q"], w["query_id"], w["strand"] = t, q, qid, s
         want.append(w)
     want = np.concatenate(want)
-    assert want.shape[0] > 1000
+    assert want.shape[0] > (1000 if pattern == PATTERN else 100)
     assert got.shape == want.shape
     for f in ("t", "q", "query_id", "strand"):
         assert np.array_equal(got[f], want[f]), f
