@@ -203,26 +203,36 @@ def seed_study(ctx, sfe, synth, sc, log_fn):
     seed with one transition (step 1) against this project's 14-of-22 seed
     (step 1 and 2): hits, HSPs, alignments, time and sensitivity."""
     import torch
-    T, Q, origin = synth.pair_small(truth=True)
     dev = torch.device("cuda:0")
-    Td, Qd = torch.from_numpy(T).to(dev), [torch.from_numpy(Q[0]).to(dev)]
     out = []
-    for name, pattern, step in (("12-of-19", synth.SEED_PATTERN, 1), ("14-of-22", synth.SEED_PATTERN_14, 1),
-                                ("14-of-22", synth.SEED_PATTERN_14, 2)):
+    X, Yf = sfe.SFE_FILTER_XDROP, sfe.SFE_FILTER_YDROP
+    cases = [(div, name, pattern, step, flt) for div in (0.15, 0.30)
+             for name, pattern, step, flt in (("12-of-19", synth.SEED_PATTERN, 1, X),
+                                              ("14-of-22", synth.SEED_PATTERN_14, 1, X),
+                                              ("14-of-22", synth.SEED_PATTERN_14, 2, X),
+                                              ("12-of-19", synth.SEED_PATTERN, 1, Yf))]
+    pairs = {}
+    for div, name, pattern, step, flt in cases:
+        if div not in pairs:
+            pairs[div] = synth.pair_small(divergence=div, truth=True)
+        T, Q, origin = pairs[div]
+        Td, Qd = torch.from_numpy(T).to(dev), [torch.from_numpy(Q[0]).to(dev)]
         idx = sfe.sfe_build_index(ctx, Td, pattern, 1, step)
-        sfe.sfe_align(ctx, idx, Qd, sc, cap=1 << 16, ops_cap=1 << 24)           # warm-up
+        sfe.sfe_align(ctx, idx, Qd, sc, cap=1 << 16, ops_cap=1 << 24, filter=flt)           # warm-up
         t0 = time.perf_counter()
-        a, o, st = sfe.sfe_align(ctx, idx, Qd, sc, cap=1 << 16, ops_cap=1 << 24)
+        a, o, st = sfe.sfe_align(ctx, idx, Qd, sc, cap=1 << 16, ops_cap=1 << 24, filter=flt)
         ms = 1e3 * (time.perf_counter() - t0)
         idx.close()
         sens = truth_sensitivity(a, o, origin, Q[0].shape[0])
-        out.append(dict(seed=name, pattern=pattern, step=step, seed_hits=st["seed_hits"], hsps=st["hsps"],
+        out.append(dict(divergence=div, seed=name, pattern=pattern, step=step,
+                        filter="ydrop" if flt == Yf else "xdrop", seed_hits=st["seed_hits"], hsps=st["hsps"],
                         alignments=st["committed"], ms_seed_xdrop=round(st["ms_seed_xdrop"], 2),
                         ms_total=round(ms, 2), sensitivity=round(sens, 5)))
-        log_fn(f"seed {name} step {step}: {st['seed_hits']} hits, {st['hsps']} HSPs, {st['committed']} alignments, "
+        log_fn(f"{div:.2f} divergence, seed {name} step {step}, {'ydrop' if flt == Yf else 'xdrop'} filter: "
+               f"{st['seed_hits']} hits, {st['hsps']} HSPs, {st['committed']} alignments, "
                f"{ms:.0f} ms, sensitivity {sens:.4f}")
-    return dict(workload="1 Mbp target vs 1 Mbp query (15% divergence, 3 + 3 SVs), truth map of every query base",
-                seeds=out)
+    return dict(workload="1 Mbp target vs 1 Mbp query (15% and 30% divergence, 3 + 3 SVs), truth map of every "
+                         "query base", seeds=out)
 
 
 def k_sweep(ctx, sfe, synth, sc, Td, Q0d, index, sample_bp, log_fn):
@@ -332,7 +342,8 @@ def main():
         log(f"position table of the {T.shape[0]} bp target built in {index_ms:.0f} ms")
 
     model, train_info, tune_info = None, None, None
-    tuned = dict(max_cells_per_lane=args.cpl, schedule=sfe.SFE_SCHED_ADAPTIVE, wave_group_cap=0)
+    tuned = dict(max_cells_per_lane=args.cpl, schedule=sfe.SFE_SCHED_ADAPTIVE, wave_group_cap=0,
+                 persist_waves_per_cu=0)
     if args.schedule in ("learned", "both"):
         model, train_info = train_cost_model(ctx, sfe, synth, log, Td, Qd[:1], args.train_bp, resident)
         if args.tune_bp > 0:
@@ -361,7 +372,8 @@ def main():
             out = sfe.sfe_align(ctx, idx, q, sc, schedule=sfe.SFE_SCHED_PLAIN, max_cells_per_lane=args.cpl,
                                 **common)
         else:
-            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=tuned["wave_group_cap"])
+            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=tuned["wave_group_cap"],
+                                   persist_waves_per_cu=tuned.get("persist_waves_per_cu", 0))
             out = sfe.sfe_align(ctx, idx, q, sc, schedule=tuned["schedule"], model=model,
                                 max_cells_per_lane=tuned["max_cells_per_lane"], **common)
         if idx is not resident:

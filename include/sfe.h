@@ -162,7 +162,20 @@ typedef struct {
     const struct sfe_model *model; /* NULL, or a cost model: with SFE_SCHED_PERSISTENT or
                                SFE_SCHED_ADAPTIVE the halves of each batch are queued (or
                                launched) longest-predicted first.  Never changes the output. */
+    int32_t filter;         /* SFE_FILTER_XDROP (0, default) or SFE_FILTER_YDROP */
+    int32_t pad;
 } sfe_align_opts;
+
+/* Filters of sfe_align.  XDROP: the ungapped X-drop extension of every seed
+ * hit (Sec. 3, Sec. 8).  YDROP: the two-dimensional filter the paper proposes
+ * in its place (Sec. 8, Sec. 9): both gapped halves of every hit around the
+ * middle column of its seed window, pruned with Y := xdrop (sfe_gapped_ydrop's
+ * rules); a hit whose total reaches hsp_thresh becomes an HSP spanning its
+ * seed window (t, q, span) with that total as score, and the pipeline goes on
+ * as with X-drop HSPs.  sfe_stats.xdrop_columns then counts the filter's DP
+ * cells. */
+#define SFE_FILTER_XDROP 0
+#define SFE_FILTER_YDROP 1
 
 /* The options sfe_align runs with: *in (NULL: all zero) with every automatic
  * field filled in -- strands 3; max_cells_per_lane 6 (others clamped into
@@ -278,20 +291,21 @@ sfe_status sfe_ctx_get_tuning(const sfe_ctx *ctx, sfe_tuning *t);
 
 /* Autotuner.  Times sfe_align on a sample of the workload (the first
  * sample_bases of every query, all against idx) under each candidate schedule
- * -- rows per lane 6 / 8 in the first band window; plain, persistent or
+ * -- rows per lane 4 / 6 in the first band window; plain, persistent or
  * adaptive launch, only the last two (with the model) when opts->model is
- * given; wave groups for long halves off or after 8192 antidiagonals --
- * three times each, and keeps the fastest (by its best time): the
- * context's wave_group_cap is set and opts->max_cells_per_lane / schedule are
+ * given; 8 or 16 waves per compute unit for the persistent grid; wave groups
+ * for long halves off or after 8192 antidiagonals -- three times each, and
+ * keeps the fastest (by its best time): the context's wave_group_cap and
+ * persist_waves_per_cu are set and opts->max_cells_per_lane / schedule are
  * written.  Other fields of *opts are used as given.  report (may be NULL)
  * receives every candidate's extension time.  No choice changes results. */
 typedef struct {
-    int32_t cells_per_lane, schedule, wave_group_cap, pad;
+    int32_t cells_per_lane, schedule, wave_group_cap, waves_per_cu;
     double ms_extend;
 } sfe_tune_entry;
 typedef struct {
     int32_t n, best;
-    sfe_tune_entry entries[16];
+    sfe_tune_entry entries[32];
 } sfe_tune_report;
 sfe_status sfe_autotune(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries, int32_t nq,
                         const sfe_scoring *sc, int64_t sample_bases, sfe_align_opts *opts,

@@ -140,6 +140,21 @@ def xdrop(tc, qc, t, q, span, sc: dict) -> np.ndarray:
     return out
 
 
+def ydrop_filter(tc, qc, t, q, span, sc: dict) -> np.ndarray:
+    """The two-dimensional filter proposed in place of X-drop (Sec. 8, Sec. 9):
+    both gapped halves around the middle column of each hit's seed window,
+    pruned with Y := the X-drop value; the hit's window becomes an HSP carrying
+    that total (kept when it reaches the HSP threshold, as X-drop HSPs are)."""
+    fsc = dict(sc)
+    fsc["ydrop"] = sc["xdrop"]
+    off = (span - 1) // 2
+    out = np.zeros(np.asarray(t).shape[0], HSP_DTYPE)
+    for x in range(out.shape[0]):
+        a, _ = extend(tc, qc, int(t[x]) + off, int(q[x]) + off, fsc)
+        out[x] = (int(t[x]), int(q[x]), span, int(a["score"]), int(a["cells"]))
+    return out
+
+
 def hsp_set(hsps: np.ndarray, hsp_thresh: int) -> np.ndarray:
     """Passing HSPs of one (query, strand) unit, exact duplicates collapsed,
     in the order the serial algorithm walks them: score descending, then
@@ -201,9 +216,10 @@ def commit_unit(tc, qc, hsps: np.ndarray, sc: dict, K: int = 0, query_id: int = 
 
 
 def pipeline(target, queries, sc: dict, pattern="1110100110010101111", transitions=1, step=1,
-             strands=3, K=0):
-    """The whole path for ASCII target/queries: seeds -> X-drop -> HSP set ->
-    Alg. 1 (or Alg. 3 with batch size K) per (query, strand).  Returns a dict
+             strands=3, K=0, filter="xdrop"):
+    """The whole path for ASCII target/queries: seeds -> X-drop (or the 2-D
+    Y-drop filter, filter="ydrop") -> HSP set -> Alg. 1 (or Alg. 3 with batch
+    size K) per (query, strand).  Returns a dict
     with per-unit hits and HSPs, and the committed alignments (ordered by
     query, strand, t_start, q_start, t_end, q_end, anchor_t, anchor_q) with
     their run-length ops."""
@@ -220,7 +236,7 @@ def pipeline(target, queries, sc: dict, pattern="1110100110010101111", transitio
                 continue
             qc, qs = (qc0, qs0) if strand == 0 else revcomp(qc0, qs0)
             t, q = seed_hits(tc, ts, qc, qs, pattern, transitions, step)
-            raw = xdrop(tc, qc, t, q, span, sc)
+            raw = xdrop(tc, qc, t, q, span, sc) if filter == "xdrop" else ydrop_filter(tc, qc, t, q, span, sc)
             hs = hsp_set(raw, sc["hsp_thresh"])
             alns, ops, ne, nc = commit_unit(tc, qc, hs, sc, K, qid, strand)
             n_ext += ne

@@ -781,6 +781,32 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     }
 }
 
+// All seed hits of the uploaded units (L) into c->tmp_c, in (unit, q, t)
+// order; returns their number.
+int64_t seed_hits_device(sfe_ctx *c, const sfe_index *ix, const QueryLayout &L, sfe_hit **hits) {
+    const int64_t nch = (int64_t)L.chunks.size();
+    *hits = nullptr;
+    if (nch == 0) return 0;
+    uint64_t *cnt = (uint64_t *)c->tmp_d.ensure((size_t)nch * 64 * 8);
+    uint64_t *off = (uint64_t *)c->tmp_e.ensure((size_t)nch * 64 * 8);
+    SeqSetView Qp = c->qplus.view(), Qm = c->qminus.view();
+    k_seed_count<<<(unsigned)nch, 64, 0, c->stream>>>(c->units_d.as<UnitDesc>(), c->chunks_d.as<Chunk>(), Qp, Qm,
+                                                     ix->offsets.as<uint32_t>(), ix->sd, cnt);
+    exclusive_sum<uint64_t>(c, cnt, off, nch * 64);
+    uint64_t lastc = 0, lasto = 0;
+    HIPCHK(hipMemcpyAsync(&lastc, cnt + nch * 64 - 1, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&lasto, off + nch * 64 - 1, 8, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    const int64_t total = (int64_t)(lastc + lasto);
+    if (total == 0) return 0;
+    sfe_hit *dst = (sfe_hit *)c->tmp_c.ensure((size_t)total * sizeof(sfe_hit));
+    k_seed_emit<<<(unsigned)nch, 64, 0, c->stream>>>(c->units_d.as<UnitDesc>(), c->chunks_d.as<Chunk>(), Qp, Qm,
+                                                    ix->offsets.as<uint32_t>(), ix->pos.as<uint32_t>(), ix->sd, off, dst);
+    HIPCHK(hipGetLastError());
+    *hits = dst;
+    return total;
+}
+
 // Features (n x 16, device) of n device HSPs; the units of L give each
 // (query, strand) its sequence; neighbours are HSPs of the same unit.
 void compute_features(sfe_ctx *c, const sfe_index *ix, const QueryLayout &L, int32_t nq, const sfe_hsp *h, int64_t n,
@@ -1245,6 +1271,7 @@ sfe_status sfe_align_opts_resolve(const sfe_align_opts *in, sfe_align_opts *out)
     if (o.schedule < SFE_SCHED_PLAIN || o.schedule > SFE_SCHED_ADAPTIVE) return SFE_EINVAL;
     if (o.policy != SFE_POLICY_DEFER && o.policy != SFE_POLICY_PREFIX) return SFE_EINVAL;
     if (o.arena_bytes < 0) return SFE_EINVAL;
+    if (o.filter != SFE_FILTER_XDROP && o.filter != SFE_FILTER_YDROP) return SFE_EINVAL;
     if (o.max_cells_per_lane == 0) o.max_cells_per_lane = 6;
     if (o.max_cells_per_lane < 0) return SFE_EINVAL;
     o.max_cells_per_lane = std::min(8, std::max(2, o.max_cells_per_lane));
@@ -1284,7 +1311,41 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         const double t1 = now_ms();
         int64_t nch = (int64_t)L.chunks.size();
         int64_t nraw = 0;
-        if (nch > 0) {
+        if (nch > 0 && o.filter == SFE_FILTER_YDROP) {
+            // the 2-D filter: both gapped halves of every seed hit around its middle column,
+            // pruned at the X-drop value; a hit whose total reaches hsp_thresh becomes an HSP
+            // spanning its seed window
+            sfe_hit *hd = nullptr;
+            const int64_t nhit = seed_hits_device(c, ix, L, &hd);
+            st.seed_hits = nhit;
+            // every hit becomes one extension item of a single batch (host records per half)
+            if (nhit > ((int64_t)1 << 27)) fail(SFE_ENOMEM, "more than 2^27 seed hits for the 2-D filter");
+            std::vector<sfe_hit> hits((size_t)nhit);
+            copy_out(c, hits.data(), hd, (size_t)nhit * sizeof(sfe_hit));
+            sync(c);
+            std::vector<int32_t> uo(2 * (size_t)std::max(nq, 1), -1);
+            for (size_t u = 0; u < L.units.size(); u++) uo[2 * L.units[u].query_id + L.units[u].strand] = (int32_t)u;
+            const uint32_t off = (uint32_t)(ix->sd.span - 1) / 2;
+            std::vector<ExtItem> fit((size_t)nhit);
+            for (int64_t x = 0; x < nhit; x++)
+                fit[x] = ExtItem{hits[x].t + off, hits[x].q + off, uo[2 * hits[x].query_id + hits[x].strand], 0};
+            ScoreDesc fsc = sc;
+            fsc.ydrop = sc.xdrop;
+            fsc.gapped_thresh = sc.hsp_thresh;
+            BatchResult fb;
+            run_batch(c, ix, fit, fsc, cpl, SFE_SCHED_PLAIN, fb);
+            std::vector<sfe_hsp> pass;
+            for (int64_t x = 0; x < nhit; x++) {
+                st.xdrop_columns += (int64_t)fb.alns[x].cells;
+                if (fb.alns[x].score >= sc.hsp_thresh)
+                    pass.push_back(sfe_hsp{hits[x].t, hits[x].q, (uint32_t)ix->sd.span, fb.alns[x].score,
+                                           hits[x].query_id, hits[x].strand, {0, 0, 0}});
+            }
+            nraw = (int64_t)pass.size();
+            sfe_hsp *raw = (sfe_hsp *)c->hsp_raw.ensure((size_t)std::max<int64_t>(nraw, 1) * sizeof(sfe_hsp));
+            copy_in(c, raw, pass.data(), (size_t)nraw * sizeof(sfe_hsp));
+            sync(c);
+        } else if (nch > 0) {
             uint64_t capraw = std::max<uint64_t>(c->hsp_raw.n / sizeof(sfe_hsp), 1u << 23);
             for (;;) {
                 sfe_hsp *raw = (sfe_hsp *)c->hsp_raw.ensure(capraw * sizeof(sfe_hsp));
@@ -1643,19 +1704,24 @@ sfe_status sfe_autotune(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries,
     int32_t best_cap = saved.wave_group_cap;
     std::vector<sfe_aln> out(1 << 16);
     std::vector<uint32_t> ops(1 << 22);
-    const int cpls[2] = {6, 8};
+    const int cpls[2] = {4, 6};
     const int caps[2] = {0, 8192};
+    const int wpcs[2] = {8, 16};
     // with a cost model only the schedules that use it compete
     const int sched_lo = opts->model ? SFE_SCHED_PERSISTENT : SFE_SCHED_PLAIN;
     bool first = true;
+    int32_t best_wpc = saved.persist_waves_per_cu;
     for (int cap : caps)
         for (int sched = sched_lo; sched <= SFE_SCHED_ADAPTIVE; sched++)
+            for (int wpc : wpcs)
             for (int cpl : cpls) {
+                if (sched == SFE_SCHED_PLAIN && wpc != wpcs[0]) continue;     // the plain launch has no grid knob
                 sfe_align_opts o = *opts;
                 o.max_cells_per_lane = cpl;
                 o.schedule = sched;
                 if (sched == SFE_SCHED_PLAIN) o.model = nullptr;
                 c->tuning.wave_group_cap = cap;
+                c->tuning.persist_waves_per_cu = sched == SFE_SCHED_PLAIN ? saved.persist_waves_per_cu : wpc;
                 sfe_stats st{};
                 int64_t na = 0, no = 0;
                 sfe_status r = SFE_OK;
@@ -1680,16 +1746,18 @@ sfe_status sfe_autotune(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries,
                     c->tuning = saved;
                     return r;
                 }
-                if (rep.n < 16) rep.entries[rep.n++] = sfe_tune_entry{cpl, sched, cap, 0, ms};
+                if (rep.n < 32) rep.entries[rep.n++] = sfe_tune_entry{cpl, sched, cap, c->tuning.persist_waves_per_cu, ms};
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = o;
                     best_cap = cap;
+                    best_wpc = c->tuning.persist_waves_per_cu;
                     rep.best = rep.n - 1;
                 }
             }
     c->tuning = saved;
     c->tuning.wave_group_cap = best_cap;
+    c->tuning.persist_waves_per_cu = best_wpc;
     opts->max_cells_per_lane = best.max_cells_per_lane;
     opts->schedule = best.schedule;
     if (report) *report = rep;

@@ -22,6 +22,7 @@ SFE_XDROP_RAW = 1
 SFE_ALN_PASSED = 1
 SFE_SCHED_PLAIN, SFE_SCHED_PERSISTENT, SFE_SCHED_ADAPTIVE = 0, 1, 2
 SFE_POLICY_DEFER, SFE_POLICY_PREFIX = 0, 1
+SFE_FILTER_XDROP, SFE_FILTER_YDROP = 0, 1
 
 HIT_DTYPE = np.dtype([("t", "<u4"), ("q", "<u4"), ("query_id", "<u4"), ("strand", "u1"), ("pad", "u1", (3,))])
 HSP_DTYPE = np.dtype([("t0", "<u4"), ("q0", "<u4"), ("len", "<u4"), ("score", "<i4"), ("query_id", "<u4"),
@@ -56,7 +57,8 @@ class _Scoring(ctypes.Structure):
 class _AlignOpts(ctypes.Structure):
     _fields_ = [("round_k", ctypes.c_int32), ("schedule", ctypes.c_int32), ("strands", ctypes.c_int32),
                 ("max_cells_per_lane", ctypes.c_int32), ("policy", ctypes.c_int32), ("near_band", ctypes.c_int32),
-                ("arena_bytes", ctypes.c_int64), ("model", ctypes.c_void_p)]
+                ("arena_bytes", ctypes.c_int64), ("model", ctypes.c_void_p), ("filter", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -67,11 +69,11 @@ class _Tuning(ctypes.Structure):
 
 class _TuneEntry(ctypes.Structure):
     _fields_ = [("cells_per_lane", ctypes.c_int32), ("schedule", ctypes.c_int32), ("wave_group_cap", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("ms_extend", ctypes.c_double)]
+                ("waves_per_cu", ctypes.c_int32), ("ms_extend", ctypes.c_double)]
 
 
 class _TuneReport(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("best", ctypes.c_int32), ("entries", _TuneEntry * 16)]
+    _fields_ = [("n", ctypes.c_int32), ("best", ctypes.c_int32), ("entries", _TuneEntry * 32)]
 
 
 class _Stats(ctypes.Structure):
@@ -245,14 +247,15 @@ def sfe_autotune(ctx: Context, idx: Index, queries, scoring: dict, sample_bases:
     seqs, keep = _seq_arrays(queries)
     sc = scoring_struct(scoring)
     opts = _AlignOpts(int(round_k), SFE_SCHED_PLAIN, 3, 0, int(policy), 0, 0,
-                      model.ptr if model is not None else None)
+                      model.ptr if model is not None else None, SFE_FILTER_XDROP, 0)
     rep = _TuneReport()
     _check(lib().sfe_autotune(ctx.ptr, idx.ptr, seqs, len(queries), ctypes.byref(sc), int(sample_bases),
                               ctypes.byref(opts), ctypes.byref(rep)), ctx)
     entries = [dict(cells_per_lane=e.cells_per_lane, schedule=e.schedule, wave_group_cap=e.wave_group_cap,
-                    ms_extend=e.ms_extend) for e in rep.entries[:rep.n]]
+                    waves_per_cu=e.waves_per_cu, ms_extend=e.ms_extend) for e in rep.entries[:rep.n]]
+    tun = sfe_ctx_get_tuning(ctx)
     chosen = dict(max_cells_per_lane=opts.max_cells_per_lane, schedule=opts.schedule,
-                  wave_group_cap=sfe_ctx_get_tuning(ctx)["wave_group_cap"])
+                  wave_group_cap=tun["wave_group_cap"], persist_waves_per_cu=tun["persist_waves_per_cu"])
     return chosen, entries
 
 
@@ -326,12 +329,13 @@ def sfe_gapped_ydrop(ctx: Context, idx: Index, queries, hsps: np.ndarray, scorin
 
 def sfe_align(ctx: Context, idx: Index, queries, scoring: dict, round_k: int = 0, schedule: int = SFE_SCHED_PLAIN,
               strands: int = 3, max_cells_per_lane: int = 0, arena_bytes: int = 0, policy: int = SFE_POLICY_DEFER,
-              cap: int = 1 << 12, ops_cap: int = 1 << 18, model=None, near_band: int = 0):
+              cap: int = 1 << 12, ops_cap: int = 1 << 18, model=None, near_band: int = 0,
+              filter: int = SFE_FILTER_XDROP):
     """Whole pipeline; returns (alignments, ops, stats dict)."""
     seqs, keep = _seq_arrays(queries)
     sc = scoring_struct(scoring)
     opts = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(policy),
-                      int(near_band), int(arena_bytes), model.ptr if model is not None else None)
+                      int(near_band), int(arena_bytes), model.ptr if model is not None else None, int(filter), 0)
     na, no = ctypes.c_int64(), ctypes.c_int64()
     stats = _Stats()
     while True:
@@ -350,15 +354,15 @@ def sfe_align(ctx: Context, idx: Index, queries, scoring: dict, round_k: int = 0
 
 def sfe_align_opts_resolve(round_k: int = 0, schedule: int = SFE_SCHED_PLAIN, strands: int = 0,
                            max_cells_per_lane: int = 0, policy: int = SFE_POLICY_DEFER, near_band: int = 0,
-                           arena_bytes: int = 0) -> dict:
+                           arena_bytes: int = 0, filter: int = SFE_FILTER_XDROP) -> dict:
     """The options sfe_align would run with (host only; raises SfeError on invalid ones)."""
     o = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(policy),
-                   int(near_band), int(arena_bytes), None)
+                   int(near_band), int(arena_bytes), None, int(filter), 0)
     r = _AlignOpts()
     st = lib().sfe_align_opts_resolve(ctypes.byref(o), ctypes.byref(r))
     if st != SFE_OK:
         raise SfeError(st, "invalid sfe_align options")
-    return {f: getattr(r, f) for f, _ in _AlignOpts._fields_ if f != "model"}
+    return {f: getattr(r, f) for f, _ in _AlignOpts._fields_ if f not in ("model", "pad")}
 
 
 def sfe_model_check_file(path: str) -> int:

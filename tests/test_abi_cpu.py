@@ -47,7 +47,7 @@ def test_struct_layouts():
     assert sfe.HSP_DTYPE.itemsize == 24
     assert sfe.ALN_DTYPE.itemsize == 56
     assert ctypes.sizeof(sfe._Scoring) == 31 * 4
-    assert ctypes.sizeof(sfe._AlignOpts) == 40
+    assert ctypes.sizeof(sfe._AlignOpts) == 48
     src = open(HEADER).read()
     assert "} sfe_aln;                  /* 56 bytes */" in src
 
@@ -109,7 +109,7 @@ def test_align_options_resolve_bounds_the_first_batch():
     assert sfe.sfe_align_opts_resolve(near_band=-1, round_k=64)["round_k"] == 64
     assert sfe.sfe_align_opts_resolve(max_cells_per_lane=13)["max_cells_per_lane"] == 8
     for bad in (dict(schedule=7), dict(policy=3), dict(strands=4), dict(round_k=-2), dict(arena_bytes=-1),
-                dict(max_cells_per_lane=-1)):
+                dict(max_cells_per_lane=-1), dict(filter=2)):
         with pytest.raises(sfe.SfeError):
             sfe.sfe_align_opts_resolve(**bad)
 

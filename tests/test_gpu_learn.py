@@ -272,8 +272,9 @@ def test_autotune_picks_a_schedule_and_keeps_results(ctx, case):
     chosen, entries = sfe.sfe_autotune(ctx, idx, Q, dict(synth.SCORING), sample_bases=20_000, model=m)
     log(f"autotune: chosen {chosen}; {len(entries)} candidates")
     # with a model only the schedules that use it compete: persistent and adaptive
-    assert len(entries) == 8 and {e["schedule"] for e in entries} == {1, 2}
-    assert chosen["max_cells_per_lane"] in (6, 8) and chosen["schedule"] in (1, 2)
+    assert len(entries) == 16 and {e["schedule"] for e in entries} == {1, 2}
+    assert {e["waves_per_cu"] for e in entries} == {8, 16}
+    assert chosen["max_cells_per_lane"] in (4, 6) and chosen["schedule"] in (1, 2)
     best = min(entries, key=lambda e: e["ms_extend"])
     assert (best["cells_per_lane"], best["schedule"], best["wave_group_cap"]) == (
         chosen["max_cells_per_lane"], chosen["schedule"], chosen["wave_group_cap"])
@@ -287,7 +288,7 @@ def test_autotune_picks_a_schedule_and_keeps_results(ctx, case):
     # without a model the plain launch competes too
     chosen2, entries2 = sfe.sfe_autotune(ctx, idx, Q, dict(synth.SCORING), sample_bases=20_000)
     sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
-    assert len(entries2) == 12 and {e["schedule"] for e in entries2} == {0, 1, 2}
+    assert len(entries2) == 20 and {e["schedule"] for e in entries2} == {0, 1, 2}
 
 
 def test_model_save_load_round_trip(ctx, tmp_path):

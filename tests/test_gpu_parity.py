@@ -432,3 +432,24 @@ def test_score_range_errors(ctx):
     alns, ops = sfe.sfe_gapped_ydrop(ctx, idx, [S], h, sc)
     assert int(alns["score"][0]) == 300 * 20_000
     idx.close()
+
+
+# ---------------------------------------------------------------------------
+# the two-dimensional (Y-drop) filter in place of X-drop
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("div", [0.15, 0.30])
+def test_align_parity_ydrop_filter(ctx, div):
+    log(f"align parity with the 2-D filter, divergence {div}")
+    rng = synth.rng_for(610)
+    T, Q = synth.pair_small(n=20_000, divergence=div, seed=61, seg_len=1500)
+    T = decorate(T, rng)
+    Q = [decorate(Q[0], rng)]
+    sc = dict(synth.SCORING)
+    ref = oracle.pipeline(T, Q, sc, filter="ydrop")
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    alns, ops, st = sfe.sfe_align(ctx, idx, Q, sc, filter=sfe.SFE_FILTER_YDROP)
+    assert alns.shape[0] >= 2
+    compare_alignments(alns, ops, ref)
+    assert st["hsps"] == sum(int(u["hsps"].shape[0]) for u in ref["units"])
+    assert st["seed_hits"] == sum(int(u["hits_t"].shape[0]) for u in ref["units"])
+    idx.close()

@@ -412,3 +412,54 @@ def test_commit_pass_over_matches_brute_force(orc, scoring, K):
         assert n_ext == want_ext
     else:
         assert n_ext >= want_ext
+
+
+# --------------------------------------------------------------------------
+# the two-dimensional filter (Y-drop in place of X-drop)
+# --------------------------------------------------------------------------
+def test_ydrop_filter_unbounded_is_two_gotoh_halves(orc, scoring):
+    """With nothing pruned, the 2-D filter's score of a hit is the anchor
+    column's substitution score plus the two free-end Gotoh extensions from
+    the middle column of its seed window (an independent full-matrix DP), and
+    the HSP it yields spans the seed window."""
+    rng = synth.rng_for(71)
+    t = synth.iid_codes(rng, 110)
+    q, _ = synth.mutate(rng, t, np.zeros(110, bool), 0.08, indel=0.03)
+    T, Q = synth.to_ascii(t), synth.to_ascii(q)
+    tc, ts = orc.encode(T)
+    qc, qs = orc.encode(Q)
+    sc = dict(scoring, xdrop=BIG)
+    ht, hq = orc.seed_hits(tc, ts, qc, qs, synth.SEED_PATTERN, 1, 1)
+    assert ht.shape[0] >= 3
+    f = orc.ydrop_filter(tc, qc, ht, hq, 19, sc)
+    sub, o, e = sc["sub"], sc["gap_open"], sc["gap_extend"]
+    for x in range(ht.shape[0]):
+        ta, qa = int(ht[x]) + 9, int(hq[x]) + 9
+        fwd = refimpl.gotoh_extension(tc[ta + 1:].tolist(), qc[qa + 1:].tolist(), sub, o, e)[0]
+        bwd = refimpl.gotoh_extension(tc[:ta][::-1].tolist(), qc[:qa][::-1].tolist(), sub, o, e)[0]
+        assert int(f["score"][x]) == sub[tc[ta]][qc[qa]] + fwd + bwd, x
+        assert (int(f["t0"][x]), int(f["q0"][x]), int(f["len"][x])) == (int(ht[x]), int(hq[x]), 19)
+
+
+def test_ydrop_filter_bridges_an_indel(orc, scoring):
+    """A 40-base match, a 2-base deletion, then 40 matching bases: the X-drop
+    HSP of a seed on either side stops at the gap, the 2-D filter's score
+    crosses it (both blocks minus the gap's cost)."""
+    rng = synth.rng_for(72)
+    left, right = synth.iid_codes(rng, 40), synth.iid_codes(rng, 40)
+    gap = synth.iid_codes(rng, 2)
+    t = np.concatenate([left, gap, right])
+    q = np.concatenate([left, right])
+    T, Q = synth.to_ascii(t), synth.to_ascii(q)
+    tc, ts = orc.encode(T)
+    qc, qs = orc.encode(Q)
+    sub = scoring["sub"]
+    ht, hq = orc.seed_hits(tc, ts, qc, qs, synth.SEED_PATTERN, 0, 1)
+    onleft = (ht == hq) & (ht + 19 <= 40)
+    assert onleft.any()
+    x = int(np.nonzero(onleft)[0][0])
+    xd = orc.xdrop(tc, qc, ht[x:x + 1], hq[x:x + 1], 19, scoring)[0]
+    fd = orc.ydrop_filter(tc, qc, ht[x:x + 1], hq[x:x + 1], 19, scoring)[0]
+    block = lambda s: sum(sub[int(c)][int(c)] for c in s)
+    assert int(xd["score"]) == block(tc[:40])                      # the ungapped scan stops at the gap
+    assert int(fd["score"]) == block(tc[:40]) + block(tc[42:]) - (scoring["gap_open"] + 2 * scoring["gap_extend"])
