@@ -8,6 +8,9 @@
 #include <functional>
 #include <memory>
 #include <mutex>
+#include <thread>
+#include <atomic>
+#include <exception>
 #include <tuple>
 #include <cstdio>
 #include <cstdlib>
@@ -945,6 +948,35 @@ struct UnitPaths {
     }
 };
 
+// f(u, thread) for every unit u in [0, n) on up to 16 host threads; the
+// units of the commit bookkeeping share nothing.  The first exception a
+// thread raises is raised again here.
+template <class F>
+void for_each_unit(size_t n, F &&f) {
+    const size_t hw = std::max<size_t>(1, std::thread::hardware_concurrency());
+    const size_t T = std::min<size_t>(n, std::min<size_t>(hw, 16));
+    if (T <= 1) {
+        for (size_t u = 0; u < n; u++) f(u, (size_t)0);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    std::exception_ptr err;
+    std::mutex mu;
+    std::vector<std::thread> th;
+    for (size_t t = 0; t < T; t++)
+        th.emplace_back([&, t] {
+            try {
+                for (size_t u = next++; u < n; u = next++) f(u, t);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!err) err = std::current_exception();
+                next = n;
+            }
+        });
+    for (auto &x : th) x.join();
+    if (err) std::rethrow_exception(err);
+}
+
 sfe_status guard(sfe_ctx *c, const std::function<void()> &f) {
     try {
         (void)hipGetLastError();        // an error left by an unrelated earlier call is not this call's
@@ -1472,14 +1504,27 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         double host_ms = 0, book_ms = 0, commit_ms = 0;
         std::vector<std::vector<uint16_t>> why(progress ? NU : 0);   // deferrals by path (lo byte) and nearness (hi)
         for (size_t u = 0; u < why.size(); u++) why[u].assign(per_unit[u].size(), 0);
-        std::vector<uint64_t> near_bits;       // nearness rule: diagonals taken (per unit, cleared after it)
-        std::vector<size_t> near_touched;
+        // nearness rule: diagonals taken, one bit set per host thread (cleared after each unit)
+        std::vector<std::vector<uint64_t>> near_bits_t(16);
+        std::vector<std::vector<size_t>> near_touched_t(16);
+        std::vector<std::vector<ExtItem>> items_u(NU);
+        std::vector<std::vector<size_t>> ref_u(NU);
+        std::vector<std::vector<sfe_aln>> committed_u(NU);
+        std::vector<std::vector<uint32_t>> cops_u(NU);
+        std::vector<int64_t> shadow_u(NU, 0);
+        std::vector<size_t> item_lo(NU + 1, 0);
         for (;;) {
             const double th = now_ms();
             items.clear();
             item_ref.clear();
             scan_no++;
-            for (size_t u = 0; u < NU; u++) {                      // Alg. 3 batch gathering, per unit
+            for_each_unit(NU, [&](size_t u, size_t tix) {        // Alg. 3 batch gathering, per unit
+                auto &near_bits = near_bits_t[tix];
+                auto &near_touched = near_touched_t[tix];
+                auto &uitems = items_u[u];
+                auto &uref = ref_u[u];
+                uitems.clear();
+                uref.clear();
                 auto &lst = per_unit[u];
                 auto &stt = state[u];
                 int64_t taken = 0;
@@ -1526,8 +1571,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                             word |= 1ull << (x & 63);
                         }
                     }
-                    items.push_back(ExtItem{ta, qa, (int32_t)u, 0});
-                    item_ref.push_back({(int32_t)u, p});
+                    uitems.push_back(ExtItem{ta, qa, (int32_t)u, 0});
+                    uref.push_back(p);
                     stt[p] = 4;
                     taken++;
                 }
@@ -1536,7 +1581,13 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 open[u].swap(still);
                 for (size_t w : near_touched) near_bits[w] = 0;
                 near_touched.clear();
+            });
+            for (size_t u = 0; u < NU; u++) {                      // the batch in unit order
+                item_lo[u] = items.size();
+                items.insert(items.end(), items_u[u].begin(), items_u[u].end());
+                for (size_t p : ref_u[u]) item_ref.push_back({(int32_t)u, p});
             }
+            item_lo[NU] = items.size();
             host_ms += now_ms() - th;
             if (items.empty()) break;
             st.rounds++;
@@ -1558,7 +1609,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             st.mispredicted_halves += br.mispredicted;
             if (progress) {
                 fprintf(stderr, "[sfe] batch %lld: %zu extensions, %.1f ms, %zu committed so far\n",
-                        (long long)st.rounds, items.size(), now_ms() - tr, committed.size());
+                        (long long)st.rounds, items.size(), now_ms() - tr,
+                        [&] { size_t n = 0; for (auto &v : committed_u) n += v.size(); return n; }());
                 size_t xl = 0;
                 int64_t kl = -1, nlong = 0;
                 for (size_t x = 0; x < items.size(); x++)
@@ -1584,22 +1636,23 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             batch_ops.push_back(std::move(br.ops));
             br.ops = std::vector<uint32_t>();
             const uint32_t *bops = batch_ops.back().data();
-            for (size_t x = 0; x < items.size(); x++) {
-                const sfe_aln &a = br.alns[x];
-                const int32_t u = item_ref[x].first;
-                const size_t p = item_ref[x].second;
-                st.cells += (int64_t)a.cells;
-                ext[u][p] = a;
-                ext_batch[u][p] = bno;
-                if (a.flags & SFE_ALN_PASSED) {
-                    paths[u].set.add(a, bops + a.ops_offset, p);
-                    if (defer) boxes[u].add(a);
+            for (size_t x = 0; x < items.size(); x++) st.cells += (int64_t)br.alns[x].cells;
+            for_each_unit(NU, [&](size_t u, size_t) {
+                for (size_t x = item_lo[u]; x < item_lo[u + 1]; x++) {
+                    const sfe_aln &a = br.alns[x];
+                    const size_t p = item_ref[x].second;
+                    ext[u][p] = a;
+                    ext_batch[u][p] = bno;
+                    if (a.flags & SFE_ALN_PASSED) {
+                        paths[u].set.add(a, bops + a.ops_offset, p);
+                        if (defer) boxes[u].add(a);
+                    }
+                    state[u][p] = 2;
                 }
-                state[u][p] = 2;
-            }
+            });
             const double th3 = now_ms();
             book_ms += th3 - th2;
-            for (size_t u = 0; u < NU; u++) {                      // in-order commit (Alg. 1 decisions)
+            for_each_unit(NU, [&](size_t u, size_t) {             // in-order commit (Alg. 1 decisions)
                 auto &lst = per_unit[u];
                 auto &stt = state[u];
                 size_t &cur = cursor[u];
@@ -1609,14 +1662,14 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     if (stt[p] == 2) {
                         const sfe_aln &a = ext[u][p];
                         if (paths[u].in_committed(a.anchor_t, a.anchor_q)) {
-                            st.shadow++;
+                            shadow_u[u]++;
                         } else if (a.flags & SFE_ALN_PASSED) {
                             sfe_aln k = a;
-                            k.ops_offset = cops.size();
+                            k.ops_offset = cops_u[u].size();
                             const uint32_t *src = batch_ops[ext_batch[u][p]].data() + a.ops_offset;
-                            cops.insert(cops.end(), src, src + a.ops_len);
+                            cops_u[u].insert(cops_u[u].end(), src, src + a.ops_len);
                             paths[u].committed[p] = 1;
-                            committed.push_back(k);
+                            committed_u[u].push_back(k);
                         }
                         stt[p] = 3;
                         cur++;
@@ -1627,15 +1680,23 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     if (paths[u].in_committed(ta, qa)) { stt[p] = 1; cur++; continue; }
                     break;                                          // needs an extension first
                 }
-            }
+            });
             commit_ms += now_ms() - th3;
             host_ms += now_ms() - th2;
         }
         if (progress)
             fprintf(stderr, "[sfe] host scan/commit time %.1f ms (scan %.1f, bookkeeping %.1f, commit %.1f)\n", host_ms,
                     host_ms - book_ms - commit_ms, book_ms, commit_ms);
-        for (size_t u = 0; u < NU; u++)
+        for (size_t u = 0; u < NU; u++) {
             if (cursor[u] != per_unit[u].size()) fail(SFE_EINTERNAL, "commit did not finish");
+            const uint64_t base_off = cops.size();
+            cops.insert(cops.end(), cops_u[u].begin(), cops_u[u].end());
+            for (sfe_aln a : committed_u[u]) {
+                a.ops_offset += base_off;
+                committed.push_back(a);
+            }
+            st.shadow += shadow_u[u];
+        }
         st.committed = (int64_t)committed.size();
         const double t4 = now_ms();
         // --- output in (query, strand, t_start, q_start, t_end, q_end, anchor) order ---
