@@ -264,6 +264,33 @@ def k_sweep(ctx, sfe, synth, sc, Td, Q0d, index, sample_bp, log_fn):
     return dict(sample=f"first {sample_bp} query bases vs the full target", rows=rows)
 
 
+def probe_half(n):
+    """One forward half along an n-base pair at 25 % divergence, anchored at
+    column 50: its time per antidiagonal on one wave (the latency that sets
+    the end of every round)."""
+    from paper_2606_06811_amd import sfe, synth
+    ctx = sfe.sfe_ctx_create(0)
+    rng = synth.rng_for(900 + n)
+    t = synth.iid_codes(rng, n)
+    q, _ = synth.mutate(rng, t, np.zeros(n, bool), 0.25)
+    T, Q = synth.to_ascii(t), [synth.to_ascii(q)]
+    idx = sfe.sfe_build_index(ctx, T, synth.SEED_PATTERN, 1, 1)
+    h = np.zeros(1, sfe.HSP_DTYPE)
+    h[0] = (50, 50, 1, 0, 0, 0, (0, 0, 0))
+    best = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        a, o = sfe.sfe_gapped_ydrop(ctx, idx, Q, h, dict(synth.SCORING))
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    k = int(a["t_end"][0] - a["t_start"][0] + a["q_end"][0] - a["q_start"][0])
+    print(json.dumps(dict(probe="one gapped half", bases=n, antidiagonals=k, cells=int(a["cells"][0]),
+                          score=int(a["score"][0]), ms=round(1e3 * best, 2),
+                          us_per_antidiagonal=round(1e6 * best / max(k, 1), 4))), flush=True)
+    idx.close()
+    ctx.close()
+
+
 def kernel_sources_digest():
     """Digest of the extension kernel's source and every header it includes (the
     stored HBM traffic figure is valid only for exactly these files)."""
@@ -305,11 +332,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-studies", action="store_true", help="skip the seed study and the K sweep")
     ap.add_argument("--sweep-bp", type=int, default=1_000_000, help="query bases of the K sweep")
+    ap.add_argument("--probe-half", type=int, default=0,
+                    help="instead of the benchmark: time one gapped half along an N-base pair at 25%% "
+                         "divergence (the per-antidiagonal latency of one wave)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path (queries would shard by unit)",
               file=sys.stderr)
         raise SystemExit(2)
+    if args.probe_half > 0:
+        probe_half(args.probe_half)
+        return
     chrom = args.workload == "chrom"
     if args.tune_bp < 0:
         args.tune_bp = 200_000 if chrom else 1_000_000
@@ -342,7 +375,7 @@ def main():
         log(f"position table of the {T.shape[0]} bp target built in {index_ms:.0f} ms")
 
     model, train_info, tune_info = None, None, None
-    tuned = dict(max_cells_per_lane=args.cpl, schedule=sfe.SFE_SCHED_ADAPTIVE, wave_group_cap=0,
+    tuned = dict(max_cells_per_lane=args.cpl, schedule=sfe.SFE_SCHED_BINNED, wave_group_cap=0,
                  persist_waves_per_cu=0)
     if args.schedule in ("learned", "both"):
         model, train_info = train_cost_model(ctx, sfe, synth, log, Td, Qd[:1], args.train_bp, resident)
@@ -359,7 +392,7 @@ def main():
             log(f"autotune on {args.tune_bp} query bases: {tuned} in {tune_info['seconds']} s")
 
     sched_name = {sfe.SFE_SCHED_PLAIN: "plain", sfe.SFE_SCHED_PERSISTENT: "persistent",
-                  sfe.SFE_SCHED_ADAPTIVE: "adaptive"}
+                  sfe.SFE_SCHED_ADAPTIVE: "adaptive", sfe.SFE_SCHED_BINNED: "binned"}
     peak_used = [0]
 
     def step(kind, k):

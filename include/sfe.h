@@ -125,6 +125,9 @@ typedef struct {
 #define SFE_SCHED_ADAPTIVE 2    /* plain launch for a batch of at least sfe_tuning.adaptive_halves
                                    halves, persistent below (fewer halves in flight at once,
                                    spread evenly over the SIMDs) */
+#define SFE_SCHED_BINNED 3      /* learned binning with plain launches: one wavefront per half, the
+                                   halves a cost model predicts to be long launched first (see
+                                   sfe_align_opts.model), the rest in batch order */
 
 /* Speculation policies of sfe_align; all give identical results.
  * PREFIX: each batch is the next round_k HSPs of a (query, strand) whose
@@ -159,9 +162,11 @@ typedef struct {
                                at first use (at least 32 GiB).  A batch whose halves
                                need more at once runs with fewer in flight; a single half
                                that needs more makes the arena grow. */
-    const struct sfe_model *model; /* NULL, or a cost model: with SFE_SCHED_PERSISTENT or
-                               SFE_SCHED_ADAPTIVE the halves of each batch are queued (or
-                               launched) longest-predicted first.  Never changes the output. */
+    const struct sfe_model *model; /* NULL, or a cost model: with SFE_SCHED_PERSISTENT,
+                               SFE_SCHED_ADAPTIVE or SFE_SCHED_BINNED the halves of each batch
+                               predicted to compute at least 2^20 cells are queued (or launched)
+                               first, longest first, the rest in batch order.  Never changes the
+                               output. */
     int32_t filter;         /* SFE_FILTER_XDROP (0, default) or SFE_FILTER_YDROP */
     int32_t pad;
 } sfe_align_opts;
@@ -291,9 +296,10 @@ sfe_status sfe_ctx_get_tuning(const sfe_ctx *ctx, sfe_tuning *t);
 
 /* Autotuner.  Times sfe_align on a sample of the workload (the first
  * sample_bases of every query, all against idx) under each candidate schedule
- * -- rows per lane 4 / 6 in the first band window; plain, persistent or
- * adaptive launch, only the last two (with the model) when opts->model is
- * given; 8 or 16 waves per compute unit for the persistent grid; wave groups
+ * -- rows per lane 4 / 6 in the first band window; plain, persistent,
+ * adaptive or binned launch, only the last three (with the model) when
+ * opts->model is given; 8 or 16 waves per compute unit for the persistent
+ * grid; wave groups
  * for long halves off or after 8192 antidiagonals -- three times each, and
  * keeps the fastest (by its best time): the context's wave_group_cap and
  * persist_waves_per_cu are set and opts->max_cells_per_lane / schedule are

@@ -551,10 +551,17 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     out.reruns = 0;
     out.predicted = out.mispredicted = 0;
     if (cost) {
+        // two bins: halves predicted to compute at least 2^20 cells start first, longest first;
+        // the rest keep batch order (neighbouring halves read neighbouring sequence, so the bulk
+        // runs faster in that order than sorted by size)
         if ((int64_t)cost->size() != nh) fail(SFE_EINTERNAL, "cost vector size");
-        todo.resize(nh);
-        for (int64_t h = 0; h < nh; h++) todo[h] = (int32_t)h;
+        const float kLong = 20.0f;
+        todo.reserve(nh);
+        for (int64_t h = 0; h < nh; h++)
+            if ((*cost)[h] >= kLong) todo.push_back((int32_t)h);
         std::stable_sort(todo.begin(), todo.end(), [&](int32_t a, int32_t b) { return (*cost)[a] > (*cost)[b]; });
+        for (int64_t h = 0; h < nh; h++)
+            if (!((*cost)[h] >= kLong)) todo.push_back((int32_t)h);
         all = false;
     }
     for (;;) {
@@ -1300,7 +1307,7 @@ sfe_status sfe_align_opts_resolve(const sfe_align_opts *in, sfe_align_opts *out)
     if (in) o = *in;
     if (o.strands == 0) o.strands = 3;
     if (o.strands < 1 || o.strands > 3) return SFE_EINVAL;
-    if (o.schedule < SFE_SCHED_PLAIN || o.schedule > SFE_SCHED_ADAPTIVE) return SFE_EINVAL;
+    if (o.schedule < SFE_SCHED_PLAIN || o.schedule > SFE_SCHED_BINNED) return SFE_EINVAL;
     if (o.policy != SFE_POLICY_DEFER && o.policy != SFE_POLICY_PREFIX) return SFE_EINVAL;
     if (o.arena_bytes < 0) return SFE_EINVAL;
     if (o.filter != SFE_FILTER_XDROP && o.filter != SFE_FILTER_YDROP) return SFE_EINVAL;
@@ -1518,6 +1525,24 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             items.clear();
             item_ref.clear();
             scan_no++;
+            {
+                // anchors already on an M column of a committed alignment stay skipped for good:
+                // found for every open HSP first, in parallel over pieces of the open lists
+                std::vector<std::pair<size_t, size_t>> jobs;
+                for (size_t u = 0; u < NU; u++)
+                    for (size_t a = 0; a < open[u].size(); a += 8192) jobs.push_back({u, a});
+                for_each_unit(jobs.size(), [&](size_t j, size_t) {
+                    const size_t u = jobs[j].first;
+                    const size_t end = std::min(open[u].size(), jobs[j].second + 8192);
+                    for (size_t q = jobs[j].second; q < end; q++) {
+                        const size_t p = open[u][q];
+                        if (state[u][p] != 0) continue;
+                        uint32_t ta, qa;
+                        anchor_of(hs[per_unit[u][p]], ta, qa);
+                        if (paths[u].in_committed(ta, qa)) state[u][p] = 1;
+                    }
+                });
+            }
             for_each_unit(NU, [&](size_t u, size_t tix) {        // Alg. 3 batch gathering, per unit
                 auto &near_bits = near_bits_t[tix];
                 auto &near_touched = near_touched_t[tix];
@@ -1540,7 +1565,6 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     if (stt[p] != 0) continue;
                     uint32_t ta, qa;
                     anchor_of(hs[lst[p]], ta, qa);
-                    if (paths[u].in_committed(ta, qa)) { stt[p] = 1; continue; }
                     if (defer) {
                         // on the path of an earlier extension that may still commit: wait for it
                         if (paths[u].set.contains(ta, qa, [&](size_t o) { return o < p && stt[o] == 2; },
@@ -1588,7 +1612,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 for (size_t p : ref_u[u]) item_ref.push_back({(int32_t)u, p});
             }
             item_lo[NU] = items.size();
-            host_ms += now_ms() - th;
+            const double scan_round_ms = now_ms() - th;
+            host_ms += scan_round_ms;
             if (items.empty()) break;
             st.rounds++;
             const double tr = now_ms();
@@ -1608,8 +1633,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             st.predicted_halves += br.predicted;
             st.mispredicted_halves += br.mispredicted;
             if (progress) {
-                fprintf(stderr, "[sfe] batch %lld: %zu extensions, %.1f ms, %zu committed so far\n",
-                        (long long)st.rounds, items.size(), now_ms() - tr,
+                fprintf(stderr, "[sfe] batch %lld: %zu extensions, %.1f ms (scan %.1f ms), %zu committed so far\n",
+                        (long long)st.rounds, items.size(), now_ms() - tr, scan_round_ms,
                         [&] { size_t n = 0; for (auto &v : committed_u) n += v.size(); return n; }());
                 size_t xl = 0;
                 int64_t kl = -1, nlong = 0;
@@ -1773,16 +1798,18 @@ sfe_status sfe_autotune(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries,
     bool first = true;
     int32_t best_wpc = saved.persist_waves_per_cu;
     for (int cap : caps)
-        for (int sched = sched_lo; sched <= SFE_SCHED_ADAPTIVE; sched++)
+        for (int sched = sched_lo; sched <= SFE_SCHED_BINNED; sched++)
             for (int wpc : wpcs)
             for (int cpl : cpls) {
-                if (sched == SFE_SCHED_PLAIN && wpc != wpcs[0]) continue;     // the plain launch has no grid knob
+                // plain and binned launches have no grid knob
+                if ((sched == SFE_SCHED_PLAIN || sched == SFE_SCHED_BINNED) && wpc != wpcs[0]) continue;
                 sfe_align_opts o = *opts;
                 o.max_cells_per_lane = cpl;
                 o.schedule = sched;
                 if (sched == SFE_SCHED_PLAIN) o.model = nullptr;
                 c->tuning.wave_group_cap = cap;
-                c->tuning.persist_waves_per_cu = sched == SFE_SCHED_PLAIN ? saved.persist_waves_per_cu : wpc;
+                c->tuning.persist_waves_per_cu =
+                    (sched == SFE_SCHED_PLAIN || sched == SFE_SCHED_BINNED) ? saved.persist_waves_per_cu : wpc;
                 sfe_stats st{};
                 int64_t na = 0, no = 0;
                 sfe_status r = SFE_OK;

@@ -20,7 +20,7 @@ SFE_OK, SFE_EINVAL, SFE_ENOMEM, SFE_ECAPACITY, SFE_ERANGE, SFE_EDEVICE, SFE_EINT
     0, -1, -2, -3, -4, -5, -6, -7
 SFE_XDROP_RAW = 1
 SFE_ALN_PASSED = 1
-SFE_SCHED_PLAIN, SFE_SCHED_PERSISTENT, SFE_SCHED_ADAPTIVE = 0, 1, 2
+SFE_SCHED_PLAIN, SFE_SCHED_PERSISTENT, SFE_SCHED_ADAPTIVE, SFE_SCHED_BINNED = 0, 1, 2, 3
 SFE_POLICY_DEFER, SFE_POLICY_PREFIX = 0, 1
 SFE_FILTER_XDROP, SFE_FILTER_YDROP = 0, 1
 

@@ -118,7 +118,7 @@ def test_bad_inputs_return_errors(ctx):
         sfe.sfe_build_index(ctx, good, "1" * 15)
     idx = sfe.sfe_build_index(ctx, good)
     with pytest.raises(sfe.SfeError) as e:
-        sfe.sfe_align(ctx, idx, [good], dict(synth.SCORING), schedule=3)
+        sfe.sfe_align(ctx, idx, [good], dict(synth.SCORING), schedule=4)
     assert e.value.status == sfe.SFE_EINVAL
     for bad in (dict(persist_waves_per_cu=-1), dict(persist_waves_per_cu=65), dict(adaptive_halves=-2)):
         with pytest.raises(sfe.SfeError):
@@ -305,7 +305,7 @@ PLAIN, PERSIST, ADAPT = sfe.SFE_SCHED_PLAIN, sfe.SFE_SCHED_PERSISTENT, sfe.SFE_S
     (1, 0, 1, PLAIN), (7, 0, 1, PLAIN), (64, 0, 1, PLAIN), (1000, 0, 1, PLAIN), (64, 4, 1, PLAIN), (64, 8, 1, PLAIN),
     (1, 0, 0, PLAIN), (3, 0, 0, PLAIN), (0, 0, 0, PLAIN), (0, 4, 0, PLAIN),
     (1, 0, 1, PERSIST), (64, 0, 1, PERSIST), (0, 0, 0, PERSIST), (0, 8, 0, PERSIST),
-    (0, 0, 0, ADAPT), (7, 0, 1, ADAPT)])
+    (0, 0, 0, ADAPT), (7, 0, 1, ADAPT), (0, 0, 0, sfe.SFE_SCHED_BINNED)])
 def test_align_parity(ctx, align_case, K, cpl, policy, schedule):
     log(f"align parity K={K} cells_per_lane={cpl} policy={policy} schedule={schedule}")
     T, Q, ref = align_case
