@@ -330,6 +330,8 @@ def main():
                     help="query bases whose HSP extensions train the cost model (-1: default)")
     ap.add_argument("--cpu-sample-bp", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graphs", action="store_true",
+                    help="run the first launch of every batch as a replay of a recorded graph")
     ap.add_argument("--no-studies", action="store_true", help="skip the seed study and the K sweep")
     ap.add_argument("--sweep-bp", type=int, default=1_000_000, help="query bases of the K sweep")
     ap.add_argument("--probe-half", type=int, default=0,
@@ -401,11 +403,11 @@ def main():
         common = dict(round_k=args.round_k, cap=1 << 21, ops_cap=1 << 26, near_band=args.near_band,
                       policy=args.policy)
         if kind == "plain":
-            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0)
+            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0, use_graphs=int(args.graphs))
             out = sfe.sfe_align(ctx, idx, q, sc, schedule=sfe.SFE_SCHED_PLAIN, max_cells_per_lane=args.cpl,
                                 **common)
         else:
-            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=tuned["wave_group_cap"],
+            sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=tuned["wave_group_cap"], use_graphs=int(args.graphs),
                                    persist_waves_per_cu=tuned.get("persist_waves_per_cu", 0))
             out = sfe.sfe_align(ctx, idx, q, sc, schedule=tuned["schedule"], model=model,
                                 max_cells_per_lane=tuned["max_cells_per_lane"], **common)
@@ -429,7 +431,8 @@ def main():
             outs.append((a, o))
             log(f"[{kind}] step {k}: {s['ms_total']:.0f} ms in align (seed+xdrop {s['ms_seed_xdrop']:.0f}, "
                 f"hsp set {s['ms_hsp_set']:.0f}, predict {s['ms_predict']:.0f}, extend {s['ms_extend']:.0f}; "
-                f"{s['rounds']} rounds)")
+                f"{s['rounds']} rounds, {s['ydrop_launches']} extension launches, "
+                f"{s['graph_launches']} graph replays)")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         return dict(ms_step=1e3 * elapsed / args.steps, stats=stats, outs=outs)
@@ -534,6 +537,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "schedule": summary(head_kind)["schedule"],
                    "policy": "prefix" if args.policy == 1 else "defer",
+                   "recorded_graphs": bool(args.graphs),
                    "round_k": sfe.sfe_align_opts_resolve(round_k=args.round_k, policy=args.policy,
                                                          near_band=args.near_band)["round_k"]},
         "gapped_gcups": round(sum(x["cells"] for x in stats) / (sum(x["ms_extend"] for x in stats) / 1e3) / 1e9, 3),
@@ -548,7 +552,8 @@ def main():
         "cost_model_training": train_info,
         "autotune": tune_info,
         "counts": {k: s[k] for k in ("seed_hits", "hsps_raw", "hsps", "rounds", "extensions", "committed",
-                                     "shadow", "cells", "overflow_reruns", "xdrop_columns")},
+                                     "shadow", "cells", "overflow_reruns", "xdrop_columns", "ydrop_launches",
+                                     "graph_launches", "graph_records")},
         "stage_ms": {k: round(s[k], 2) for k in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total",
                                                  "ms_ydrop_kernel", "ms_seed_xdrop_kernel", "ms_predict")},
         "region_length_histogram": length_histogram(head["outs"][-1][0]),

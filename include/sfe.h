@@ -212,6 +212,9 @@ typedef struct {
     int64_t mispredicted_halves;/* of those: predicted log2(1 + cells) off by more than 2 */
     double ms_predict;          /* host wall clock of features + model inference */
     int64_t narrow_launches;    /* of ydrop_launches: launches of the packed 16-bit kernel */
+    int64_t graph_launches;     /* of ydrop_launches: first launches of a batch run as a replay of a
+                                   recorded graph (tuning.use_graphs) */
+    int64_t graph_records;      /* graphs recorded for them (the rest were replays of an earlier one) */
 } sfe_stats;
 
 /* Context on `device` using `hip_stream` (a hipStream_t, or NULL for a
@@ -281,7 +284,14 @@ sfe_status sfe_align(sfe_ctx *ctx, const sfe_index *idx, const sfe_seq *queries,
 typedef struct {
     int32_t wave_group_cap;
     int32_t use_graphs;     /* 1: sfe_model_train records its whole step sequence in one hipGraph
-                               and launches it once (same kernels, same order, same results) */
+                               and launches it once; sfe_align runs the first one-wave launch of
+                               every batch (pool and queue reset, half tasks, fused extension) as
+                               a recorded graph that reads the item and half counts from device
+                               memory, replayed while buffers, scores and launch shape stay the
+                               same (buffers then sized for the next power of two of the batch;
+                               a plain launch covers that capacity and its extra waves exit at
+                               once).  Same kernels, same results; if recording fails, stream
+                               launches from then on. */
     int32_t wide_scores;    /* 1: gapped extension always in 32-bit arithmetic; 0 (default): in
                                packed 16-bit arithmetic, values relative to the Y-drop threshold,
                                when every score fits in int8 and ydrop + gap_open + gap_extend +

@@ -82,7 +82,7 @@ struct sfe_ctx {
     DBuf units_d, chunks_d, qdesc_d;
     DBuf hsp_raw, hsp_pass, hsp_sorted;
     DBuf items_d, tasks_d, hres_d, ids_d, aln_d, runoff_d, runs_d, nruns_d, opsoff_d, ops_d, nops_d, ring_d;
-    DBuf sched_d;                       // u64 run-arena head, u32 work-queue head
+    DBuf sched_d;                       // scheduling words (kSchedBytes: heads, free count, counts)
     DBuf feat_unit, feat_key, feat_key2, feat_ids, feat_ids2, feat_okey, feat_range, feat_hsp, feat_out, feat_pred;
     DBuf busy_d;                        // bitmap of the traceback chunk pool
     int cu_count = 0;
@@ -100,6 +100,14 @@ struct sfe_ctx {
     // per-call kernel accounting (reset by sfe_align)
     double ydrop_ms = 0, sx_ms = 0;
     int64_t ydrop_launches = 0, ydrop_cells = 0, sx_launches = 0, narrow_launches = 0;
+    int64_t graph_launches = 0, graph_records = 0;
+    // first launch of a batch recorded as a graph (tuning.use_graphs): the
+    // executable graph, the launch it was recorded for (buffers, sizes,
+    // scores), and the item and half counts it reads from device memory
+    hipGraphExec_t round_exec = nullptr;
+    std::vector<uint8_t> round_key;
+    bool graphs_failed = false;         // recording failed once: plain stream launches from then on
+    int64_t graph_counts[2] = {0, 0};
 };
 
 struct sfe_index {
@@ -476,19 +484,100 @@ int persistent_per_cu(sfe_ctx *c, int C, bool perm, bool narrow, int wpc, size_t
 }
 
 // Chunk pool over arena 0: chunks of 256 KB (smaller for a small arena, so
-// that it holds at least 256 of them), all free.
-ChunkPool make_pool(sfe_ctx *c) {
+// that it holds at least 256 of them).  pool_layout only places it; make_pool
+// also marks every chunk free.
+ChunkPool pool_layout(sfe_ctx *c) {
     int shift = 18;
     while (shift > 12 && ((uint64_t)c->arena_bytes >> shift) < 256) shift--;
     const uint64_t nchunks = std::min<uint64_t>((uint64_t)c->arena_bytes >> shift, (uint64_t)1 << 30);
     const int32_t nwords = (int32_t)(nchunks / 32);
     if (nwords < 1) fail(SFE_EINVAL, "traceback arena too small");
     uint32_t *bits = (uint32_t *)c->busy_d.ensure((size_t)nwords * 4);
-    HIPCHK(hipMemsetAsync(bits, 0, (size_t)nwords * 4, c->stream));
     int32_t *avail = (int32_t *)(c->sched_d.as<uint8_t>() + 16);
     c->pool_avail = nwords * 32;
-    HIPCHK(hipMemcpyAsync(avail, &c->pool_avail, 4, hipMemcpyHostToDevice, c->stream));
     return ChunkPool{c->arenas[0]->as<uint8_t>(), bits, avail, nwords, shift};
+}
+
+ChunkPool make_pool(sfe_ctx *c) {
+    ChunkPool pool = pool_layout(c);
+    HIPCHK(hipMemsetAsync(pool.bits, 0, (size_t)pool.nwords * 4, c->stream));
+    HIPCHK(hipMemcpyAsync(pool.avail, &c->pool_avail, 4, hipMemcpyHostToDevice, c->stream));
+    return pool;
+}
+
+// Device words of the scheduling block c->sched_d: run-arena head (u64 at 0),
+// work-queue head (u32 at 8), pool free count (i32 at 16), and the item and
+// half counts a recorded launch reads (i64 at 24 and 32).
+constexpr int kSchedBytes = 64;
+
+template <class T> void key_put(std::vector<uint8_t> &k, const T &v) {
+    const uint8_t *b = (const uint8_t *)&v;
+    k.insert(k.end(), b, b + sizeof(T));
+}
+
+// First launch of a batch as one graph: clear the pool bitmap, the pool's free
+// count, the work-queue head and the run-arena head (a kernel, no memset
+// node), build the half tasks of the first n_dev[0] items, and run the fused
+// extension over the first n_dev[1] halves of the queue.  The graph is
+// recorded for item capacity icap and half capacity hcap and replayed, with the
+// counts written to device memory first, for every later batch whose buffers,
+// scores and launch shape are the same.  Returns false when recording or
+// instantiation fails (the caller then launches on the stream).
+bool launch_first_recorded(sfe_ctx *c, const sfe_index *idx, const ExtItem *items_d, int64_t n, int64_t icap,
+                           HalfTask *tasks, const int32_t *ids, int64_t cnt, int64_t hcap, int C, bool perm,
+                           bool narrow, bool persistent, int64_t count, SeqSetView T, SeqSetView Qp, SeqSetView Qm,
+                           const ScoreDesc &sc, ChunkPool pool, RunArena ra, HalfResult *hres, int long_cap,
+                           size_t dyn) {
+    uint8_t *sched = c->sched_d.as<uint8_t>();
+    unsigned int *qhead = (unsigned int *)(sched + 8);
+    const int64_t *n_items = (const int64_t *)(sched + 24), *n_halves = (const int64_t *)(sched + 32);
+    const int64_t grid = persistent ? count : hcap;
+    std::vector<uint8_t> key;
+    key_put(key, items_d); key_put(key, icap); key_put(key, tasks); key_put(key, ids); key_put(key, hcap);
+    key_put(key, C); key_put(key, perm); key_put(key, narrow); key_put(key, persistent); key_put(key, grid);
+    key_put(key, T); key_put(key, Qp); key_put(key, Qm); key_put(key, sc); key_put(key, pool); key_put(key, ra);
+    key_put(key, hres); key_put(key, long_cap); key_put(key, dyn); key_put(key, idx->nt);
+    key_put(key, c->units_d.p); key_put(key, sched);
+    if (!c->round_exec || key != c->round_key) {
+        if (c->round_exec) { (void)hipGraphExecDestroy(c->round_exec); c->round_exec = nullptr; }
+        c->round_key.clear();
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        launch_sched_reset(pool.bits, pool.nwords, pool.avail, pool.nwords * 32, qhead, ra.head, c->stream);
+        launch_make_tasks(items_d, icap, c->units_d.as<UnitDesc>(), idx->nt, tasks, c->stream, n_items);
+        launch_ydrop_fused(C, perm, narrow, persistent, tasks, WorkQueue{ids, hcap, qhead, n_halves}, grid, T, Qp, Qm,
+                           sc, pool, ra, hres, long_cap, dyn, c->stream);
+        const hipError_t e0 = hipGetLastError();
+        const hipError_t e1 = hipStreamEndCapture(c->stream, &g);
+        hipGraphExec_t ge = nullptr;
+        const hipError_t e2 = (e0 == hipSuccess && e1 == hipSuccess && g)
+                                  ? hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) : hipErrorUnknown;
+        if (g) (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            if (ge) (void)hipGraphExecDestroy(ge);
+            (void)hipGetLastError();
+            return false;
+        }
+        c->round_exec = ge;
+        c->round_key = key;
+        c->graph_records++;
+    }
+    c->graph_counts[0] = n;
+    c->graph_counts[1] = cnt;
+    HIPCHK(hipMemcpyAsync(sched + 24, c->graph_counts, 16, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    HIPCHK(hipGraphLaunch(c->round_exec, c->stream));
+    c->graph_launches++;
+    return true;
+}
+
+int64_t pow2_at_least(int64_t x, int64_t lo) {
+    int64_t p = lo;
+    while (p < x) p <<= 1;
+    return p;
 }
 
 // Stages of a half: one wave with the caller's rows per lane, one wave with 8,
@@ -514,11 +603,15 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     out.alns.assign(n, sfe_aln{});
     out.ops.clear();
     if (n == 0) return;
-    ExtItem *items_d = (ExtItem *)c->items_d.ensure((size_t)n * sizeof(ExtItem));
-    HalfTask *tasks = (HalfTask *)c->tasks_d.ensure((size_t)2 * n * sizeof(HalfTask));
-    HalfResult *hres = (HalfResult *)c->hres_d.ensure((size_t)2 * n * sizeof(HalfResult));
+    // recorded first launch: buffers sized for a power-of-two capacity, so that
+    // later batches of up to that many items replay the same graph
+    bool pending = c->tuning.use_graphs == 1 && !c->graphs_failed;
+    const int64_t icap = pending ? pow2_at_least(n, 4096) : n;
+    ExtItem *items_d = (ExtItem *)c->items_d.ensure((size_t)icap * sizeof(ExtItem));
+    HalfTask *tasks = (HalfTask *)c->tasks_d.ensure((size_t)2 * icap * sizeof(HalfTask));
+    HalfResult *hres = (HalfResult *)c->hres_d.ensure((size_t)2 * icap * sizeof(HalfResult));
     copy_in(c, items_d, items.data(), (size_t)n * sizeof(ExtItem));
-    launch_make_tasks(items_d, n, c->units_d.as<UnitDesc>(), idx->nt, tasks, c->stream);
+    if (!pending) launch_make_tasks(items_d, n, c->units_d.as<UnitDesc>(), idx->nt, tasks, c->stream);
     SeqSetView T = idx->target.view(), Qp = c->qplus.view(), Qm = c->qminus.view();
     bool perm = true;                   // every score fits in int8: scores come from packed row profiles
     int smax = 0;
@@ -541,10 +634,16 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     if (extent && long_cap > 0)
         for (int64_t h = 0; h < nh; h++)
             if ((*extent)[h] > std::log2((double)long_cap)) stage[h] = ST_COOP2;
-    c->sched_d.ensure(64);
+    c->sched_d.ensure(kSchedBytes);
     if (c->arenas.empty() || !c->arenas[0]->p) ensure_arena(c, default_arena(c));
-    set_run_head(c, 0);
+    if (!pending) set_run_head(c, 0);
     RunArena ra = run_arena(c, std::max<uint64_t>(1 << 12, (uint64_t)c->arena_bytes / 256), 0);
+    // the work a recorded first launch does, on the stream instead
+    auto eager_setup = [&] {
+        launch_make_tasks(items_d, n, c->units_d.as<UnitDesc>(), idx->nt, tasks, c->stream);
+        set_run_head(c, 0);
+        pending = false;
+    };
     std::vector<int32_t> todo;
     size_t ai = 0;                      // workgroup-kernel arena
     bool all = true, first = true;
@@ -576,10 +675,12 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
                 if (stage[h] == sg) lv = std::min(lv, level[h]);
             for (int32_t h : todo) (stage[h] == sg && (sg >= ST_RING || level[h] == lv) ? group : rest).push_back(h);
         }
+        if (pending && !(sg <= ST_WAVE8 && lv == 0)) eager_setup();
         const int32_t *ids = nullptr;
         int64_t cnt = nh;
+        const int64_t hcap = pending ? pow2_at_least(all ? nh : (int64_t)group.size(), 8192) : 0;
         if (!all) {
-            int32_t *idd = (int32_t *)c->ids_d.ensure(group.size() * 4);
+            int32_t *idd = (int32_t *)c->ids_d.ensure(std::max<size_t>(group.size(), (size_t)hcap) * 4);
             copy_in(c, idd, group.data(), group.size() * 4);
             ids = idd;
             cnt = (int64_t)group.size();
@@ -587,6 +688,7 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         }
         first = false;
         const bool fused = sg <= ST_COOP4;         // chunk pool + traceback in the same kernel
+        bool recorded = false;                     // launched as a replay of the recorded graph
         int64_t nwaves = 0;
         uint64_t chunk_bytes = 0;
         Arena ar{};
@@ -605,15 +707,28 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
                 count = (int64_t)persistent_per_cu(c, C, perm, narrow, wpc, dyn) * c->cu_count;
                 if (lv > 0) count = std::max<int64_t>(1, count >> std::min(62, 2 * lv));
             }
-            ChunkPool pool = make_pool(c);
             nwaves = persistent ? count : 0;
-            chunk_bytes = (uint64_t)1 << pool.shift;
-            unsigned int *qhead = (unsigned int *)(c->sched_d.as<uint8_t>() + 8);
-            HIPCHK(hipMemsetAsync(qhead, 0, 4, c->stream));
-            WorkQueue wq{ids, cnt, qhead};
-            HIPCHK(hipEventRecord(c->ev0, c->stream));
-            launch_ydrop_fused(C, perm, narrow, persistent, tasks, wq, persistent ? count : cnt, T, Qp, Qm, sc, pool,
-                               ra, hres, long_cap, dyn, c->stream);
+            if (pending) {
+                const ChunkPool pool = pool_layout(c);
+                chunk_bytes = (uint64_t)1 << pool.shift;
+                if (!launch_first_recorded(c, idx, items_d, n, icap, tasks, ids, cnt, hcap, C, perm, narrow,
+                                           persistent, count, T, Qp, Qm, sc, pool, ra, hres, long_cap, dyn)) {
+                    c->graphs_failed = true;
+                    eager_setup();
+                }
+                pending = false;
+                recorded = !c->graphs_failed;
+            }
+            if (!recorded) {
+                ChunkPool pool = make_pool(c);
+                chunk_bytes = (uint64_t)1 << pool.shift;
+                unsigned int *qhead = (unsigned int *)(c->sched_d.as<uint8_t>() + 8);
+                HIPCHK(hipMemsetAsync(qhead, 0, 4, c->stream));
+                WorkQueue wq{ids, cnt, qhead, nullptr};
+                HIPCHK(hipEventRecord(c->ev0, c->stream));
+                launch_ydrop_fused(C, perm, narrow, persistent, tasks, wq, persistent ? count : cnt, T, Qp, Qm, sc,
+                                   pool, ra, hres, long_cap, dyn, c->stream);
+            }
         } else if (sg <= ST_COOP4) {
             // wave groups; level L > 0: at most 256 / 4^(L-1) halves in flight
             const int C = sg == ST_COOP2 ? 2 : 4;
@@ -726,8 +841,8 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         if (pool_full) grow_arena(c);
         if (getenv("SFE_PROGRESS")) {
             if (fused)
-                fprintf(stderr, "[sfe]   launch: %s C=%d level %d, %lld halves, %lld waves, %llu KiB chunks, next %zu\n",
-                        sg <= ST_WAVE8 ? "wave" : "wave group", sg == ST_WAVE ? cells_per_lane : sg == ST_WAVE8 ? 8
+                fprintf(stderr, "[sfe]   launch: %s%s C=%d level %d, %lld halves, %lld waves, %llu KiB chunks, next %zu\n",
+                        sg <= ST_WAVE8 ? "wave" : "wave group", recorded ? " (graph)" : "", sg == ST_WAVE ? cells_per_lane : sg == ST_WAVE8 ? 8
                         : sg == ST_COOP2 ? 2 : 4, lv, (long long)cnt, (long long)nwaves,
                         (unsigned long long)(chunk_bytes >> 10), next.size());
             else
@@ -1127,6 +1242,7 @@ void sfe_ctx_destroy(sfe_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->round_exec) (void)hipGraphExecDestroy(c->round_exec);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1344,6 +1460,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         sfe_stats st{};
         c->ydrop_ms = c->sx_ms = 0;
         c->ydrop_launches = c->ydrop_cells = c->sx_launches = c->narrow_launches = 0;
+        c->graph_launches = c->graph_records = 0;
         QueryLayout L;
         upload_queries(c, queries, nq, strands, ix->sd.span, L);
         // --- seeds + X-drop (fused) --------------------------------------------------
@@ -1742,6 +1859,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             st.ms_total = now_ms() - t0;
             st.ydrop_launches = c->ydrop_launches;
             st.narrow_launches = c->narrow_launches;
+            st.graph_launches = c->graph_launches;
+            st.graph_records = c->graph_records;
             st.ydrop_kernel_cells = c->ydrop_cells;
             st.seed_xdrop_launches = c->sx_launches;
             st.ms_ydrop_kernel = c->ydrop_ms;

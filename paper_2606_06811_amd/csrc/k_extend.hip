@@ -46,9 +46,10 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // Half tasks of the batch items: task 2x is the forward half, 2x+1 the backward half.
-__global__ void k_make_tasks(const ExtItem *__restrict__ items, int64_t n, const UnitDesc *__restrict__ units,
-                             int64_t nt, HalfTask *__restrict__ tasks) {
+__global__ void k_make_tasks(const ExtItem *__restrict__ items, int64_t n, const int64_t *__restrict__ n_dev,
+                             const UnitDesc *__restrict__ units, int64_t nt, HalfTask *__restrict__ tasks) {
     int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n_dev) n = *n_dev;
     if (x >= n) return;
     ExtItem it = items[x];
     UnitDesc u = units[it.unit];
@@ -64,9 +65,29 @@ __global__ void k_make_tasks(const ExtItem *__restrict__ items, int64_t n, const
 }
 
 void launch_make_tasks(const ExtItem *items, int64_t n, const UnitDesc *units, int64_t nt, HalfTask *tasks,
-                       hipStream_t st) {
+                       hipStream_t st, const int64_t *n_dev) {
     if (n <= 0) return;
-    k_make_tasks<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(items, n, units, nt, tasks);
+    k_make_tasks<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(items, n, n_dev, units, nt, tasks);
+}
+
+// Clears the launch bookkeeping of a batch inside a recorded graph (a kernel,
+// not a memset node): the chunk pool's bitmap and free count, the work-queue
+// head and the run-arena head.
+__global__ void k_sched_reset(uint32_t *__restrict__ bits, int32_t nwords, int32_t *__restrict__ avail,
+                              int32_t avail0, unsigned int *__restrict__ qhead,
+                              unsigned long long *__restrict__ run_head) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < nwords) bits[x] = 0u;
+    if (x == 0) {
+        *avail = avail0;
+        *qhead = 0u;
+        *run_head = 0ull;
+    }
+}
+
+void launch_sched_reset(uint32_t *bits, int32_t nwords, int32_t *avail, int32_t avail0, unsigned int *qhead,
+                        unsigned long long *run_head, hipStream_t st) {
+    k_sched_reset<<<(unsigned)((nwords + 255) / 256), 256, 0, st>>>(bits, nwords, avail, avail0, qhead, run_head);
 }
 
 // ---------------------------------------------------------------------------

@@ -318,13 +318,16 @@ __global__ void __launch_bounds__(64) k_ydrop_fused(const HalfTask *__restrict__
     auto chunk = [&](int c) { return chunk_ptr(pool, c); };
 
     int64_t item = PERSIST ? -1 : (int64_t)blockIdx.x;
+    const int64_t nq = wq.n_dev ? *wq.n_dev : wq.n;     // halves in the queue
     for (;;) {
         if (PERSIST) {
             unsigned int q = 0;
             if (lane == 0) q = atomicAdd(wq.head, 1u);
             q = (unsigned int)__builtin_amdgcn_readfirstlane((int)q);
-            if ((int64_t)q >= wq.n) break;
+            if ((int64_t)q >= nq) break;
             item = q;
+        } else if (item >= nq) {
+            break;      // a launch sized for more halves than the queue holds
         }
         const int64_t tid = wq.ids ? wq.ids[item] : item;
         const HalfTask tk = tasks[tid];
@@ -667,13 +670,16 @@ __global__ void __launch_bounds__(64) k_ydrop_fused16(const HalfTask *__restrict
     auto chunk = [&](int c) { return chunk_ptr(pool, c); };
 
     int64_t item = PERSIST ? -1 : (int64_t)blockIdx.x;
+    const int64_t nq = wq.n_dev ? *wq.n_dev : wq.n;     // halves in the queue
     for (;;) {
         if (PERSIST) {
             unsigned int q = 0;
             if (lane == 0) q = atomicAdd(wq.head, 1u);
             q = (unsigned int)__builtin_amdgcn_readfirstlane((int)q);
-            if ((int64_t)q >= wq.n) break;
+            if ((int64_t)q >= nq) break;
             item = q;
+        } else if (item >= nq) {
+            break;      // a launch sized for more halves than the queue holds
         }
         const int64_t tid = wq.ids ? wq.ids[item] : item;
         const HalfTask tk = tasks[tid];

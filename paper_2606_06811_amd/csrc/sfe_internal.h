@@ -137,6 +137,7 @@ struct WorkQueue {
     const int32_t *ids;
     int64_t n;
     unsigned int *head;
+    const int64_t *n_dev;   // if set, the number of halves is *n_dev (read when the kernel starts)
 };
 
 // Traceback pointer arena.  Allocations of one or more ARENA_PAGE pages, a

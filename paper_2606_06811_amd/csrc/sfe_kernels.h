@@ -74,7 +74,9 @@ __global__ void k_nsum(const uint32_t *nbits, int64_t nwords, uint32_t *nsum);
 
 // gapped stage (k_extend.hip)
 void launch_make_tasks(const ExtItem *items, int64_t n, const UnitDesc *units, int64_t nt, HalfTask *tasks,
-                       hipStream_t st);
+                       hipStream_t st, const int64_t *n_dev = nullptr);
+void launch_sched_reset(uint32_t *bits, int32_t nwords, int32_t *avail, int32_t avail0, unsigned int *qhead,
+                        unsigned long long *run_head, hipStream_t st);
 // fused extension + traceback (k_fused.hip); plain: grid = wq.n blocks, one
 // half each; persistent: `grid` waves pulling halves from the queue
 // kcap > 0: a half still running at antidiagonal kcap stops with HALF_LONG

@@ -83,7 +83,8 @@ class _Stats(ctypes.Structure):
                [(n, ctypes.c_double) for n in ("ms_seed_xdrop", "ms_hsp_set", "ms_extend", "ms_total",
                                                "ms_ydrop_kernel", "ms_seed_xdrop_kernel")] + \
                [("predicted_halves", ctypes.c_int64), ("mispredicted_halves", ctypes.c_int64),
-                ("ms_predict", ctypes.c_double), ("narrow_launches", ctypes.c_int64)]
+                ("ms_predict", ctypes.c_double), ("narrow_launches", ctypes.c_int64),
+                ("graph_launches", ctypes.c_int64), ("graph_records", ctypes.c_int64)]
 
 MLP_NFEAT, MLP_NOUT, MLP_NPARAMS = 16, 4, 9668
 NOALLOC_MAX_SAMPLES = 16384

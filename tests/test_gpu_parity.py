@@ -346,6 +346,42 @@ def test_align_parity_wave_groups(ctx, align_case, policy):
     assert st["overflow_reruns"] > 0
 
 
+@pytest.mark.parametrize("K,policy,schedule,arena", [
+    (7, 1, PLAIN, 0), (64, 1, PERSIST, 0), (0, 0, PLAIN, 0), (0, 0, sfe.SFE_SCHED_BINNED, 0),
+    (16, 1, PERSIST, 1 << 20)])
+def test_align_parity_recorded_graphs(align_case, K, policy, schedule, arena):
+    """The first launch of every batch run as a replay of a recorded graph
+    (device-side counts): the same alignments and edit operations as the
+    oracle and as stream launches, over two calls on one context (the second
+    replays what the first recorded), with stream work and synchronisation
+    between the replays; a small arena adds re-runs and regrowth."""
+    log(f"align with recorded graphs K={K} policy={policy} schedule={schedule} arena={arena}")
+    T, Q, ref = align_case
+    c = sfe.sfe_ctx_create(0)
+    try:
+        idx = sfe.sfe_build_index(c, T, PATTERN, 1, 1)
+        kw = dict(round_k=K, policy=policy, schedule=schedule, arena_bytes=arena)
+        eager = sfe.sfe_align(c, idx, Q, dict(synth.SCORING), **kw)
+        assert eager[2]["graph_launches"] == 0
+        sfe.sfe_ctx_set_tuning(c, use_graphs=1)
+        launches = records = 0
+        for call in range(2):
+            alns, ops, st = sfe.sfe_align(c, idx, Q, dict(synth.SCORING), **kw)
+            compare_alignments(alns, ops, ref)
+            assert np.array_equal(alns, eager[0]) and np.array_equal(ops, eager[1]), call
+            assert st["graph_launches"] >= 1, call
+            launches += st["graph_launches"]
+            records += st["graph_records"]
+        assert launches > records        # replays of an earlier recording happened
+        sfe.sfe_ctx_set_tuning(c)
+        alns, ops, st = sfe.sfe_align(c, idx, Q, dict(synth.SCORING), **kw)
+        assert st["graph_launches"] == 0
+        assert np.array_equal(alns, eager[0]) and np.array_equal(ops, eager[1])
+        idx.close()
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("arena,schedule", [(1 << 20, PLAIN), (1 << 20, PERSIST), (3 << 18, PLAIN)])
 def test_align_tiny_arena_reruns(align_case, arena, schedule):
     """A small traceback arena (fresh context, so the run arena starts small
