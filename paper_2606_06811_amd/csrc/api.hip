@@ -1355,9 +1355,8 @@ sfe_status sfe_ungapped_xdrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *qu
         sfe_hsp *raw = (sfe_hsp *)c->hsp_raw.ensure((size_t)n * sizeof(sfe_hsp));
         int *err = (int *)c->counters.as<char>() + 8;
         HIPCHK(hipMemsetAsync(err, 0, 4, c->stream));
-        k_xdrop_raw<<<grid(n, 256), 256, 0, c->stream>>>(hd, n, c->qdesc_d.as<QueryDesc>(), nq, ix->target.view(), 0,
-                                                        ix->nt, c->qplus.view(), c->qminus.view(), sc, ix->sd.span, raw,
-                                                        err);
+        launch_xdrop_raw(hd, n, c->qdesc_d.as<QueryDesc>(), nq, ix->target.view(), 0, ix->nt, c->qplus.view(),
+                         c->qminus.view(), sc, ix->sd.span, raw, err, c->stream);
         HIPCHK(hipGetLastError());
         int herr = 0;
         HIPCHK(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, c->stream));
@@ -1508,10 +1507,9 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 unsigned long long *cnt = c->counters.as<unsigned long long>();
                 HIPCHK(hipMemsetAsync(cnt, 0, 32, c->stream));
                 HIPCHK(hipEventRecord(c->ev0, c->stream));
-                k_seed_xdrop<<<(unsigned)nch, 256, 0, c->stream>>>(c->units_d.as<UnitDesc>(), c->chunks_d.as<Chunk>(),
-                                                                  ix->target.view(), 0, ix->nt, c->qplus.view(),
-                                                                  c->qminus.view(), ix->offsets.as<uint32_t>(),
-                                                                  ix->pos.as<uint32_t>(), ix->sd, sc, raw, capraw, cnt);
+                launch_seed_xdrop(c->units_d.as<UnitDesc>(), c->chunks_d.as<Chunk>(), nch, ix->target.view(), 0, ix->nt,
+                                  c->qplus.view(), c->qminus.view(), ix->offsets.as<uint32_t>(), ix->pos.as<uint32_t>(),
+                                  ix->sd, sc, raw, capraw, cnt, c->stream);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipEventRecord(c->ev1, c->stream));
                 unsigned long long hc[4];

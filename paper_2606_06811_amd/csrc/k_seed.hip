@@ -185,101 +185,159 @@ __device__ __forceinline__ int code_at(const Codes16 &c, int u) {
     return ((c.n >> u) & 1u) ? 4 : (int)((c.c2 >> (2 * u)) & 3u);
 }
 
-// t, q relative to their sequences (which start at tb / qb in their sets and
-// have lengths nt / nq).  sub: 5x8 table in LDS.  Columns are read 16 at a
-// time (two words per side), their scores looked up together, then scanned
-// in order; the scan stops exactly where the column-by-column rule does.
-__device__ __forceinline__ XResult xdrop_one(const SeqSetView &T, int64_t tb, int64_t nt, const SeqSetView &Q,
-                                             int64_t qb, int64_t nq, int64_t t, int64_t q, int span,
-                                             const int *sub, int32_t X) {
-    int32_t s0 = 0;
-    {
-        const Codes16 a0 = codes16(T, tb + t), b0 = codes16(Q, qb + q);
-        const Codes16 a1 = codes16(T, tb + t + 16), b1 = codes16(Q, qb + q + 16);
-        for (int u = 0; u < span; u++)
-            s0 += u < 16 ? sub[code_at(a0, u) * 8 + code_at(b0, u)] : sub[code_at(a1, u - 16) * 8 + code_at(b1, u - 16)];
+// Tables of the ungapped filter in LDS: sub[a * 8 + b] for codes a, b in
+// 0..4 (N = 4), and the 16 N-free pairs at (a << 2) | b, as int8 when every
+// score fits (I8) or int32.
+struct XTables {
+    int sub[40];
+    int sub16[16];
+    int8_t sub8[16];
+};
+
+__device__ __forceinline__ void load_xtables(XTables &x, const ScoreDesc &sc) {
+    const int i = threadIdx.x;
+    if (i < 40) x.sub[i] = (i & 7) < 5 ? sc.sub[i >> 3][i & 7] : 0;
+    if (i < 16) {
+        x.sub16[i] = sc.sub[i >> 2][i & 3];
+        x.sub8[i] = (int8_t)sc.sub[i >> 2][i & 3];
     }
-    bool range = false;
-    // right of the seed: columns r = 1 .. lim at t + span - 1 + r
-    int32_t s = 0, bR = 0;
-    int64_t R = 0;
-    int32_t work = span;
-    {
-        int64_t lim = nt - t - span;
-        if (nq - q - span < lim) lim = nq - q - span;
-        bool stop = false;
-        for (int64_t r0 = 1; r0 <= lim && !stop; r0 += 16) {
-            const int m = (int)min((int64_t)16, lim - r0 + 1);
-            const Codes16 a = codes16(T, tb + t + span - 1 + r0), b = codes16(Q, qb + q + span - 1 + r0);
-            int sv[16];
+}
+
+template <bool I8>
+__device__ __forceinline__ int pair_score(const XTables &x, uint32_t ca, uint32_t cb, int i) {
+    const uint32_t idx = (((ca >> (2 * i)) & 3u) << 2) | ((cb >> (2 * i)) & 3u);
+    return I8 ? (int)x.sub8[idx] : x.sub16[idx];
+}
+
+// Codes of a 16-base block in reverse order: the block of m <= 16 bases whose
+// base u (u < m) becomes position m - 1 - u.
+__device__ __forceinline__ Codes16 reverse16(Codes16 c, int m) {
+    uint32_t r = __builtin_bitreverse32(c.c2);                      // field u -> 15 - u, its two bits swapped
+    r = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+    const uint32_t n = __builtin_bitreverse32(c.n & 0xffffu);        // bit u -> 31 - u
+    return Codes16{r >> (2 * (16 - m)), n >> (32 - m)};
+}
+
+// Score of the seed span (span <= 32 columns from t, q).
+template <bool I8>
+__device__ __forceinline__ int32_t span_score(const SeqSetView &T, int64_t pt, const SeqSetView &Q, int64_t pq,
+                                              int span, const XTables &x) {
+    int32_t s0 = 0;
+    for (int h = 0; h < span; h += 16) {
+        const Codes16 a = codes16(T, pt + h), b = codes16(Q, pq + h);
+        const int m = min(16, span - h);
+        if (((a.n | b.n) & 0xffffu) == 0) {
 #pragma unroll
-            for (int i = 0; i < 16; i++) sv[i] = sub[code_at(a, i) * 8 + code_at(b, i)];
-            for (int i = 0; i < m; i++) {
-                s += sv[i];
-                work++;
-                if (s > bR) {
-                    bR = s;
-                    R = r0 + i;
-                    if (bR >= SFE_SCORE_LIMIT) { range = true; stop = true; break; }
-                } else if (bR - s > X) {
-                    stop = true;
-                    break;
-                }
-            }
+            for (int i = 0; i < 16; i++)
+                if (i < m) s0 += pair_score<I8>(x, a.c2, b.c2, i);
+        } else {
+            for (int i = 0; i < m; i++) s0 += x.sub[code_at(a, i) * 8 + code_at(b, i)];
         }
     }
-    // left of the seed: columns r = 1 .. lim at t - r
-    int32_t bL = 0;
-    int64_t L = 0;
-    if (!range) {
-        const int64_t lim = t < q ? t : q;
-        s = 0;
-        bool stop = false;
-        for (int64_t r0 = 1; r0 <= lim && !stop; r0 += 16) {
-            const int m = (int)min((int64_t)16, lim - r0 + 1);
-            // bases t - r0 - m + 1 .. t - r0: column r0 + i is bit m - 1 - i
-            const Codes16 a = codes16(T, tb + t - r0 - m + 1), b = codes16(Q, qb + q - r0 - m + 1);
-            int sv[16];
-#pragma unroll
-            for (int i = 0; i < 16; i++) {
-                const int u = (m - 1 - i) & 15;
-                sv[i] = sub[code_at(a, u) * 8 + code_at(b, u)];
+    return s0;
+}
+
+// Ungapped X-drop of one hit (t, q relative to their sequences, which start
+// at tb / qb in their sets and have lengths nt / nq): the seed span, then the
+// scan to the right of it and the scan to the left, each stopping at the first
+// column where best - running > X (a strictly better running score moves the
+// end; the sequence ends stop it too).  The two scans run in one loop of
+// 16-column blocks, so a lane whose right scan ends early starts its left scan
+// while the other lanes of its wave are still scanning right.  A block without
+// N takes the unrolled path (pair scores from the 16-entry table, the stop
+// rule applied column by column through a live flag); the last, partial block
+// of a scan and blocks with an N take the column loop.  work counts the
+// columns scored, the span included.
+template <bool I8>
+__device__ __forceinline__ XResult xdrop_hit(const SeqSetView &T, int64_t tb, int64_t nt, const SeqSetView &Q,
+                                             int64_t qb, int64_t nq, int64_t t, int64_t q, int span,
+                                             const XTables &x, int32_t X) {
+    const int32_t s0 = span_score<I8>(T, tb + t, Q, qb + q, span, x);
+    int32_t work = span;
+    bool range = false;
+    int side = 0;                                   // 0 right, 1 left
+    int64_t lim = min(nt - t - span, nq - q - span);
+    int64_t r0 = 1, arg = 0, R = 0;
+    int32_t s = 0, best = 0, bR = 0;
+    for (;;) {
+        const int64_t left = lim - r0 + 1;        // columns not yet scanned on this side
+        bool done = left <= 0;
+        if (!done) {
+            const int m = (int)min((int64_t)16, left);
+            // right: bases t + span - 1 + r of both; left: t - r, read as the block ending at t - r0
+            const int64_t pt = side ? tb + t - r0 - m + 1 : tb + t + span - 1 + r0;
+            const int64_t pq = side ? qb + q - r0 - m + 1 : qb + q + span - 1 + r0;
+            Codes16 a = codes16(T, pt), b = codes16(Q, pq);
+            if (side) {
+                a = reverse16(a, m);
+                b = reverse16(b, m);
             }
-            for (int i = 0; i < m; i++) {
-                s += sv[i];
-                work++;
-                if (s > bL) {
-                    bL = s;
-                    L = r0 + i;
-                    if (bL >= SFE_SCORE_LIMIT) { range = true; stop = true; break; }
-                } else if (bL - s > X) {
-                    stop = true;
-                    break;
+            const int32_t best0 = best;
+            int argi = 0;
+            bool live = true;
+            if (m == 16 && ((a.n | b.n) & 0xffffu) == 0) {
+                int sv[16];
+#pragma unroll
+                for (int i = 0; i < 16; i++) sv[i] = pair_score<I8>(x, a.c2, b.c2, i);
+#pragma unroll
+                for (int i = 0; i < 16; i++) {
+                    s += sv[i];
+                    work += live ? 1 : 0;
+                    const bool up = live && s > best;
+                    best = up ? s : best;
+                    argi = up ? i : argi;
+                    live = live && best - s <= X;
+                }
+            } else {
+                for (int i = 0; i < m && live; i++) {
+                    s += x.sub[code_at(a, i) * 8 + code_at(b, i)];
+                    work++;
+                    if (s > best) { best = s; argi = i; }
+                    else if (best - s > X) live = false;
                 }
             }
+            if (best > best0) arg = r0 + argi;
+            range = best >= SFE_SCORE_LIMIT;
+            r0 += 16;
+            done = !live || range || m < 16;
+        }
+        if (done) {
+            if (side == 0 && !range) {
+                bR = best;
+                R = arg;
+                side = 1;
+                lim = min(t, q);
+                r0 = 1;
+                s = best = 0;
+                arg = 0;
+                continue;
+            }
+            break;
         }
     }
     XResult res;
-    res.t0 = t - L;
-    res.q0 = q - L;
-    res.len = L + span + R;
-    res.score = s0 + bL + bR;
+    if (side == 0) { bR = best; R = arg; best = 0; arg = 0; }   // stopped by the score range on the right
+    res.t0 = t - arg;
+    res.q0 = q - arg;
+    res.len = arg + span + R;
+    res.score = s0 + best + bR;
     res.work = work;
     res.range = range;
     return res;
 }
 
+template <bool I8>
 __global__ void k_xdrop_raw(const sfe_hit *__restrict__ hits, int64_t n, const QueryDesc *__restrict__ qd,
                             int32_t nq, SeqSetView T, int64_t tb, int64_t nt, SeqSetView Qp, SeqSetView Qm,
                             ScoreDesc sc, int span, sfe_hsp *__restrict__ out, int *__restrict__ err) {
-    __shared__ int sub[40];
-    if (threadIdx.x < 40) sub[threadIdx.x] = (threadIdx.x & 7) < 5 ? sc.sub[threadIdx.x >> 3][threadIdx.x & 7] : 0;
+    __shared__ XTables xt;
+    load_xtables(xt, sc);
     __syncthreads();
     int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     sfe_hit h = hits[x];
     QueryDesc d = qd[h.query_id];
-    XResult r = xdrop_one(T, tb, nt, h.strand ? Qm : Qp, d.start, d.len, h.t, h.q, span, sub, sc.xdrop);
+    XResult r = xdrop_hit<I8>(T, tb, nt, h.strand ? Qm : Qp, d.start, d.len, h.t, h.q, span, xt, sc.xdrop);
     if (r.range) atomicOr(err, 1);
     sfe_hsp o;
     o.t0 = (uint32_t)r.t0;
@@ -295,19 +353,20 @@ __global__ void k_xdrop_raw(const sfe_hit *__restrict__ hits, int64_t n, const Q
 // Fused seed + X-drop: a block takes one chunk of 64 windows; its threads
 // walk the chunk's hits (flattened over windows and buckets) and append the
 // passing segments.  Hits never leave the chip.
+template <bool I8>
 __global__ void __launch_bounds__(256) k_seed_xdrop(const UnitDesc *__restrict__ units, const Chunk *__restrict__ chunks,
                                                     SeqSetView T, int64_t tb, int64_t nt, SeqSetView Qp, SeqSetView Qm,
                                                     const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ tpos,
                                                     SeedDesc sd, ScoreDesc sc, sfe_hsp *__restrict__ out, uint64_t cap,
                                                     unsigned long long *__restrict__ counters) {
-    __shared__ int sub[40];
+    __shared__ XTables xt;
     __shared__ uint32_t s_bstart[64][16];
     __shared__ uint32_t s_bcum[64][17];     // cumulative bucket counts per window
     __shared__ uint32_t s_wcum[65];         // cumulative hit counts over windows
     Chunk c = chunks[blockIdx.x];
     UnitDesc u = units[c.unit];
     const SeqSetView Q = u.strand ? Qm : Qp;
-    if (threadIdx.x < 40) sub[threadIdx.x] = (threadIdx.x & 7) < 5 ? sc.sub[threadIdx.x >> 3][threadIdx.x & 7] : 0;
+    load_xtables(xt, sc);
     if (threadIdx.x < 64) {
         int64_t q = (int64_t)c.w0 + threadIdx.x;
         uint32_t bs[17], bc[17];
@@ -331,7 +390,6 @@ __global__ void __launch_bounds__(256) k_seed_xdrop(const UnitDesc *__restrict__
     __syncthreads();
     uint32_t total = s_wcum[64];
     if (threadIdx.x == 0 && total) atomicAdd(&counters[0], (unsigned long long)total);
-    uint32_t passed = 0;
     unsigned long long work = 0;
     for (uint32_t h = threadIdx.x; h < total; h += blockDim.x) {
         // window: last w with s_wcum[w] <= h
@@ -346,12 +404,11 @@ __global__ void __launch_bounds__(256) k_seed_xdrop(const UnitDesc *__restrict__
         while (s_bcum[w][b + 1] <= r) b++;
         uint32_t t = tpos[s_bstart[w][b] + (r - s_bcum[w][b])];
         int64_t q = (int64_t)c.w0 + w;
-        XResult x = xdrop_one(T, tb, nt, Q, u.seq_start, u.len, t, q, sd.span, sub, sc.xdrop);
+        XResult x = xdrop_hit<I8>(T, tb, nt, Q, u.seq_start, u.len, t, q, sd.span, xt, sc.xdrop);
         work += (unsigned long long)x.work;
         if (x.range) atomicOr((unsigned long long *)&counters[3], 1ull);
         if (x.score >= sc.hsp_thresh) {
             unsigned long long slot = atomicAdd(&counters[1], 1ull);
-            passed++;
             if (slot < cap) {
                 sfe_hsp o;
                 o.t0 = (uint32_t)x.t0;
@@ -365,10 +422,39 @@ __global__ void __launch_bounds__(256) k_seed_xdrop(const UnitDesc *__restrict__
             }
         }
     }
-    (void)passed;
     // columns scored, summed over the wave, one atomic per wave
     for (int m = 32; m >= 1; m >>= 1) work += __shfl_xor(work, m, 64);
     if ((threadIdx.x & 63) == 0 && work) atomicAdd(&counters[2], work);
+}
+
+bool scores_fit_int8(const ScoreDesc &sc) {
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++)
+            if (sc.sub[a][b] < -128 || sc.sub[a][b] > 127) return false;
+    return true;
+}
+
+void launch_xdrop_raw(const sfe_hit *hits, int64_t n, const QueryDesc *qd, int32_t nq, SeqSetView T, int64_t tb,
+                      int64_t nt, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, int span, sfe_hsp *out, int *err,
+                      hipStream_t st) {
+    if (n <= 0) return;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (scores_fit_int8(sc))
+        k_xdrop_raw<true><<<g, 256, 0, st>>>(hits, n, qd, nq, T, tb, nt, Qp, Qm, sc, span, out, err);
+    else
+        k_xdrop_raw<false><<<g, 256, 0, st>>>(hits, n, qd, nq, T, tb, nt, Qp, Qm, sc, span, out, err);
+}
+
+void launch_seed_xdrop(const UnitDesc *units, const Chunk *chunks, int64_t nch, SeqSetView T, int64_t tb, int64_t nt,
+                       SeqSetView Qp, SeqSetView Qm, const uint32_t *offsets, const uint32_t *tpos, const SeedDesc &sd,
+                       const ScoreDesc &sc, sfe_hsp *out, uint64_t cap, unsigned long long *counters, hipStream_t st) {
+    if (nch <= 0) return;
+    if (scores_fit_int8(sc))
+        k_seed_xdrop<true><<<(unsigned)nch, 256, 0, st>>>(units, chunks, T, tb, nt, Qp, Qm, offsets, tpos, sd, sc, out,
+                                                          cap, counters);
+    else
+        k_seed_xdrop<false><<<(unsigned)nch, 256, 0, st>>>(units, chunks, T, tb, nt, Qp, Qm, offsets, tpos, sd, sc,
+                                                           out, cap, counters);
 }
 
 // ---------------------------------------------------------------------------

@@ -48,12 +48,13 @@ __global__ void k_seed_count(const UnitDesc *units, const Chunk *chunks, SeqSetV
 __global__ void k_seed_emit(const UnitDesc *units, const Chunk *chunks, SeqSetView Qp, SeqSetView Qm,
                             const uint32_t *offsets, const uint32_t *tpos, SeedDesc sd, const uint64_t *hit_off,
                             sfe_hit *out);
-__global__ void k_xdrop_raw(const sfe_hit *hits, int64_t n, const QueryDesc *qd, int32_t nq, SeqSetView T, int64_t tb,
-                            int64_t nt, SeqSetView Qp, SeqSetView Qm, ScoreDesc sc, int span, sfe_hsp *out,
-                            int *err);
-__global__ void k_seed_xdrop(const UnitDesc *units, const Chunk *chunks, SeqSetView T, int64_t tb, int64_t nt,
-                             SeqSetView Qp, SeqSetView Qm, const uint32_t *offsets, const uint32_t *tpos, SeedDesc sd,
-                             ScoreDesc sc, sfe_hsp *out, uint64_t cap, unsigned long long *counters);
+// ungapped X-drop of given hits, and the fused seed + X-drop over query chunks
+void launch_xdrop_raw(const sfe_hit *hits, int64_t n, const QueryDesc *qd, int32_t nq, SeqSetView T, int64_t tb,
+                      int64_t nt, SeqSetView Qp, SeqSetView Qm, const ScoreDesc &sc, int span, sfe_hsp *out, int *err,
+                      hipStream_t st);
+void launch_seed_xdrop(const UnitDesc *units, const Chunk *chunks, int64_t nch, SeqSetView T, int64_t tb, int64_t nt,
+                       SeqSetView Qp, SeqSetView Qm, const uint32_t *offsets, const uint32_t *tpos, const SeedDesc &sd,
+                       const ScoreDesc &sc, sfe_hsp *out, uint64_t cap, unsigned long long *counters, hipStream_t st);
 __global__ void k_hsp_key(const sfe_hsp *h, const uint32_t *perm, int64_t n, int field, uint32_t *key);
 __global__ void k_iota(uint32_t *a, int64_t n);
 

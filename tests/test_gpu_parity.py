@@ -154,6 +154,58 @@ def test_xdrop_raw_parity(ctx, seeded):
             assert np.array_equal(g[f].astype(np.int64), ref[f]), f
 
 
+@pytest.mark.parametrize("scale", [1, 200])
+def test_xdrop_raw_parity_scaled(ctx, seeded, scale):
+    """Scores scaled by 200 no longer fit int8, so the filter reads its 32-bit
+    pair table; both tables give the oracle's segments."""
+    log(f"x-drop raw parity, scores x{scale}")
+    T, Q, idx, hits = seeded
+    sc = dict(synth.SCORING)
+    sc["sub"] = [[v * scale for v in row] for row in sc["sub"]]
+    sc["xdrop"] *= scale
+    got = sfe.sfe_ungapped_xdrop(ctx, idx, Q, hits, sc, raw=True)
+    for qid, s, tc, ts, c, m in oracle_units(T, Q):
+        sel = (hits["query_id"] == qid) & (hits["strand"] == s)
+        ref = oracle.xdrop(tc, c, hits["t"][sel], hits["q"][sel], 19, sc)
+        for f in ("t0", "q0", "len", "score"):
+            assert np.array_equal(got[sel][f].astype(np.int64), ref[f]), f
+
+
+@pytest.mark.parametrize("xdrop", [910, 0, 1 << 20])
+def test_xdrop_edges(ctx, xdrop):
+    """Hits placed at and around both sequence ends and the 16-column block
+    boundaries of the scan, on a near-identical pair (scans reach the ends)
+    with N runs next to some hits: every segment equals the oracle's."""
+    log(f"x-drop edge hits, xdrop={xdrop}")
+    rng = synth.rng_for(4242)
+    n = 700
+    t = synth.iid_codes(rng, n)
+    q, _ = synth.mutate(rng, t, np.zeros(n, bool), 0.02, indel=0.0)
+    m = min(n, q.shape[0])
+    T, Qa = synth.to_ascii(t), synth.to_ascii(q[:m])
+    for a in (40, 41, 300):
+        T[a:a + 3] = ord("N")
+    Qa[500:504] = ord("N")
+    T[200:260] += 32            # soft-masked: scored like upper case
+    sc = dict(synth.SCORING, xdrop=xdrop)
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    span = len(PATTERN)
+    pos = sorted({p for b in (0, 16, 32, 48, 64, 250, 480) for p in (b - 1, b, b + 1, b + 15, b + 17)
+                  if 0 <= p} | {m - span - k for k in (0, 1, 2, 15, 16, 17, 33)})
+    pos = [p for p in pos if p + span <= m]
+    pairs = [(a, a) for a in pos] + [(a, b) for a in pos[::3] for b in pos[1::4]]
+    hits = np.zeros(len(pairs), sfe.HIT_DTYPE)
+    hits["t"] = [a for a, _ in pairs]
+    hits["q"] = [b for _, b in pairs]
+    got = sfe.sfe_ungapped_xdrop(ctx, idx, [Qa], hits, sc, raw=True)
+    tc, _ = oracle.encode(T)
+    qc, _ = oracle.encode(Qa)
+    ref = oracle.xdrop(tc, qc, hits["t"], hits["q"], span, sc)
+    for f in ("t0", "q0", "len", "score"):
+        assert np.array_equal(got[f].astype(np.int64), ref[f]), (f, np.nonzero(got[f].astype(np.int64) != ref[f]))
+    idx.close()
+
+
 @pytest.mark.parametrize("xdrop", [910, 0, 1 << 28])
 def test_hsp_set_parity(ctx, seeded, xdrop):
     log(f"hsp set parity xdrop={xdrop}")
@@ -316,6 +368,8 @@ def test_align_parity(ctx, align_case, K, cpl, policy, schedule):
     compare_alignments(alns, ops, ref)
     assert st["committed"] == alns.shape[0]
     assert st["extensions"] >= ref["n_extensions"]
+    # columns the ungapped filter scored, over every hit, as the oracle counts them
+    assert st["xdrop_columns"] == sum(int(u["raw"]["work"].sum()) for u in ref["units"])
 
 
 def test_align_parity_wide_scores(ctx, align_case):
