@@ -762,8 +762,10 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         if (fused) HIPCHK(hipEventRecord(c->ev1, c->stream));
         copy_out(c, hr.data(), hres, hr.size() * sizeof(HalfResult));
         sync(c);
+        double launch_ms = 0;
         if (fused) {
-            c->ydrop_ms += event_ms(c);
+            launch_ms = event_ms(c);
+            c->ydrop_ms += launch_ms;
             c->ydrop_launches++;
             if (narrow && sg <= ST_WAVE8) c->narrow_launches++;
         }
@@ -840,11 +842,15 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
         if (arena_full) ai++;
         if (pool_full) grow_arena(c);
         if (getenv("SFE_PROGRESS")) {
+            int32_t kmax_seen = 0;      // antidiagonals of the longest half of the launch
+            if (all) for (int32_t h = 0; h < nh; h++) kmax_seen = std::max(kmax_seen, hr[h].k_last);
+            else for (int32_t h : group) kmax_seen = std::max(kmax_seen, hr[h].k_last);
             if (fused)
-                fprintf(stderr, "[sfe]   launch: %s%s C=%d level %d, %lld halves, %lld waves, %llu KiB chunks, next %zu\n",
+                fprintf(stderr, "[sfe]   launch: %s%s C=%d level %d, %lld halves, %lld waves, %llu KiB chunks, next %zu; "
+                        "%.1f ms, longest half %d antidiagonals\n",
                         sg <= ST_WAVE8 ? "wave" : "wave group", recorded ? " (graph)" : "", sg == ST_WAVE ? cells_per_lane : sg == ST_WAVE8 ? 8
                         : sg == ST_COOP2 ? 2 : 4, lv, (long long)cnt, (long long)nwaves,
-                        (unsigned long long)(chunk_bytes >> 10), next.size());
+                        (unsigned long long)(chunk_bytes >> 10), next.size(), launch_ms, kmax_seen);
             else
                 fprintf(stderr, "[sfe]   launch: workgroup stage %d, %lld halves, arena %zu%s, next %zu\n", sg,
                         (long long)cnt, ai, arena_full ? " (full)" : "", next.size());
@@ -1000,24 +1006,37 @@ struct BoxGrid {
 // (so sorted by t and disjoint in t) and is entered in every 16 kbp target
 // bin its box touches; a test reads the alignments of one bin, checks the box
 // and binary-searches the run that could hold t.
+// M runs of computed extensions: run start (target), length, and diagonal
+// minus the alignment's start diagonal.
+struct RunStore {
+    std::vector<uint32_t> rt, rl;
+    std::vector<int32_t> rd;
+};
+
+// Paths (the M runs of one alignment each, in a RunStore) binned by target
+// position; several sets may share one store.
 struct PathSet {
     static const int SH = 14;
     struct Path { uint32_t t0, t1, q0, q1; size_t owner; size_t first; uint32_t count; };
+    const RunStore *rs = nullptr;
     std::vector<Path> paths;
-    std::vector<uint32_t> rt, rl;      // run start (target) and length
-    std::vector<int32_t> rd;           // run diagonal minus the alignment's start diagonal
     std::vector<std::vector<uint32_t>> bins;    // by target position >> SH
-    void reset(int64_t nt) { bins.assign((size_t)(nt >> SH) + 2, {}); }
-    void add(const sfe_aln &a, const uint32_t *ops, size_t owner) {
-        Path P{a.t_start, a.t_end, a.q_start, a.q_end, owner, rt.size(), 0};
+    void reset(int64_t nt, const RunStore *store) {
+        rs = store;
+        paths.clear();
+        bins.assign((size_t)(nt >> SH) + 2, {});
+    }
+    // appends a's M runs to the store; returns the new path's id, or -1 when it has none
+    static int64_t append_runs(RunStore &st, const sfe_aln &a, const uint32_t *ops, size_t &first, uint32_t &count) {
+        first = st.rt.size();
         uint32_t t = a.t_start, q = a.q_start;
         const int64_t d0 = (int64_t)a.t_start - (int64_t)a.q_start;
         for (uint32_t x = 0; x < a.ops_len; x++) {
             const uint32_t len = ops[x] >> 2, op = ops[x] & 3u;
             if (op == 0) {
-                rt.push_back(t);
-                rl.push_back(len);
-                rd.push_back((int32_t)((int64_t)t - (int64_t)q - d0));
+                st.rt.push_back(t);
+                st.rl.push_back(len);
+                st.rd.push_back((int32_t)((int64_t)t - (int64_t)q - d0));
                 t += len;
                 q += len;
             } else if (op == 1) {
@@ -1026,18 +1045,25 @@ struct PathSet {
                 t += len;
             }
         }
-        P.count = (uint32_t)(rt.size() - P.first);
-        if (P.count == 0 || a.t_end <= a.t_start) return;
-        const uint32_t id = (uint32_t)paths.size();
-        paths.push_back(P);
-        for (uint32_t b = a.t_start >> SH; b <= (a.t_end - 1) >> SH; b++) bins[b].push_back(id);
+        count = (uint32_t)(st.rt.size() - first);
+        return count;
     }
-    // (t, q) on an M column of a path whose owner passes `pre` (cheap, tested before the
-    // search) and then `post` (tested only on a match)
-    template <class Pre, class Post>
-    bool contains(uint32_t t, uint32_t q, Pre pre, Post post) const {
+    // a path over runs [first, first + count) of the store; returns its id, or -1 if empty
+    int64_t link(const sfe_aln &a, size_t first, uint32_t count, size_t owner) {
+        if (count == 0 || a.t_end <= a.t_start) return -1;
+        const uint32_t id = (uint32_t)paths.size();
+        paths.push_back(Path{a.t_start, a.t_end, a.q_start, a.q_end, owner, first, count});
+        for (uint32_t b = a.t_start >> SH; b <= (a.t_end - 1) >> SH; b++) bins[b].push_back(id);
+        return id;
+    }
+    // visits the owners of the paths that have (t, q) on an M column and pass `pre` (cheap,
+    // tested before the search); stops when `found` returns true, and returns whether it did
+    template <class Pre, class Found>
+    bool search(uint32_t t, uint32_t q, Pre pre, Found found) const {
         const size_t b = (size_t)(t >> SH);
         if (b >= bins.size()) return false;
+        const uint32_t *rt = rs->rt.data(), *rl = rs->rl.data();
+        const int32_t *rd = rs->rd.data();
         for (uint32_t id : bins[b]) {
             const Path &P = paths[id];
             if (t < P.t0 || t >= P.t1 || q < P.q0 || q >= P.q1 || !pre(P.owner)) continue;
@@ -1049,24 +1075,44 @@ struct PathSet {
                 else hi = mid;
             }
             if (rt[lo] <= t && t < rt[lo] + rl[lo] &&
-                (int64_t)t - (int64_t)q - ((int64_t)P.t0 - (int64_t)P.q0) == (int64_t)rd[lo] && post(P.owner))
+                (int64_t)t - (int64_t)q - ((int64_t)P.t0 - (int64_t)P.q0) == (int64_t)rd[lo] && found(P.owner))
                 return true;
         }
         return false;
     }
+    // (t, q) on an M column of a path whose owner passes `pre` and then `post`
+    template <class Pre, class Post>
+    bool contains(uint32_t t, uint32_t q, Pre pre, Post post) const { return search(t, q, pre, post); }
 };
 
-// M runs of computed extensions of one unit, each tagged with the position of
-// its HSP in the walking order.
 // Every passing extension's M runs of one (query, strand) unit, owner = its
-// position in the walking order; committed ones are flagged in `committed`.
-// Alg. 1's containment test reads the committed ones; the deferral rule reads
-// the ones still waiting for commit.
+// position in the walking order, in `set`; the committed ones also in `done`
+// (same runs).  Alg. 1's containment test reads `done`; the deferral rule
+// reads `set`, restricted to the extensions still waiting for commit.
 struct UnitPaths {
-    PathSet set;
+    RunStore runs;
+    PathSet set, done;
+    std::vector<size_t> run_first;      // per position: its runs in the store
+    std::vector<uint32_t> run_count;
     std::vector<uint8_t> committed;
+    void reset(int64_t nt, size_t n) {
+        runs = RunStore{};
+        set.reset(nt, &runs);
+        done.reset(nt, &runs);
+        run_first.assign(n, 0);
+        run_count.assign(n, 0);
+        committed.assign(n, 0);
+    }
+    void add(const sfe_aln &a, const uint32_t *ops, size_t p) {
+        PathSet::append_runs(runs, a, ops, run_first[p], run_count[p]);
+        set.link(a, run_first[p], run_count[p], p);
+    }
+    void commit(const sfe_aln &a, size_t p) {
+        committed[p] = 1;
+        done.link(a, run_first[p], run_count[p], p);
+    }
     bool in_committed(uint32_t t, uint32_t q) const {
-        return set.contains(t, q, [&](size_t o) { return committed[o] != 0; }, [](size_t) { return true; });
+        return done.contains(t, q, [](size_t) { return true; }, [](size_t) { return true; });
     }
 };
 
@@ -1568,9 +1614,10 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         std::vector<std::vector<size_t>> open(NU);               // positions in state 0, ascending
         std::vector<UnitPaths> paths(NU);
         // deferral rule: a waiting extension is "doomed" when it will most likely be skipped at
-        // commit (memo per scan: stamp, value; `perm` = its anchor lies in a committed alignment)
-        std::vector<std::vector<uint32_t>> doom_stamp(NU);
-        std::vector<std::vector<uint8_t>> doom_val(NU), doom_perm(NU);
+        // commit (`perm`: its anchor lies in a committed alignment, for good); `wait` of an open
+        // HSP: 1 its anchor lies on the path of an earlier waiting extension that is not
+        // doomed, 2 in a committed alignment (skipped for good), 0 neither
+        std::vector<std::vector<uint8_t>> doom_val(NU), doom_perm(NU), wait(NU);
         for (size_t u = 0; u < NU; u++) {
             const size_t n = per_unit[u].size();
             state[u].assign(n, 0);
@@ -1578,11 +1625,10 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             for (size_t p = 0; p < n; p++) open[u][p] = p;
             ext[u].resize(n);
             ext_batch[u].assign(n, 0);
-            paths[u].committed.assign(n, 0);
-            paths[u].set.reset(ix->nt);
-            doom_stamp[u].assign(n, 0);
+            paths[u].reset(ix->nt, n);
             doom_val[u].assign(n, 0);
             doom_perm[u].assign(n, 0);
+            wait[u].assign(n, 0);
         }
         std::vector<size_t> cursor(NU, 0);
         std::vector<BoxGrid> boxes(NU);
@@ -1596,28 +1642,6 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         const bool defer = o.policy == SFE_POLICY_DEFER;
         const bool progress = getenv("SFE_PROGRESS") != nullptr;
         const int64_t DB = o.near_band;                              // diagonal band of the nearness rule (< 0: off)
-        uint32_t scan_no = 0;
-        // doomed: the anchor of waiting extension p lies in a committed alignment, or on the
-        // path of an earlier waiting extension that is not itself doomed (depth-capped; the
-        // rule only steers scheduling, never results)
-        std::function<bool(size_t, size_t, int)> doomed = [&](size_t u, size_t p, int depth) -> bool {
-            if (doom_perm[u][p]) return true;
-            if (doom_stamp[u][p] == scan_no) return doom_val[u][p] != 0;
-            doom_stamp[u][p] = scan_no;
-            doom_val[u][p] = 0;
-            const sfe_aln &a = ext[u][p];
-            const auto &stt = state[u];
-            bool d = false;
-            if (paths[u].in_committed(a.anchor_t, a.anchor_q)) {
-                doom_perm[u][p] = 1;
-                d = true;
-            } else if (depth < 64) {
-                d = paths[u].set.contains(a.anchor_t, a.anchor_q, [&](size_t o) { return o < p && stt[o] == 2; },
-                                          [&](size_t o) { return !doomed(u, o, depth + 1); });
-            }
-            doom_val[u][p] = d ? 1 : 0;
-            return d;
-        };
         auto anchor_of = [&](const sfe_hsp &h, uint32_t &ta, uint32_t &qa) {
             uint32_t off = (h.len - 1) / 2;
             ta = h.t0 + off;
@@ -1639,7 +1663,44 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             const double th = now_ms();
             items.clear();
             item_ref.clear();
-            scan_no++;
+            if (defer) {
+                // doomed flags of the waiting extensions in walking order: the anchor of waiting
+                // extension p lies in a committed alignment, or on the path of an earlier waiting
+                // extension that is not doomed itself (the rule only steers scheduling)
+                // first, in parallel over pieces of the units: `perm`, and the earlier waiting
+                // extensions whose paths hold each anchor; then each unit in order
+                std::vector<std::pair<size_t, size_t>> jobs;
+                for (size_t u = 0; u < NU; u++)
+                    for (size_t a = 0; a < state[u].size(); a += 8192) jobs.push_back({u, a});
+                std::vector<std::vector<std::pair<uint32_t, uint32_t>>> cand(jobs.size());   // (p, o)
+                for_each_unit(jobs.size(), [&](size_t j, size_t) {
+                    const size_t u = jobs[j].first;
+                    const auto &stt = state[u];
+                    const size_t end = std::min(stt.size(), jobs[j].second + 8192);
+                    for (size_t p = jobs[j].second; p < end; p++) {
+                        if (stt[p] != 2) continue;
+                        const sfe_aln &a = ext[u][p];
+                        if (!doom_perm[u][p] && paths[u].in_committed(a.anchor_t, a.anchor_q)) doom_perm[u][p] = 1;
+                        if (doom_perm[u][p]) continue;
+                        paths[u].set.search(a.anchor_t, a.anchor_q, [&](size_t o) { return o < p && stt[o] == 2; },
+                                            [&](size_t o) {
+                                                cand[j].push_back({(uint32_t)p, (uint32_t)o});
+                                                return false;
+                                            });
+                    }
+                });
+                for_each_unit(NU, [&](size_t u, size_t) {
+                    const auto &stt = state[u];
+                    auto &dv = doom_val[u];
+                    for (size_t p = 0; p < stt.size(); p++)
+                        if (stt[p] == 2) dv[p] = doom_perm[u][p];
+                    for (size_t j = 0; j < jobs.size(); j++) {
+                        if (jobs[j].first != u) continue;
+                        for (const auto &po : cand[j])
+                            if (!dv[po.first] && dv[po.second] == 0) dv[po.first] = 2;    // 2: doomed by a path
+                    }
+                });
+            }
             {
                 // anchors already on an M column of a committed alignment stay skipped for good:
                 // found for every open HSP first, in parallel over pieces of the open lists
@@ -1649,13 +1710,25 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 for_each_unit(jobs.size(), [&](size_t j, size_t) {
                     const size_t u = jobs[j].first;
                     const size_t end = std::min(open[u].size(), jobs[j].second + 8192);
+                    const auto &stt = state[u];
+                    const auto &dv = doom_val[u];
                     for (size_t q = jobs[j].second; q < end; q++) {
                         const size_t p = open[u][q];
-                        if (state[u][p] != 0) continue;
+                        if (stt[p] != 0) continue;
                         uint32_t ta, qa;
                         anchor_of(hs[per_unit[u][p]], ta, qa);
-                        if (paths[u].in_committed(ta, qa)) state[u][p] = 1;
+                        if (paths[u].in_committed(ta, qa)) {
+                            wait[u][p] = 2;
+                        } else if (defer) {
+                            // on the path of an earlier extension that may still commit
+                            wait[u][p] = paths[u].set.contains(ta, qa, [&](size_t o) { return o < p && stt[o] == 2; },
+                                                               [&](size_t o) { return dv[o] == 0; });
+                        }
                     }
+                });
+                for_each_unit(NU, [&](size_t u, size_t) {
+                    for (size_t p : open[u])
+                        if (wait[u][p] == 2) state[u][p] = 1;
                 });
             }
             for_each_unit(NU, [&](size_t u, size_t tix) {        // Alg. 3 batch gathering, per unit
@@ -1682,8 +1755,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     anchor_of(hs[lst[p]], ta, qa);
                     if (defer) {
                         // on the path of an earlier extension that may still commit: wait for it
-                        if (paths[u].set.contains(ta, qa, [&](size_t o) { return o < p && stt[o] == 2; },
-                                                  [&](size_t o) { return !doomed(u, o, 0); })) {
+                        if (wait[u][p] == 1) {
                             if (progress) why[u][p] += 1;
                             still.push_back(p);
                             continue;
@@ -1784,7 +1856,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     ext[u][p] = a;
                     ext_batch[u][p] = bno;
                     if (a.flags & SFE_ALN_PASSED) {
-                        paths[u].set.add(a, bops + a.ops_offset, p);
+                        paths[u].add(a, bops + a.ops_offset, p);
                         if (defer) boxes[u].add(a);
                     }
                     state[u][p] = 2;
@@ -1808,7 +1880,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                             k.ops_offset = cops_u[u].size();
                             const uint32_t *src = batch_ops[ext_batch[u][p]].data() + a.ops_offset;
                             cops_u[u].insert(cops_u[u].end(), src, src + a.ops_len);
-                            paths[u].committed[p] = 1;
+                            paths[u].commit(a, p);
                             committed_u[u].push_back(k);
                         }
                         stt[p] = 3;
@@ -1824,9 +1896,14 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             commit_ms += now_ms() - th3;
             host_ms += now_ms() - th2;
         }
-        if (progress)
+        if (progress) {
             fprintf(stderr, "[sfe] host scan/commit time %.1f ms (scan %.1f, bookkeeping %.1f, commit %.1f)\n", host_ms,
                     host_ms - book_ms - commit_ms, book_ms, commit_ms);
+            for (size_t u = 0; u < NU; u++)
+                fprintf(stderr, "[sfe]   unit %zu: %zu HSPs, %zu extension paths (%zu M runs), %zu committed\n", u,
+                        per_unit[u].size(), paths[u].set.paths.size(), paths[u].runs.rt.size(),
+                        paths[u].done.paths.size());
+        }
         for (size_t u = 0; u < NU; u++) {
             if (cursor[u] != per_unit[u].size()) fail(SFE_EINTERNAL, "commit did not finish");
             const uint64_t base_off = cops.size();
