@@ -1001,13 +1001,12 @@ struct BoxGrid {
     }
 };
 
-// M runs of a set of alignments of one unit, for "does (t, q) lie on an M
-// column of one of them" tests.  Each alignment keeps its runs in path order
-// (so sorted by t and disjoint in t) and is entered in every 16 kbp target
-// bin its box touches; a test reads the alignments of one bin, checks the box
-// and binary-searches the run that could hold t.
-// M runs of computed extensions: run start (target), length, and diagonal
-// minus the alignment's start diagonal.
+// M runs of computed extensions, for "does (t, q) lie on an M column of one of
+// them" tests: run start (target), length, and diagonal minus the alignment's
+// start diagonal.  Each alignment keeps its runs in path order (so sorted by
+// t and disjoint in t) and is entered in every 16 kbp target bin its box
+// touches; a test reads the alignments of one bin, checks the box and
+// binary-searches the run that could hold t.
 struct RunStore {
     std::vector<uint32_t> rt, rl;
     std::vector<int32_t> rd;
@@ -1026,17 +1025,23 @@ struct PathSet {
         paths.clear();
         bins.assign((size_t)(nt >> SH) + 2, {});
     }
-    // appends a's M runs to the store; returns the new path's id, or -1 when it has none
-    static int64_t append_runs(RunStore &st, const sfe_aln &a, const uint32_t *ops, size_t &first, uint32_t &count) {
-        first = st.rt.size();
+    static uint32_t count_runs(const sfe_aln &a, const uint32_t *ops) {
+        uint32_t n = 0;
+        for (uint32_t x = 0; x < a.ops_len; x++) n += (ops[x] & 3u) == 0;
+        return n;
+    }
+    // writes a's M runs at entry `first` of the store (sized for them)
+    static void write_runs(RunStore &st, size_t first, const sfe_aln &a, const uint32_t *ops) {
         uint32_t t = a.t_start, q = a.q_start;
         const int64_t d0 = (int64_t)a.t_start - (int64_t)a.q_start;
+        size_t r = first;
         for (uint32_t x = 0; x < a.ops_len; x++) {
             const uint32_t len = ops[x] >> 2, op = ops[x] & 3u;
             if (op == 0) {
-                st.rt.push_back(t);
-                st.rl.push_back(len);
-                st.rd.push_back((int32_t)((int64_t)t - (int64_t)q - d0));
+                st.rt[r] = t;
+                st.rl[r] = len;
+                st.rd[r] = (int32_t)((int64_t)t - (int64_t)q - d0);
+                r++;
                 t += len;
                 q += len;
             } else if (op == 1) {
@@ -1045,8 +1050,6 @@ struct PathSet {
                 t += len;
             }
         }
-        count = (uint32_t)(st.rt.size() - first);
-        return count;
     }
     // a path over runs [first, first + count) of the store; returns its id, or -1 if empty
     int64_t link(const sfe_aln &a, size_t first, uint32_t count, size_t owner) {
@@ -1103,9 +1106,11 @@ struct UnitPaths {
         run_count.assign(n, 0);
         committed.assign(n, 0);
     }
-    void add(const sfe_aln &a, const uint32_t *ops, size_t p) {
-        PathSet::append_runs(runs, a, ops, run_first[p], run_count[p]);
-        set.link(a, run_first[p], run_count[p], p);
+    // extension p, whose runs were written at [first, first + count)
+    void add(const sfe_aln &a, size_t first, uint32_t count, size_t p) {
+        run_first[p] = first;
+        run_count[p] = count;
+        set.link(a, first, count, p);
     }
     void commit(const sfe_aln &a, size_t p) {
         committed[p] = 1;
@@ -1635,7 +1640,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         if (o.policy == SFE_POLICY_DEFER)
             for (size_t u = 0; u < NU; u++) boxes[u].reset(ix->nt);
         std::vector<sfe_aln> committed;
-        std::vector<uint32_t> cops;
+        std::vector<uint32_t> cbatch;           // per committed alignment: the batch holding its ops
         std::vector<ExtItem> items;
         std::vector<std::pair<int32_t, size_t>> item_ref;
         BatchResult br;
@@ -1656,7 +1661,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         std::vector<std::vector<ExtItem>> items_u(NU);
         std::vector<std::vector<size_t>> ref_u(NU);
         std::vector<std::vector<sfe_aln>> committed_u(NU);
-        std::vector<std::vector<uint32_t>> cops_u(NU);
+        std::vector<std::vector<uint32_t>> cbatch_u(NU);
         std::vector<int64_t> shadow_u(NU, 0);
         std::vector<size_t> item_lo(NU + 1, 0);
         for (;;) {
@@ -1849,19 +1854,50 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             br.ops = std::vector<uint32_t>();
             const uint32_t *bops = batch_ops.back().data();
             for (size_t x = 0; x < items.size(); x++) st.cells += (int64_t)br.alns[x].cells;
-            for_each_unit(NU, [&](size_t u, size_t) {
-                for (size_t x = item_lo[u]; x < item_lo[u + 1]; x++) {
-                    const sfe_aln &a = br.alns[x];
-                    const size_t p = item_ref[x].second;
-                    ext[u][p] = a;
-                    ext_batch[u][p] = bno;
-                    if (a.flags & SFE_ALN_PASSED) {
-                        paths[u].add(a, bops + a.ops_offset, p);
-                        if (defer) boxes[u].add(a);
+            {
+                // M runs of the passing extensions: counted and written in parallel over pieces
+                // of the batch, each unit's at the end of its store
+                const size_t nb = items.size();
+                const size_t piece = 4096;
+                std::vector<uint32_t> nrun(nb, 0);
+                std::vector<size_t> roff(nb, 0);
+                for_each_unit((nb + piece - 1) / piece, [&](size_t j, size_t) {
+                    for (size_t x = j * piece; x < std::min(nb, (j + 1) * piece); x++)
+                        if (br.alns[x].flags & SFE_ALN_PASSED)
+                            nrun[x] = PathSet::count_runs(br.alns[x], bops + br.alns[x].ops_offset);
+                });
+                for (size_t u = 0; u < NU; u++) {
+                    size_t at = paths[u].runs.rt.size();
+                    for (size_t x = item_lo[u]; x < item_lo[u + 1]; x++) {
+                        roff[x] = at;
+                        at += nrun[x];
                     }
-                    state[u][p] = 2;
+                    paths[u].runs.rt.resize(at);
+                    paths[u].runs.rl.resize(at);
+                    paths[u].runs.rd.resize(at);
                 }
-            });
+                std::vector<int32_t> unit_x(nb);
+                for (size_t u = 0; u < NU; u++)
+                    for (size_t x = item_lo[u]; x < item_lo[u + 1]; x++) unit_x[x] = (int32_t)u;
+                for_each_unit((nb + piece - 1) / piece, [&](size_t j, size_t) {
+                    for (size_t x = j * piece; x < std::min(nb, (j + 1) * piece); x++)
+                        if (nrun[x])
+                            PathSet::write_runs(paths[unit_x[x]].runs, roff[x], br.alns[x], bops + br.alns[x].ops_offset);
+                });
+                for_each_unit(NU, [&](size_t u, size_t) {
+                    for (size_t x = item_lo[u]; x < item_lo[u + 1]; x++) {
+                        const sfe_aln &a = br.alns[x];
+                        const size_t p = item_ref[x].second;
+                        ext[u][p] = a;
+                        ext_batch[u][p] = bno;
+                        if (a.flags & SFE_ALN_PASSED) {
+                            paths[u].add(a, roff[x], nrun[x], p);
+                            if (defer) boxes[u].add(a);
+                        }
+                        state[u][p] = 2;
+                    }
+                });
+            }
             const double th3 = now_ms();
             book_ms += th3 - th2;
             for_each_unit(NU, [&](size_t u, size_t) {             // in-order commit (Alg. 1 decisions)
@@ -1876,12 +1912,10 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                         if (paths[u].in_committed(a.anchor_t, a.anchor_q)) {
                             shadow_u[u]++;
                         } else if (a.flags & SFE_ALN_PASSED) {
-                            sfe_aln k = a;
-                            k.ops_offset = cops_u[u].size();
-                            const uint32_t *src = batch_ops[ext_batch[u][p]].data() + a.ops_offset;
-                            cops_u[u].insert(cops_u[u].end(), src, src + a.ops_len);
+                            // ops stay in their batch's buffer until the output is written
                             paths[u].commit(a, p);
-                            committed_u[u].push_back(k);
+                            committed_u[u].push_back(a);
+                            cbatch_u[u].push_back(ext_batch[u][p]);
                         }
                         stt[p] = 3;
                         cur++;
@@ -1906,12 +1940,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         }
         for (size_t u = 0; u < NU; u++) {
             if (cursor[u] != per_unit[u].size()) fail(SFE_EINTERNAL, "commit did not finish");
-            const uint64_t base_off = cops.size();
-            cops.insert(cops.end(), cops_u[u].begin(), cops_u[u].end());
-            for (sfe_aln a : committed_u[u]) {
-                a.ops_offset += base_off;
-                committed.push_back(a);
-            }
+            committed.insert(committed.end(), committed_u[u].begin(), committed_u[u].end());
+            cbatch.insert(cbatch.end(), cbatch_u[u].begin(), cbatch_u[u].end());
             st.shadow += shadow_u[u];
         }
         st.committed = (int64_t)committed.size();
@@ -1925,8 +1955,10 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             auto ky = std::make_tuple(y.query_id, y.strand, y.t_start, y.q_start, y.t_end, y.q_end, y.anchor_t, y.anchor_q);
             return kx < ky;
         });
+        uint64_t total_ops = 0;
+        for (const sfe_aln &a : committed) total_ops += a.ops_len;
         *n_alns = (int64_t)committed.size();
-        *n_ops = (int64_t)cops.size();
+        *n_ops = (int64_t)total_ops;
         if (stats) {
             st.ms_seed_xdrop = t2 - t1;
             st.ms_hsp_set = t3 - t2;
@@ -1945,15 +1977,22 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         if (*n_alns > cap || *n_ops > ops_cap) fail(SFE_ECAPACITY, "alignment or ops buffer too small");
         if ((*n_alns && !out) || (*n_ops && !ops)) fail(SFE_EINVAL, "null output");
         std::vector<sfe_aln> oa(committed.size());
-        std::vector<uint32_t> oo;
-        oo.reserve(cops.size());
+        std::vector<uint32_t> oo(total_ops);
+        uint64_t at = 0;
         for (size_t x = 0; x < order.size(); x++) {
-            sfe_aln a = committed[order[x]];
-            uint64_t src = a.ops_offset;
-            a.ops_offset = oo.size();
-            oo.insert(oo.end(), cops.begin() + src, cops.begin() + src + a.ops_len);
-            oa[x] = a;
+            oa[x] = committed[order[x]];
+            oa[x].ops_offset = at;
+            at += oa[x].ops_len;
         }
+        // edit runs straight from the batch buffers, in parallel over pieces of the output
+        const size_t piece = 4096;
+        for_each_unit((order.size() + piece - 1) / piece, [&](size_t j, size_t) {
+            for (size_t x = j * piece; x < std::min(order.size(), (j + 1) * piece); x++) {
+                const sfe_aln &a = committed[order[x]];
+                const uint32_t *src = batch_ops[cbatch[order[x]]].data() + a.ops_offset;
+                std::copy(src, src + a.ops_len, oo.begin() + (ptrdiff_t)oa[x].ops_offset);
+            }
+        });
         copy_out(c, out, oa.data(), oa.size() * sizeof(sfe_aln));
         copy_out(c, ops, oo.data(), oo.size() * 4);
         sync(c);
