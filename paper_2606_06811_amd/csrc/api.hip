@@ -900,15 +900,16 @@ void run_batch(sfe_ctx *c, const sfe_index *idx, const std::vector<ExtItem> &ite
     copy_in(c, ooff_d, ops_off.data(), (size_t)np * 8);
     launch_ops_assemble(nullptr, np, roff_d, ra.base, nruns_d, ooff_d, ops_d, nops_d, c->stream);
     HIPCHK(hipGetLastError());
-    std::vector<uint32_t> nops(np), ops_all(ooff);
+    // the edit runs stay at their reserved offsets (each item's slot may end in unused words)
+    std::vector<uint32_t> nops(np);
+    out.ops.resize(ooff);
     copy_out(c, nops.data(), nops_d, (size_t)np * 4);
-    copy_out(c, ops_all.data(), ops_d, (size_t)ooff * 4);
+    copy_out(c, out.ops.data(), ops_d, (size_t)ooff * 4);
     sync(c);
     for (int64_t p = 0; p < np; p++) {
         sfe_aln &a = out.alns[pass[p]];
-        a.ops_offset = out.ops.size();
+        a.ops_offset = ops_off[p];
         a.ops_len = nops[p];
-        out.ops.insert(out.ops.end(), ops_all.begin() + ops_off[p], ops_all.begin() + ops_off[p] + nops[p]);
     }
 }
 
@@ -1457,12 +1458,20 @@ sfe_status sfe_gapped_ydrop(sfe_ctx *c, const sfe_index *ix, const sfe_seq *quer
         }
         BatchResult br;
         run_batch(c, ix, items, sc, 6, SFE_SCHED_PLAIN, br);
-        int64_t need = (int64_t)br.ops.size();
+        // edit runs packed in item order
+        std::vector<uint32_t> packed;
+        for (sfe_aln &a : br.alns) {
+            if (!(a.flags & SFE_ALN_PASSED)) continue;
+            const uint64_t src = a.ops_offset;
+            a.ops_offset = packed.size();
+            packed.insert(packed.end(), br.ops.begin() + (ptrdiff_t)src, br.ops.begin() + (ptrdiff_t)(src + a.ops_len));
+        }
+        int64_t need = (int64_t)packed.size();
         *n_ops = need;
         if (need > ops_cap) fail(SFE_ECAPACITY, "ops buffer too small");
         if (need && !ops) fail(SFE_EINVAL, "null ops");
         copy_out(c, out, br.alns.data(), (size_t)n * sizeof(sfe_aln));
-        copy_out(c, ops, br.ops.data(), (size_t)need * 4);
+        copy_out(c, ops, packed.data(), (size_t)need * 4);
         sync(c);
     });
 }
