@@ -7,6 +7,7 @@
 #include <chrono>
 #include <functional>
 #include <memory>
+#include <sys/mman.h>
 #include <mutex>
 #include <thread>
 #include <atomic>
@@ -346,9 +347,23 @@ __global__ void k_hsp_filter(const sfe_hsp *__restrict__ in, int64_t n, int32_t 
 // ---------------------------------------------------------------------------
 // One batch of gapped extensions (no commit): items -> alignments + ops.
 // ---------------------------------------------------------------------------
+// Host vector whose new elements are left uninitialised (buffers that a copy
+// fills right away).
+template <class T>
+struct NoInit : std::allocator<T> {
+    template <class U> struct rebind { using other = NoInit<U>; };
+    NoInit() = default;
+    template <class U> NoInit(const NoInit<U> &) {}
+    template <class U, class... A> void construct(U *p, A &&...a) {
+        if constexpr (sizeof...(A) == 0) ::new ((void *)p) U;
+        else ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+using OpsVec = std::vector<uint32_t, NoInit<uint32_t>>;
+
 struct BatchResult {
     std::vector<sfe_aln> alns;        // per item; ops_offset indexes `ops`, ops_len set for passing items
-    std::vector<uint32_t> ops;
+    OpsVec ops;
     std::vector<HalfResult> halves;   // per half (2x forward, 2x+1 backward of item x)
     int64_t reruns = 0;
     int64_t predicted = 0, mispredicted = 0;
@@ -1009,8 +1024,35 @@ struct BoxGrid {
 // touches; a test reads the alignments of one bin, checks the box and
 // binary-searches the run that could hold t.
 struct RunStore {
-    std::vector<uint32_t> rt, rl;
-    std::vector<int32_t> rd;
+    // one block of three arrays, 2 MiB aligned and advised as huge pages (the first
+    // touch of hundreds of MB of 4 KiB pages costs more than the writes)
+    struct Free { void operator()(uint8_t *p) const { free(p); } };
+    std::unique_ptr<uint8_t[], Free> mem;
+    uint32_t *rt = nullptr, *rl = nullptr;
+    int32_t *rd = nullptr;
+    size_t n = 0, cap = 0;
+    // room for `more` further runs (new entries are left uninitialised; capacity doubles)
+    void grow(size_t more) {
+        if (n + more <= cap) return;
+        const size_t nc = std::max(n + more, 2 * cap);
+        const size_t huge = (size_t)2 << 20;
+        const size_t bytes = (nc * 12 + huge - 1) / huge * huge;
+        uint8_t *m = (uint8_t *)aligned_alloc(huge, bytes);
+        if (!m) throw std::bad_alloc();
+        (void)madvise(m, bytes, MADV_HUGEPAGE);
+        uint32_t *t2 = (uint32_t *)m, *l2 = t2 + nc;
+        int32_t *d2 = (int32_t *)(l2 + nc);
+        if (n) {
+            memcpy(t2, rt, n * 4);
+            memcpy(l2, rl, n * 4);
+            memcpy(d2, rd, n * 4);
+        }
+        mem.reset(m);
+        rt = t2;
+        rl = l2;
+        rd = d2;
+        cap = nc;
+    }
 };
 
 // Paths (the M runs of one alignment each, in a RunStore) binned by target
@@ -1066,8 +1108,8 @@ struct PathSet {
     bool search(uint32_t t, uint32_t q, Pre pre, Found found) const {
         const size_t b = (size_t)(t >> SH);
         if (b >= bins.size()) return false;
-        const uint32_t *rt = rs->rt.data(), *rl = rs->rl.data();
-        const int32_t *rd = rs->rd.data();
+        const uint32_t *rt = rs->rt, *rl = rs->rl;
+        const int32_t *rd = rs->rd;
         for (uint32_t id : bins[b]) {
             const Path &P = paths[id];
             if (t < P.t0 || t >= P.t1 || q < P.q0 || q >= P.q1 || !pre(P.owner)) continue;
@@ -1100,7 +1142,10 @@ struct UnitPaths {
     std::vector<uint32_t> run_count;
     std::vector<uint8_t> committed;
     void reset(int64_t nt, size_t n) {
-        runs = RunStore{};
+        runs.mem.reset();
+        runs.rt = runs.rl = nullptr;
+        runs.rd = nullptr;
+        runs.n = runs.cap = 0;
         set.reset(nt, &runs);
         done.reset(nt, &runs);
         run_first.assign(n, 0);
@@ -1624,7 +1669,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         // extension of each position once computed: alignment, batch whose edit runs hold its ops
         std::vector<std::vector<sfe_aln>> ext(NU);
         std::vector<std::vector<uint32_t>> ext_batch(NU);
-        std::vector<std::vector<uint32_t>> batch_ops;          // edit runs of every batch so far
+        std::vector<OpsVec> batch_ops;                          // edit runs of every batch so far
         std::vector<std::vector<size_t>> open(NU);               // positions in state 0, ascending
         std::vector<UnitPaths> paths(NU);
         // deferral rule: a waiting extension is "doomed" when it will most likely be skipped at
@@ -1662,6 +1707,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             qa = h.q0 + off;
         };
         double host_ms = 0, book_ms = 0, commit_ms = 0;
+        double ph[6] = {0, 0, 0, 0, 0, 0};      // doomed, pre-pass, unit scans, run writes, unit updates, commit
         std::vector<std::vector<uint16_t>> why(progress ? NU : 0);   // deferrals by path (lo byte) and nearness (hi)
         for (size_t u = 0; u < why.size(); u++) why[u].assign(per_unit[u].size(), 0);
         // nearness rule: diagonals taken, one bit set per host thread (cleared after each unit)
@@ -1677,6 +1723,8 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             const double th = now_ms();
             items.clear();
             item_ref.clear();
+            double tp = th;
+            auto lap = [&](int k) { const double n = now_ms(); ph[k] += n - tp; tp = n; };
             if (defer) {
                 // doomed flags of the waiting extensions in walking order: the anchor of waiting
                 // extension p lies in a committed alignment, or on the path of an earlier waiting
@@ -1715,6 +1763,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     }
                 });
             }
+            lap(0);
             {
                 // anchors already on an M column of a committed alignment stay skipped for good:
                 // found for every open HSP first, in parallel over pieces of the open lists
@@ -1745,6 +1794,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                         if (wait[u][p] == 2) state[u][p] = 1;
                 });
             }
+            lap(1);
             for_each_unit(NU, [&](size_t u, size_t tix) {        // Alg. 3 batch gathering, per unit
                 auto &near_bits = near_bits_t[tix];
                 auto &near_touched = near_touched_t[tix];
@@ -1813,6 +1863,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 for (size_t p : ref_u[u]) item_ref.push_back({(int32_t)u, p});
             }
             item_lo[NU] = items.size();
+            lap(2);
             const double scan_round_ms = now_ms() - th;
             host_ms += scan_round_ms;
             if (items.empty()) break;
@@ -1856,11 +1907,12 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                 }
             }
             const double th2 = now_ms();
+            tp = th2;
             st.overflow_reruns += br.reruns;
             st.extensions += (int64_t)items.size();
             const uint32_t bno = (uint32_t)batch_ops.size();
             batch_ops.push_back(std::move(br.ops));
-            br.ops = std::vector<uint32_t>();
+            br.ops = OpsVec();
             const uint32_t *bops = batch_ops.back().data();
             for (size_t x = 0; x < items.size(); x++) st.cells += (int64_t)br.alns[x].cells;
             {
@@ -1876,14 +1928,13 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                             nrun[x] = PathSet::count_runs(br.alns[x], bops + br.alns[x].ops_offset);
                 });
                 for (size_t u = 0; u < NU; u++) {
-                    size_t at = paths[u].runs.rt.size();
+                    size_t at = paths[u].runs.n;
                     for (size_t x = item_lo[u]; x < item_lo[u + 1]; x++) {
                         roff[x] = at;
                         at += nrun[x];
                     }
-                    paths[u].runs.rt.resize(at);
-                    paths[u].runs.rl.resize(at);
-                    paths[u].runs.rd.resize(at);
+                    paths[u].runs.grow(at - paths[u].runs.n);
+                    paths[u].runs.n = at;
                 }
                 std::vector<int32_t> unit_x(nb);
                 for (size_t u = 0; u < NU; u++)
@@ -1893,6 +1944,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                         if (nrun[x])
                             PathSet::write_runs(paths[unit_x[x]].runs, roff[x], br.alns[x], bops + br.alns[x].ops_offset);
                 });
+                lap(3);
                 for_each_unit(NU, [&](size_t u, size_t) {
                     for (size_t x = item_lo[u]; x < item_lo[u + 1]; x++) {
                         const sfe_aln &a = br.alns[x];
@@ -1907,6 +1959,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     }
                 });
             }
+            lap(4);
             const double th3 = now_ms();
             book_ms += th3 - th2;
             for_each_unit(NU, [&](size_t u, size_t) {             // in-order commit (Alg. 1 decisions)
@@ -1936,15 +1989,18 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
                     break;                                          // needs an extension first
                 }
             });
+            lap(5);
             commit_ms += now_ms() - th3;
             host_ms += now_ms() - th2;
         }
         if (progress) {
             fprintf(stderr, "[sfe] host scan/commit time %.1f ms (scan %.1f, bookkeeping %.1f, commit %.1f)\n", host_ms,
                     host_ms - book_ms - commit_ms, book_ms, commit_ms);
+            fprintf(stderr, "[sfe]   phases: doomed %.1f, pre-pass %.1f, unit scans %.1f, run writes %.1f, unit updates "
+                    "%.1f, commit %.1f ms\n", ph[0], ph[1], ph[2], ph[3], ph[4], ph[5]);
             for (size_t u = 0; u < NU; u++)
                 fprintf(stderr, "[sfe]   unit %zu: %zu HSPs, %zu extension paths (%zu M runs), %zu committed\n", u,
-                        per_unit[u].size(), paths[u].set.paths.size(), paths[u].runs.rt.size(),
+                        per_unit[u].size(), paths[u].set.paths.size(), paths[u].runs.n,
                         paths[u].done.paths.size());
         }
         for (size_t u = 0; u < NU; u++) {
@@ -1986,7 +2042,7 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
         if (*n_alns > cap || *n_ops > ops_cap) fail(SFE_ECAPACITY, "alignment or ops buffer too small");
         if ((*n_alns && !out) || (*n_ops && !ops)) fail(SFE_EINVAL, "null output");
         std::vector<sfe_aln> oa(committed.size());
-        std::vector<uint32_t> oo(total_ops);
+        OpsVec oo(total_ops);
         uint64_t at = 0;
         for (size_t x = 0; x < order.size(); x++) {
             oa[x] = committed[order[x]];
