@@ -237,6 +237,27 @@ __device__ __forceinline__ int32_t span_score(const SeqSetView &T, int64_t pt, c
     return s0;
 }
 
+// The 64 bases from absolute position p0 as four 16-base code words (N read
+// as its stored code); reads the five words that hold them.
+__device__ __forceinline__ void window64(const SeqSetView &S, int64_t p0, uint32_t X[4]) {
+    const int64_t w = p0 >> 4;
+    const uint32_t sh = (uint32_t)(p0 & 15) * 2;
+    uint32_t W[5];
+#pragma unroll
+    for (int i = 0; i < 5; i++) W[i] = S.bases[w + i];
+#pragma unroll
+    for (int i = 0; i < 4; i++) X[i] = (uint32_t)((((uint64_t)W[i + 1] << 32) | W[i]) >> sh);
+}
+
+// True when no base of [p0, p0 + len) is N (len <= 64), from the summary bits
+// of the N plane.
+__device__ __forceinline__ bool window_has_no_n(const SeqSetView &S, int64_t p0, int len) {
+    const int64_t nw0 = p0 >> 5, nw1 = (p0 + len - 1) >> 5;
+    const uint64_t bits = ((uint64_t)S.nsum[(nw0 >> 5) + 1] << 32) | S.nsum[nw0 >> 5];
+    const uint32_t cnt = (uint32_t)(nw1 - nw0 + 1);
+    return ((bits >> (nw0 & 31)) & ((1ull << cnt) - 1)) == 0;
+}
+
 // Ungapped X-drop of one hit (t, q relative to their sequences, which start
 // at tb / qb in their sets and have lengths nt / nq): the seed span, then the
 // scan to the right of it and the scan to the left, each stopping at the first
@@ -252,11 +273,36 @@ template <bool I8>
 __device__ __forceinline__ XResult xdrop_hit(const SeqSetView &T, int64_t tb, int64_t nt, const SeqSetView &Q,
                                              int64_t qb, int64_t nq, int64_t t, int64_t q, int span,
                                              const XTables &x, int32_t X) {
-    const int32_t s0 = span_score<I8>(T, tb + t, Q, qb + q, span, x);
+    int64_t lim = min(nt - t - span, nq - q - span);
+    // Most hits end within the first block on each side: when both first blocks are whole
+    // and no base from t - 16 to the end of the first right block is N, one round of loads
+    // (64 bases of each sequence from t - 16, q - 16) serves the span and both first blocks.
+    const bool pre = span < 32 && lim >= 16 && t >= 16 && q >= 16 && window_has_no_n(T, tb + t - 16, span + 32) &&
+                     window_has_no_n(Q, qb + q - 16, span + 32);
+    Codes16 ra{0, 0}, rb{0, 0}, la{0, 0}, lb{0, 0};
+    int32_t s0 = 0;
+    if (pre) {
+        uint32_t A[4], B[4];
+        window64(T, tb + t - 16, A);
+        window64(Q, qb + q - 16, B);
+#pragma unroll
+        for (int i = 0; i < 32; i++)
+            if (i < span) s0 += pair_score<I8>(x, A[1 + i / 16], B[1 + i / 16], i & 15);
+        // first right block: bases t + span .. t + span + 15 (span < 32), from A[1..3]
+        const uint32_t sh = 2u * (uint32_t)(span & 15);
+        const int k = 1 + span / 16;
+        const uint32_t a0 = k == 1 ? A[1] : A[2], a1 = k == 1 ? A[2] : A[3];
+        const uint32_t b0 = k == 1 ? B[1] : B[2], b1 = k == 1 ? B[2] : B[3];
+        ra.c2 = (uint32_t)((((uint64_t)a1 << 32) | a0) >> sh);
+        rb.c2 = (uint32_t)((((uint64_t)b1 << 32) | b0) >> sh);
+        la.c2 = A[0];       // bases t - 16 .. t - 1, reversed below like any left block
+        lb.c2 = B[0];
+    } else {
+        s0 = span_score<I8>(T, tb + t, Q, qb + q, span, x);
+    }
     int32_t work = span;
     bool range = false;
     int side = 0;                                   // 0 right, 1 left
-    int64_t lim = min(nt - t - span, nq - q - span);
     int64_t r0 = 1, arg = 0, R = 0;
     int32_t s = 0, best = 0, bR = 0;
     for (;;) {
@@ -265,9 +311,16 @@ __device__ __forceinline__ XResult xdrop_hit(const SeqSetView &T, int64_t tb, in
         if (!done) {
             const int m = (int)min((int64_t)16, left);
             // right: bases t + span - 1 + r of both; left: t - r, read as the block ending at t - r0
-            const int64_t pt = side ? tb + t - r0 - m + 1 : tb + t + span - 1 + r0;
-            const int64_t pq = side ? qb + q - r0 - m + 1 : qb + q + span - 1 + r0;
-            Codes16 a = codes16(T, pt), b = codes16(Q, pq);
+            Codes16 a, b;
+            if (pre && r0 == 1 && m == 16) {
+                a = side ? la : ra;
+                b = side ? lb : rb;
+            } else {
+                const int64_t pt = side ? tb + t - r0 - m + 1 : tb + t + span - 1 + r0;
+                const int64_t pq = side ? qb + q - r0 - m + 1 : qb + q + span - 1 + r0;
+                a = codes16(T, pt);
+                b = codes16(Q, pq);
+            }
             if (side) {
                 a = reverse16(a, m);
                 b = reverse16(b, m);
