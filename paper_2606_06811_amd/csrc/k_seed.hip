@@ -405,9 +405,12 @@ __global__ void k_xdrop_raw(const sfe_hit *__restrict__ hits, int64_t n, const Q
 
 // Fused seed + X-drop: a block takes one chunk of 64 windows; its threads
 // walk the chunk's hits (flattened over windows and buckets) and append the
-// passing segments.  Hits never leave the chip.
+// passing segments.  Hits never leave the chip.  The kernel waits on gathers
+// most of the time, so it asks for 8 waves per SIMD (64 VGPRs, with 160 bytes
+// per lane spilled to scratch): ~10 % faster than the 7 waves its 71 VGPRs
+// would allow.
 template <bool I8>
-__global__ void __launch_bounds__(256) k_seed_xdrop(const UnitDesc *__restrict__ units, const Chunk *__restrict__ chunks,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_seed_xdrop(const UnitDesc *__restrict__ units, const Chunk *__restrict__ chunks,
                                                     SeqSetView T, int64_t tb, int64_t nt, SeqSetView Qp, SeqSetView Qm,
                                                     const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ tpos,
                                                     SeedDesc sd, ScoreDesc sc, sfe_hsp *__restrict__ out, uint64_t cap,
