@@ -48,8 +48,8 @@ YDROP_OPS_PER_CELL = 12      # E 3, F 3, G 2, H 1, prune 2, best 1
 # HBM bytes per extension launch of the mid workload's plain step (rocprofv3 FETCH_SIZE x 2.000 +
 # WRITE_SIZE x 1.000, the factors a 1 GiB device copy gives; the traffic summary under profiles/
 # holds the commands), valid only for the kernel source the counters were taken on
-YDROP_TRAFFIC_BYTES = 96.593e9
-YDROP_TRAFFIC_SOURCE_SHA256 = "no-measurement-for-the-current-sources"
+YDROP_TRAFFIC_BYTES = 70.487e9
+YDROP_TRAFFIC_SOURCE_SHA256 = "b9f55cc6e372a45c"
 YDROP_TRAFFIC_WORKLOAD = "mid"
 XDROP_OPS_PER_COLUMN = 6     # 2 base extracts, index, lookup, add, max / drop test
 
