@@ -12,6 +12,10 @@ extension with traceback and serial commit.  Workloads:
   chrom       1 Gbp target (1000 repeat families, index resident in HBM, built
               once and timed apart) vs a 200 Mbp query (20 large SVs, 35 %
               divergence) streamed as 10 Mbp chunks: step k aligns chunk k;
+  segdup      250 Mbp x 250 Mbp at 30 % divergence, the mid target recipe plus
+              segmental duplications over 5 % of the target (1-100 kbp copies,
+              1-10 % diverged), 10 + 10 SVs per Mbp: the learned-scheduling
+              workload;
   small       1 Mbp x 1 Mbp, 15 % divergence.
 
 Inputs are synthetic (seeded), resident in HBM before the timed region.
@@ -19,9 +23,9 @@ Inputs are synthetic (seeded), resident in HBM before the timed region.
 Two schedules of the gapped stage run on the same steps: plain (one wave per
 anchor-half, halves in batch order) and learned: the cost model, trained on
 the GPU from extension logs of the first query bases, orders every batch
-(persistent queue or adaptive launch, longest predicted first); the
-autotuner picks among the schedules that use the model.  Their outputs must
-be identical.
+(halves predicted to be long first, in a plain, binned, persistent or
+adaptive launch); the autotuner picks among the schedules that use the
+model.  Their outputs must be identical.
 
 Prints one JSON line.  `value` is unique HSPs per second of the whole step
 with the faster of the two schedules (`config.schedule` names it); the other
@@ -73,6 +77,11 @@ def make_workload(name: str):
         desc = ("1 Gbp target (1000 repeat families x 50 copies, 1% soft-masked low complexity, index resident in "
                 "HBM) vs 200 Mbp query (10 inversions + 10 translocations of 1-5 Mbp, 35% divergence, 2% indels) "
                 "streamed in 10 Mbp chunks, one chunk per step")
+    elif name == "segdup":
+        T, Q = synth.pair_segdup()
+        desc = ("250 Mbp target (200 repeat families x 50 copies, 1% soft-masked low complexity, segmental "
+                "duplications over 5% of it: 1-100 kbp copies at 1-10% divergence) vs 250 Mbp query (10 "
+                "inversions + 10 translocations of 20 kbp per Mbp, 30% divergence, 2% indels)")
     elif name == "small":
         T, Q = synth.pair_small()
         desc = "1 Mbp target vs 1 Mbp query (3 inversions, 3 translocations of 20 kbp, 15% divergence, 2% indels)"
@@ -317,7 +326,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=["mid", "mid-stress", "chrom", "small"])
+    ap.add_argument("--workload", default="mid", choices=["mid", "mid-stress", "chrom", "segdup", "small"])
     ap.add_argument("--round-k", type=int, default=0)
     ap.add_argument("--schedule", default="both", choices=["plain", "learned", "both"],
                     help="both: time the plain schedule and the learned one (the model orders every batch)")

@@ -265,6 +265,79 @@ def pair_mid(n=50_000_000, divergence=0.25, seed=2, families=200, copies=50,
     return to_ascii(t, ts), [to_ascii(qc, qs)]
 
 
+def segmental_duplications(rng, codes, soft, fraction, len_lo, len_hi, div_lo, div_hi):
+    """Copies of target segments of log-uniform length in [len_lo, len_hi], each
+    mutated at U(div_lo, div_hi), on a random strand, written over a random
+    position, until the copies cover `fraction` of the sequence."""
+    n = codes.shape[0]
+    target, covered = int(fraction * n), 0
+    while covered < target:
+        L = int(np.exp(rng.uniform(np.log(len_lo), np.log(len_hi))))
+        src = int(rng.integers(0, n - L))
+        dst = int(rng.integers(0, n - L))
+        c, m = mutate(rng, codes[src:src + L], soft[src:src + L], rng.uniform(div_lo, div_hi))
+        if rng.random() < 0.5:
+            c, m = revcomp_codes(c, m)
+        c, m = c[:n - dst], m[:n - dst]
+        codes[dst:dst + c.shape[0]] = c
+        soft[dst:dst + c.shape[0]] = m
+        covered += L
+    return codes, soft
+
+
+def many_svs(rng, codes, soft, n_inv, n_trans, seg_len):
+    """structural_variants for long sequences with many segments: the same
+    disjoint segments, inversions in place, the translocated segments cut out;
+    each is then pasted at an independent uniform position of what remains
+    (equal positions keep the cut order), assembled in one pass."""
+    codes, soft = codes.copy(), soft.copy()
+    segs = _disjoint_segments(rng, codes.shape[0], n_inv + n_trans, seg_len)
+    order = rng.permutation(len(segs))
+    inv = [segs[i] for i in order[:n_inv]]
+    trans = sorted(segs[i] for i in order[n_inv:])
+    for a in inv:
+        c, m = revcomp_codes(codes[a:a + seg_len], soft[a:a + seg_len])
+        codes[a:a + seg_len], soft[a:a + seg_len] = c, m
+    keep = np.ones(codes.shape[0], dtype=bool)
+    pieces = []
+    for a in trans:
+        pieces.append((codes[a:a + seg_len].copy(), soft[a:a + seg_len].copy()))
+        keep[a:a + seg_len] = False
+    codes, soft = codes[keep], soft[keep]
+    at = rng.integers(0, codes.shape[0] + 1, size=len(pieces))
+    rank = np.argsort(at, kind="stable")
+    out_c, out_s, prev = [], [], 0
+    for x in rank:
+        p = int(at[x])
+        out_c += [codes[prev:p], pieces[x][0]]
+        out_s += [soft[prev:p], pieces[x][1]]
+        prev = p
+    out_c.append(codes[prev:])
+    out_s.append(soft[prev:])
+    return np.concatenate(out_c), np.concatenate(out_s)
+
+
+def pair_segdup(n=250_000_000, divergence=0.30, seed=4, families=200, copies=50, low_complexity=0.01,
+                sd_fraction=0.05, sd_lo=1_000, sd_hi=100_000, sd_div_lo=0.01, sd_div_hi=0.10,
+                sv_per_mbp=10, seg_len=20_000):
+    """The learned-scheduling workload: an n-base target built as in pair_mid
+    (repeat families, 1 % soft-masked low-complexity runs) plus segmental
+    duplications covering sd_fraction of it (1-100 kbp copies at 1-10 %
+    divergence); the query gets sv_per_mbp inversions and translocations of
+    seg_len per Mbp, then mutate(divergence)."""
+    rng = rng_for(seed)
+    t = iid_codes(rng, n)
+    ts = np.zeros(n, dtype=bool)
+    t, ts = add_repeats(rng, t, ts, families, copies, 300, 6000, 0.10, 0.20)
+    t, ts = add_low_complexity(rng, t, ts, low_complexity)
+    t, ts = segmental_duplications(rng, t, ts, sd_fraction, sd_lo, sd_hi, sd_div_lo, sd_div_hi)
+    nsv = max(1, int(round(sv_per_mbp * n / 1e6)))
+    seg_len = min(seg_len, max(1, n // (4 * nsv)))
+    qc, qs = many_svs(rng, t, ts, nsv, nsv, seg_len)
+    qc, qs = mutate(rng, qc, qs, divergence)
+    return to_ascii(t, ts), [to_ascii(qc, qs)]
+
+
 def pair_chunks(n=100_000_000, n_chunks=4096, seed=3, families=200, copies=50,
                 low_complexity=0.01, median=50_000, len_lo=10_000, len_hi=2_000_000,
                 sigma=1.0, div_lo=0.10, div_hi=0.35, chunk_ids=None):
