@@ -12,6 +12,10 @@ extension with traceback and serial commit.  Workloads:
   chrom       1 Gbp target (1000 repeat families, index resident in HBM, built
               once and timed apart) vs a 200 Mbp query (20 large SVs, 35 %
               divergence) streamed as 10 Mbp chunks: step k aligns chunk k;
+  chunks      100 Mbp target (the mid recipe) vs --chunks query chunks of
+              lognormal length (median 50 kbp, 10 kbp - 2 Mbp), each a target
+              segment on a random strand at 10-35 % divergence, all in every
+              step: the batched workload;
   segdup      250 Mbp x 250 Mbp at 30 % divergence, the mid target recipe plus
               segmental duplications over 5 % of the target (1-100 kbp copies,
               1-10 % diverged), 10 + 10 SVs per Mbp: the learned-scheduling
@@ -62,7 +66,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_workload(name: str):
+def make_workload(name: str, chunks: int = 4096):
     from paper_2606_06811_amd import synth
     if name == "mid":
         T, Q = synth.pair_mid()
@@ -77,6 +81,11 @@ def make_workload(name: str):
         desc = ("1 Gbp target (1000 repeat families x 50 copies, 1% soft-masked low complexity, index resident in "
                 "HBM) vs 200 Mbp query (10 inversions + 10 translocations of 1-5 Mbp, 35% divergence, 2% indels) "
                 "streamed in 10 Mbp chunks, one chunk per step")
+    elif name == "chunks":
+        T, Q = synth.pair_chunks(n_chunks=chunks)
+        desc = (f"100 Mbp target (200 repeat families x 50 copies, 1% soft-masked low complexity) vs {chunks} "
+                "query chunks of lognormal length (median 50 kbp, 10 kbp-2 Mbp), each a target segment on a "
+                "random strand at U(10%, 35%) divergence, 2% indels, all aligned in every step")
     elif name == "segdup":
         T, Q = synth.pair_segdup()
         desc = ("250 Mbp target (200 repeat families x 50 copies, 1% soft-masked low complexity, segmental "
@@ -326,7 +335,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=["mid", "mid-stress", "chrom", "segdup", "small"])
+    ap.add_argument("--workload", default="mid", choices=["mid", "mid-stress", "chrom", "chunks", "segdup", "small"])
+    ap.add_argument("--chunks", type=int, default=4096, help="query chunks of the chunks workload")
     ap.add_argument("--round-k", type=int, default=0)
     ap.add_argument("--schedule", default="both", choices=["plain", "learned", "both"],
                     help="both: time the plain schedule and the learned one (the model orders every batch)")
@@ -364,7 +374,7 @@ def main():
     from paper_2606_06811_amd import sfe, synth
 
     t0 = time.time()
-    T, Q, desc = make_workload(args.workload)
+    T, Q, desc = make_workload(args.workload, args.chunks)
     log(f"workload generated in {time.time() - t0:.1f} s: target {T.shape[0]} bp, {len(Q)} queries, "
         f"{sum(q.shape[0] for q in Q)} bp")
     sc = dict(synth.SCORING)
@@ -388,13 +398,22 @@ def main():
     model, train_info, tune_info = None, None, None
     tuned = dict(max_cells_per_lane=args.cpl, schedule=sfe.SFE_SCHED_BINNED, wave_group_cap=0,
                  persist_waves_per_cu=0)
+    # training and tuning sample: the first query (its first train_bp / tune_bp bases), or as many
+    # leading chunks as hold train_bp bases
+    sample_q = Qd[:1]
+    if args.workload == "chunks":
+        k, tot = 0, 0
+        while k < len(Qd) and tot < args.train_bp:
+            tot += Qd[k].shape[0]
+            k += 1
+        sample_q = Qd[:max(k, 1)]
     if args.schedule in ("learned", "both"):
-        model, train_info = train_cost_model(ctx, sfe, synth, log, Td, Qd[:1], args.train_bp, resident)
+        model, train_info = train_cost_model(ctx, sfe, synth, log, Td, sample_q, args.train_bp, resident)
         if args.tune_bp > 0:
             # autotuner over the schedules that use the model, on the first tune_bp bases of the first query
             t0 = time.perf_counter()
             idx = resident or sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
-            tuned, entries = sfe.sfe_autotune(ctx, idx, Qd[:1], sc, sample_bases=args.tune_bp, model=model,
+            tuned, entries = sfe.sfe_autotune(ctx, idx, sample_q, sc, sample_bases=args.tune_bp, model=model,
                                               round_k=args.round_k, policy=args.policy)
             if idx is not resident:
                 idx.close()
@@ -409,8 +428,10 @@ def main():
     def step(kind, k):
         q = [Qd[k % len(Qd)]] if chrom else Qd
         idx = resident or sfe.sfe_build_index(ctx, Td, synth.SEED_PATTERN, 1, 1)
-        common = dict(round_k=args.round_k, cap=1 << 21, ops_cap=1 << 26, near_band=args.near_band,
-                      policy=args.policy)
+        # output capacities large enough that the call never has to be repeated for a larger buffer
+        big = args.workload in ("chunks", "segdup", "chrom")
+        common = dict(round_k=args.round_k, cap=1 << (23 if big else 21), ops_cap=1 << (29 if big else 26),
+                      near_band=args.near_band, policy=args.policy)
         if kind == "plain":
             sfe.sfe_ctx_set_tuning(ctx, wave_group_cap=0, use_graphs=int(args.graphs))
             out = sfe.sfe_align(ctx, idx, q, sc, schedule=sfe.SFE_SCHED_PLAIN, max_cells_per_lane=args.cpl,

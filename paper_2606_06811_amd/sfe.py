@@ -332,7 +332,9 @@ def sfe_align(ctx: Context, idx: Index, queries, scoring: dict, round_k: int = 0
               strands: int = 3, max_cells_per_lane: int = 0, arena_bytes: int = 0, policy: int = SFE_POLICY_DEFER,
               cap: int = 1 << 12, ops_cap: int = 1 << 18, model=None, near_band: int = 0,
               filter: int = SFE_FILTER_XDROP):
-    """Whole pipeline; returns (alignments, ops, stats dict)."""
+    """Whole pipeline; returns (alignments, ops, stats dict).  When the results
+    do not fit cap / ops_cap the call is made again with the sizes the library
+    reported (the whole pipeline runs twice), so size them generously."""
     seqs, keep = _seq_arrays(queries)
     sc = scoring_struct(scoring)
     opts = _AlignOpts(int(round_k), int(schedule), int(strands), int(max_cells_per_lane), int(policy),
