@@ -1606,7 +1606,12 @@ sfe_status sfe_align(sfe_ctx *c, const sfe_index *ix, const sfe_seq *queries, in
             copy_in(c, raw, pass.data(), (size_t)nraw * sizeof(sfe_hsp));
             sync(c);
         } else if (nch > 0) {
-            uint64_t capraw = std::max<uint64_t>(c->hsp_raw.n / sizeof(sfe_hsp), 1u << 23);
+            // room for one passing segment per 8 query bases (both strands) from the start: a launch
+            // whose segments do not fit is run again with room for all of them
+            uint64_t qbases = 0;
+            for (const UnitDesc &ud : L.units) qbases += (uint64_t)ud.len;
+            uint64_t capraw = std::max<uint64_t>(std::max<uint64_t>(c->hsp_raw.n / sizeof(sfe_hsp), 1u << 23),
+                                                 qbases / 8);
             for (;;) {
                 sfe_hsp *raw = (sfe_hsp *)c->hsp_raw.ensure(capraw * sizeof(sfe_hsp));
                 unsigned long long *cnt = c->counters.as<unsigned long long>();
