@@ -372,6 +372,29 @@ def test_align_parity(ctx, align_case, K, cpl, policy, schedule):
     assert st["xdrop_columns"] == sum(int(u["raw"]["work"].sum()) for u in ref["units"])
 
 
+@pytest.fixture(scope="module")
+def mid_case():
+    """The benchmark's generator at 250 kbp: repeat families, soft-masked
+    low-complexity runs, inversions and translocations, 25 % divergence."""
+    T, Q = synth.pair_mid(n=250_000, families=20, copies=10, seed=21)
+    ref = oracle.pipeline(T, Q, dict(synth.SCORING))
+    return T, Q, ref
+
+
+@pytest.mark.parametrize("K,policy", [(0, 0), (64, 1)])
+def test_align_parity_mid_shape(ctx, mid_case, K, policy):
+    """The whole pipeline on a scaled-down benchmark pair (several deferral
+    rounds, long colinear blocks) equals the oracle's Alg. 1 bit for bit."""
+    log(f"align parity on a 250 kbp mid-style pair K={K} policy={policy}")
+    T, Q, ref = mid_case
+    idx = sfe.sfe_build_index(ctx, T, PATTERN, 1, 1)
+    alns, ops, st = sfe.sfe_align(ctx, idx, Q, dict(synth.SCORING), round_k=K, policy=policy)
+    assert alns.shape[0] >= 100
+    compare_alignments(alns, ops, ref)
+    assert st["xdrop_columns"] == sum(int(u["raw"]["work"].sum()) for u in ref["units"])
+    idx.close()
+
+
 def test_align_parity_wide_scores(ctx, align_case):
     """The whole pipeline on the 32-bit extension kernel."""
     log("align parity with 32-bit extension")
